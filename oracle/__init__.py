@@ -1,0 +1,27 @@
+"""CPU oracle for the Legendre-coefficient method (arXiv 1106.0463).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+the CPU-baseline leg of the benchmark may import this package.  It shares no
+code with the HIP library and imports nothing from it.
+
+* :mod:`oracle.definition` -- eq. (2.3) by brute-force Gauss-Legendre
+  quadrature with the three-term recurrence (long double, O(N K)).
+* :mod:`oracle.method` -- the paper's discretized method step by step
+  (Abel-type transform eqs. (2.5)/(2.14), trapezoid rule for eq. (2.4),
+  c_n = (2n+1) a_n), long double, with a plain O(M N) Fourier sum.
+* :mod:`oracle.closed_forms` -- closed-form coefficients and Abel transforms
+  used to pin the two above.
+
+Pins (the tests under ``tests/test_oracle_*.py``): textbook Gauss-Legendre
+nodes, monomial exactness, f = P_m, the generating function eq. (2.2),
+e^{ax} through modified spherical Bessel functions, |x|^{3/2} against the
+True column of Table 1, reconstruction by eq. (2.1), mpmath brute-force
+quadrature of eq. (2.3) and eq. (2.14), polynomial exactness of the
+discretized method and its aliasing law.
+"""
+from ._lib import build, load, threads  # noqa: F401
+from .definition import (gauss_legendre, legendre_coeffs,  # noqa: F401
+                         legendre_coeffs_from_samples,
+                         legendre_coeffs_piecewise, legendre_eval)
+from .method import (abel_fhat, abel_phi, coeffs_from_fhat,  # noqa: F401
+                     fhat_from_phi, fourier_coeffs, method_coeffs, y_grid)

@@ -1,0 +1,106 @@
+"""Closed-form Legendre coefficients and Abel transforms used to pin the
+oracle (all computed with mpmath at high precision, independently of the
+oracle's own quadrature and recurrences).
+
+References are to De Micheli & Viano, arXiv 1106.0463, Section 2.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import mpmath as mp
+import numpy as np
+
+mp.mp.dps = 40
+
+
+def genfn_coeffs(t: float, N: int) -> np.ndarray:
+    """Generating function eq. (2.2): (1-2xt+t^2)^{-1/2} = sum P_n t^n,
+    hence c_n = t^n."""
+    return np.array([mp.mpf(t) ** n for n in range(N)], dtype=object)
+
+
+def exp_coeffs(a: float, N: int) -> np.ndarray:
+    """e^{a x} = sum_n (2n+1) i_n(a) P_n(x), with the modified spherical
+    Bessel function i_n(z) = sqrt(pi/(2z)) I_{n+1/2}(z) and i_n(-z) =
+    (-1)^n i_n(z); a = 0 gives delta_{n0}."""
+    a = mp.mpf(a)
+    out = []
+    for n in range(N):
+        if a == 0:
+            out.append(mp.mpf(1) if n == 0 else mp.mpf(0))
+            continue
+        z = abs(a)
+        i_n = mp.sqrt(mp.pi / (2 * z)) * mp.besseli(n + mp.mpf(1) / 2, z)
+        sgn = 1 if (a > 0 or n % 2 == 0) else -1
+        out.append((2 * n + 1) * sgn * i_n)
+    return np.array(out, dtype=object)
+
+
+def cos_coeffs(omega: float, N: int) -> np.ndarray:
+    """cos(omega x) = sum_{n even} (2n+1) (-1)^{n/2} j_n(omega) P_n(x),
+    j_n(z) = sqrt(pi/(2z)) J_{n+1/2}(z)."""
+    w = mp.mpf(omega)
+    out = []
+    for n in range(N):
+        if n % 2:
+            out.append(mp.mpf(0))
+            continue
+        j_n = mp.sqrt(mp.pi / (2 * w)) * mp.besselj(n + mp.mpf(1) / 2, w)
+        out.append((2 * n + 1) * (-1) ** (n // 2) * j_n)
+    return np.array(out, dtype=object)
+
+
+def abs_pow_coeffs(N: int, alpha: Fraction = Fraction(3, 2)) -> list:
+    """Closed form printed before Table 1 (Section 2) for f = |x|^alpha,
+    read as: 0 for odd n; 1/(alpha+1) for n = 0; otherwise
+    (2n+1) prod_{k=0}^{n/2-1} (alpha - 2k) / prod_{k=0}^{n/2} (alpha + 1 + 2k).
+    Exact rationals."""
+    out = []
+    for n in range(N):
+        if n % 2:
+            out.append(Fraction(0))
+        elif n == 0:
+            out.append(1 / (alpha + 1))
+        else:
+            num = Fraction(2 * n + 1)
+            for k in range(n // 2):
+                num *= alpha - 2 * k
+            den = Fraction(1)
+            for k in range(n // 2 + 1):
+                den *= alpha + 1 + 2 * k
+            out.append(num / den)
+    return out
+
+
+def phi_legendre(m: int, y) -> float:
+    """phi(y) of eq. (2.14) for f = P_m: 2 sin((m+1/2) y) / (2m+1).
+    (It is pinned separately against mpmath quadrature of eq. (2.14).)"""
+    return 2 * mp.sin((m + mp.mpf(1) / 2) * mp.mpf(y)) / (2 * m + 1)
+
+
+def phi_quad(f_mp, y) -> mp.mpf:
+    """phi(y) of eq. (2.14), integral_{cos y}^1 f(x)/sqrt(2(x - cos y)) dx,
+    by mpmath's tanh-sinh quadrature (handles the end-point singularity)."""
+    y = mp.mpf(y)
+    cy = mp.cos(y)
+    return mp.quad(lambda x: f_mp(x) / mp.sqrt(2 * (x - cy)), [cy, 1])
+
+
+def coeff_quad(f_mp, n: int, breakpoints=()) -> mp.mpf:
+    """c_n of eq. (2.3) by mpmath's adaptive quadrature."""
+    pts = [-1] + list(breakpoints) + [1]
+    return (n + mp.mpf(1) / 2) * mp.quad(lambda x: f_mp(x) * mp.legendre(n, x), pts)
+
+
+def load_table1(path: str) -> tuple[list[int], list[str]]:
+    ns, vals = [], []
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            a, b = line.split()
+            ns.append(int(a))
+            vals.append(b)
+    return ns, vals
