@@ -1,0 +1,214 @@
+/*
+ * lc.h -- C ABI of the MI355X (gfx950) implementation of the Legendre-
+ * coefficient method of E. De Micheli and G. A. Viano, "A new and efficient
+ * method for the computation of Legendre coefficients", arXiv 1106.0463.
+ *
+ * Problem (Section 2, eqs. (2.1) and (2.3)): given f summable on [-1, 1],
+ * compute
+ *     c_n = (n + 1/2) * integral_{-1}^{1} f(x) P_n(x) dx,   n = 0 .. N-1.
+ *
+ * Method (Theorem 1, eqs. (2.4), (2.5), (2.12)-(2.14)): a_n = c_n / (2n+1)
+ * are the Fourier coefficients (n >= 0) of the Abel-type transform
+ *     fhat(y) = (1/(2 pi i)) eps(y) e^{i y/2} phi(|y|),
+ *     phi(y)  = integral_{cos y}^{1} f(x) / sqrt(2 (x - cos y)) dx.
+ * The library evaluates phi on the grid y_j = pi j / H (j = 1..H, H = M/2)
+ * after the change of variable x = cos y + 2 sin^2(y/2) t^2, which turns the
+ * end-point singularity into a smooth integrand, with the positive half of
+ * the 2Q-point Gauss-Legendre rule in t:
+ *     phi_j = 2 s_j * sum_{q<Q} w_q f(x_{jq}),
+ *     x_{jq} = 1 - 2 s_j^2 (1 - t_q^2) = cos y_j + 2 sin^2(y_j/2) t_q^2,
+ *     s_j = sin(y_j / 2),
+ * (exact for polynomial f of degree <= 2Q-1), then applies the twist and the
+ * one FFT of eq. (2.4) (as a DST-III of length H computed with a complex FFT
+ * of length H/2) and the rescale c_n = (2n+1) a_n.  For real f only
+ * y in (0, pi] needs Abel integrals: fhat(-y) follows from eq. (2.12).
+ *
+ * Conventions for every entry point:
+ *  - Return value is an lc_status; LC_OK (0) on success.  On error nothing
+ *    is written to out-parameters and lc_last_error() (thread-local) holds a
+ *    message.  No C++ exception crosses this interface.
+ *  - "device pointer": memory on the current HIP device (hipMalloc or a
+ *    torch CUDA/HIP tensor).  "host pointer": ordinary process memory.
+ *  - Execute calls are asynchronous on the given stream: they enqueue work
+ *    and return without synchronizing; faults inside kernels surface at the
+ *    caller's next synchronization.  They allocate nothing.
+ *  - A plan is bound to the device that was current when it was created and
+ *    owns all of its device buffers (nodes, weights, twiddles, workspace).
+ *    One plan must not be executed concurrently from two streams (the
+ *    workspace is per plan); distinct plans are independent.
+ */
+#ifndef LC_H
+#define LC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LC_OK = 0,
+    LC_ERR_INVALID = 1,      /* bad argument (sizes, null pointer, wrong plan kind) */
+    LC_ERR_NOMEM = 2,        /* device or host allocation failed                   */
+    LC_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed          */
+    LC_ERR_UNSUPPORTED = 4,  /* valid request outside what this build implements   */
+    LC_ERR_INTERNAL = 5
+} lc_status;
+
+/* Sample / accumulation precision of a request. */
+typedef enum {
+    LC_FP64 = 0,       /* f samples FP64; Abel sums, twist, FFT, rescale FP64   */
+    LC_FP32_QUAD = 1   /* f samples FP32 (half the bytes); everything after the
+                          load (Abel sums, FFT, rescale) in FP64                */
+} lc_precision;
+
+/* Arithmetic of the Abel-as-GEMM form (product-integration matrix times
+ * samples).  Split modes write each FP64 operand as a sum of 16-bit pieces
+ * and accumulate the piece products on MFMA in FP32. */
+typedef enum {
+    LC_GEMM_FP64 = 0,    /* FP64 product (reference arithmetic)                   */
+    LC_GEMM_BF16X3 = 1,  /* A=Ah+Al, F=Fh+Fl (bf16): Ah Fh + Ah Fl + Al Fh        */
+    LC_GEMM_BF16X6 = 2,  /* three bf16 pieces each: the six products of order <=2 */
+    LC_GEMM_FP16X3 = 3,  /* power-of-two-scaled fp16 pieces: three products       */
+    LC_GEMM_FP16X1 = 4   /* one scaled fp16 piece each: one product                */
+} lc_gemm_mode;
+
+typedef enum { LC_PLAN_SINGLE = 0, LC_PLAN_BATCH = 1, LC_PLAN_GEMM = 2 } lc_plan_kind;
+
+typedef struct lc_plan_s *lc_plan_t;
+
+typedef struct {
+    int32_t kind;        /* lc_plan_kind                                         */
+    int32_t precision;   /* lc_precision (single plans) / lc_gemm_mode (GEMM)    */
+    int64_t N;           /* coefficients returned (single / GEMM plans)          */
+    int64_t M;           /* y-grid size requested                                */
+    int64_t M_eff;       /* y-grid size used (see lc_grid_size)                  */
+    int64_t H;           /* M_eff / 2: rows of the node array                    */
+    int32_t Q;           /* Abel nodes per row (single); P sample nodes (GEMM)   */
+    int32_t B;           /* functions (batch plans), 0 otherwise                 */
+    int64_t samples;     /* f samples the caller provides per execute           */
+    int64_t sample_bytes;/* bytes of those samples                               */
+    int64_t workspace_bytes; /* device bytes owned by the plan                   */
+} lc_plan_desc;
+
+/* Size rule for the y-grid (host only, no device work).  The FFT of eq. (2.4)
+ * is computed as a complex FFT of length H/2; this build supports lengths
+ * 2^a 3^b.  M_eff is the smallest M' >= max(M, 4) with M' = 4 * 2^a 3^b.
+ * Using M_eff >= M only refines the trapezoid grid of eq. (2.4).
+ * Errors: LC_ERR_INVALID if M < 2 or M_eff is null or the size overflows. */
+lc_status lc_grid_size(int64_t M, int64_t *M_eff);
+
+/* Single-function plan (eq. (2.4) on the M-point grid, Q Abel nodes).
+ * N >= 1, M even >= 2, N <= M/2, 1 <= Q <= 65536, prec in lc_precision.
+ * Builds on the current device: the Gauss rule (host, long double), the
+ * nodes x_{jq} (device, FP64, half-angle form), FFT twiddles (host, long
+ * double with exact integer argument reduction, stored FP64) and a
+ * workspace.  *out is written only on success.
+ * Errors: LC_ERR_INVALID, LC_ERR_NOMEM, LC_ERR_HIP. */
+lc_status lc_plan(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t *out);
+
+/* Describes any plan.  Errors: LC_ERR_INVALID on null arguments. */
+lc_status lc_plan_info(lc_plan_t plan, lc_plan_desc *desc);
+
+/* Device pointer to the sample nodes, owned by the plan and valid until
+ * lc_plan_destroy.  Single plans: x[H][Q] row-major FP64, row r holds
+ * y_{r+1} = pi (r+1)/H; the caller writes f(x[r][q]) into f[r][q].
+ * Batch plans: the node arena, function b at element offset x_off[b] (see
+ * lc_plan_batch_offsets), laid out like a single plan.  GEMM plans: the P
+ * Chebyshev-Gauss nodes x_p = cos((2p+1) pi / (2P)).
+ * rows / Q may be null.  Errors: LC_ERR_INVALID. */
+lc_status lc_plan_nodes(lc_plan_t plan, const double **x_dev, int64_t *rows, int32_t *Q);
+
+/* Executes a single plan: f_dev is the device array of samples f[H][Q]
+ * (FP64, or FP32 for LC_FP32_QUAD), c_dev a device array of N doubles that
+ * receives c_0..c_{N-1}.  Asynchronous on stream (0 = null stream); no
+ * allocation, no host synchronization.  f_dev must be 16-byte aligned.
+ * Errors: LC_ERR_INVALID (null pointer, wrong plan kind, misaligned f_dev),
+ * LC_ERR_HIP (launch failure). */
+lc_status lc_execute(lc_plan_t plan, const void *f_dev, double *c_dev, hipStream_t stream);
+
+/* Batched plan for B independent functions of uneven sizes (N[b], M[b],
+ * Q[b], prec[b], host arrays of length B, each entry validated as in
+ * lc_plan).  Samples live in one device arena (byte offsets f_off, every
+ * function 256-byte aligned, FP64 or FP32 per prec[b]); coefficients in one
+ * FP64 arena (element offsets c_off).  Execution is a fixed sequence of
+ * kernels captured once into a HIP graph on the first lc_execute_batch and
+ * replayed afterwards.  Errors: LC_ERR_INVALID, LC_ERR_NOMEM, LC_ERR_HIP. */
+lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int32_t *Q,
+                        const lc_precision *prec, lc_plan_t *out);
+
+/* Host copies of the batch layout, each array of length B+1 (may be null):
+ * f_off  byte offset of function b's samples in the f arena (f_off[B] =
+ *        arena bytes);
+ * x_off  element offset (doubles) of its nodes in the node arena;
+ * c_off  element offset (doubles) of its coefficients in the c arena.
+ * Errors: LC_ERR_INVALID (not a batch plan). */
+lc_status lc_plan_batch_offsets(lc_plan_t plan, int64_t *f_off, int64_t *x_off, int64_t *c_off);
+
+/* Executes a batch plan (graph replay on stream).  f_arena: device arena of
+ * samples (layout of lc_plan_batch_offsets), c_arena: device FP64 arena.
+ * Pointers must be 256-byte aligned.  The first call on a given
+ * (f_arena, c_arena, stream) triple captures the graph; a call with other
+ * pointers re-captures it.  Errors: LC_ERR_INVALID, LC_ERR_HIP. */
+lc_status lc_execute_batch(lc_plan_t plan, const void *f_arena, double *c_arena, hipStream_t stream);
+
+/* Abel-as-GEMM plan: functions sampled on the fixed P-point Chebyshev-Gauss
+ * grid.  The Abel step becomes phi = A F with the product-integration matrix
+ * A[j][p] = integral_{cos y_j}^{1} l_p(x) / sqrt(2 (x - cos y_j)) dx
+ * (l_p the Lagrange cardinal polynomial of node p; exact for f of degree
+ * < P), built in FP64 on the device.  Then the twist/FFT/rescale of a
+ * single plan, batched over the functions.  2 <= P <= 16384, M even with
+ * M/2 >= N, N >= 1.  Errors: LC_ERR_INVALID, LC_ERR_NOMEM, LC_ERR_HIP. */
+lc_status lc_plan_gemm(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_plan_t *out);
+
+/* Executes a GEMM plan on B functions: F_dev device FP64 [P][B] (row p holds
+ * f_b(x_p) for every b), C_dev device FP64 [B][N].  B <= the plan's
+ * capacity (lc_plan_gemm_reserve, default 16384).  Asynchronous on stream.
+ * Errors: LC_ERR_INVALID, LC_ERR_HIP. */
+lc_status lc_execute_gemm(lc_plan_t plan, const double *F_dev, int32_t B, double *C_dev,
+                          hipStream_t stream);
+
+/* Sets the largest B a GEMM plan accepts (allocates its workspace).
+ * Errors: LC_ERR_INVALID, LC_ERR_NOMEM. */
+lc_status lc_plan_gemm_reserve(lc_plan_t plan, int32_t B_max);
+
+/* Device pointer to the GEMM plan's FP64 product-integration matrix A,
+ * [H+1][P] row-major (row 0, y = 0, is zero), valid until destroy.
+ * Errors: LC_ERR_INVALID. */
+lc_status lc_plan_gemm_matrix(lc_plan_t plan, const double **A_dev);
+
+/* Times the plan's kernel variants (quadrature lanes per row and rows per
+ * block, FFT radix schedule and threads) on the plan's own buffers and
+ * keeps the fastest; results persist in the file named by LC_AUTOTUNE_CACHE
+ * (if set), keyed by device architecture, H, Q and precision.  Synchronizes
+ * stream.  Errors: LC_ERR_INVALID, LC_ERR_HIP, LC_ERR_NOMEM. */
+lc_status lc_autotune(lc_plan_t plan, hipStream_t stream);
+
+/* Frees the plan and all of its device memory (synchronizes the device
+ * first).  A null plan is accepted.  Returns LC_OK. */
+lc_status lc_plan_destroy(lc_plan_t plan);
+
+/* Static string for a status code. */
+const char *lc_status_string(lc_status s);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *lc_last_error(void);
+
+/* Kernel timing of the plan's dominant kernel (the Abel quadrature
+ * reduction for single and batch plans, the MFMA product for GEMM plans).
+ * lc_plan_set_timing(plan, 1) starts recording a pair of HIP events around
+ * that kernel, on the execute stream, at every execute (up to 4096 executes;
+ * later ones are not recorded); enable = 0 stops and discards the record.
+ * lc_plan_kernel_ms synchronizes the recorded events and returns the mean
+ * kernel duration in milliseconds over the recorded executes and their
+ * number.  Errors: LC_ERR_INVALID (null arguments, timing disabled or
+ * nothing recorded), LC_ERR_HIP. */
+lc_status lc_plan_set_timing(lc_plan_t plan, int32_t enable);
+lc_status lc_plan_kernel_ms(lc_plan_t plan, double *avg_ms, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LC_H */

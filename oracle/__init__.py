@@ -24,4 +24,5 @@ from .definition import (gauss_legendre, legendre_coeffs,  # noqa: F401
                          legendre_coeffs_from_samples,
                          legendre_coeffs_piecewise, legendre_eval)
 from .method import (abel_fhat, abel_phi, coeffs_from_fhat,  # noqa: F401
-                     fhat_from_phi, fourier_coeffs, method_coeffs, y_grid)
+                     fhat_from_phi, fourier_coeffs, fourier_coeffs_at,
+                     method_coeffs, method_coeffs_at, y_grid)

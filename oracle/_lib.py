@@ -42,6 +42,8 @@ def load() -> ctypes.CDLL:
     lib.oracle_legendre_coeffs.restype = ctypes.c_int
     lib.oracle_fourier_coeffs.argtypes = [lg, vp, vp, lg, vp, vp]
     lib.oracle_fourier_coeffs.restype = ctypes.c_int
+    lib.oracle_fourier_coeffs_idx.argtypes = [lg, vp, vp, lg, vp, vp, vp]
+    lib.oracle_fourier_coeffs_idx.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib

@@ -66,7 +66,7 @@ int oracle_gauss_legendre(long K, ld *x, ld *w)
     for (long k = 0; k < half; ++k) {
         /* initial guess for the (k+1)-th largest zero */
         ld xi = cosl(PI_L * ((ld)k + 0.75L) / ((ld)K + 0.5L));
-        ld pk, pkm1, dp;
+        ld pk, pkm1, dp, prev = 1.0L;
         int it, ok = 0;
         for (it = 0; it < 100; ++it) {
             legendre_pair(K, xi, &pk, &pkm1);
@@ -74,6 +74,10 @@ int oracle_gauss_legendre(long K, ld *x, ld *w)
             ld dx = pk / dp;
             xi -= dx;
             if (fabsl(dx) <= 4.0L * LDBL_EPSILON * fabsl(xi) + 1e-4900L) { ok = 1; break; }
+            /* quadratic convergence has stopped: the step is at the rounding
+             * level of P_K (grows like K eps near the ends) */
+            if (it >= 3 && fabsl(dx) > 0.25L * prev && fabsl(dx) < 1e-15L) { ok = 1; break; }
+            prev = fabsl(dx);
         }
         /* weight at the converged node, with P_K' from the same recurrence
          * (the rounding errors of P_K and P_{K-1} are correlated and cancel
@@ -161,6 +165,41 @@ int oracle_fourier_coeffs(long M, const ld *fhat_re, const ld *fhat_im,
         ld sign = (n % 2 == 0) ? 1.0L : -1.0L;
         a_re[n] = sign * (2.0L * PI_L / (ld)M) * sr;
         a_im[n] = sign * (2.0L * PI_L / (ld)M) * si;
+    }
+    free(cs);
+    free(sn);
+    return 0;
+}
+
+/* The same sum for a list of indices n = idx[i] (sampled outputs). */
+int oracle_fourier_coeffs_idx(long M, const ld *fhat_re, const ld *fhat_im,
+                              long nidx, const long *idx, ld *a_re, ld *a_im)
+{
+    if (M < 1 || nidx < 0 || !fhat_re || !fhat_im || !idx || !a_re || !a_im) return -1;
+    ld *cs = (ld *)malloc((size_t)M * sizeof(ld));
+    ld *sn = (ld *)malloc((size_t)M * sizeof(ld));
+    if (!cs || !sn) { free(cs); free(sn); return -3; }
+    for (long m = 0; m < M; ++m) {
+        ld ang = 2.0L * PI_L * (ld)m / (ld)M;
+        cs[m] = cosl(ang);
+        sn[m] = sinl(ang);
+    }
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nidx; ++i) {
+        long n = idx[i];
+        ld sr = 0.0L, si = 0.0L;
+        long nm = n % M;
+        long id = 0;
+        for (long j = 0; j < M; ++j) {
+            ld er = cs[id], ei = sn[id];
+            sr += fhat_re[j] * er - fhat_im[j] * ei;
+            si += fhat_re[j] * ei + fhat_im[j] * er;
+            id += nm;
+            if (id >= M) id -= M;
+        }
+        ld sign = (n % 2 == 0) ? 1.0L : -1.0L;
+        a_re[i] = sign * (2.0L * PI_L / (ld)M) * sr;
+        a_im[i] = sign * (2.0L * PI_L / (ld)M) * si;
     }
     free(cs);
     free(sn);

@@ -37,17 +37,22 @@ LD = np.longdouble
 PI = LD("3.141592653589793238462643383279502884")
 
 
-def abel_phi(f, y: np.ndarray, Q: int) -> np.ndarray:
+def abel_phi(f, y: np.ndarray, Q: int, chunk: int = 2048) -> np.ndarray:
     """phi(y) of eq. (2.14) for y in [-pi, pi] (even in y), with the
-    (2Q)-point Gauss-Legendre rule after x = cos y + (1 - cos y) t^2."""
+    (2Q)-point Gauss-Legendre rule after x = cos y + (1 - cos y) t^2
+    (evaluated in blocks of ``chunk`` y values to bound memory)."""
     y = np.asarray(y, dtype=LD)
     T, W = gauss_legendre(2 * int(Q))
-    cy = np.cos(y)
-    L = 1 - cy                              # length of [cos y, 1]
-    x = cy[:, None] + L[:, None] * (T[None, :] ** 2)
-    fx = np.asarray(f(x), dtype=LD)
-    integral = LD(0.5) * (fx * W[None, :]).sum(axis=1)
-    return np.sqrt(2 * L) * integral
+    out = np.empty(y.shape, dtype=LD)
+    for a in range(0, y.size, chunk):
+        yy = y[a:a + chunk]
+        cy = np.cos(yy)
+        L = 1 - cy                              # length of [cos y, 1]
+        x = cy[:, None] + L[:, None] * (T[None, :] ** 2)
+        fx = np.asarray(f(x), dtype=LD)
+        integral = LD(0.5) * (fx * W[None, :]).sum(axis=1)
+        out[a:a + chunk] = np.sqrt(2 * L) * integral
+    return out
 
 
 def fhat_from_phi(phi_abs_y: np.ndarray, y: np.ndarray) -> np.ndarray:
@@ -81,6 +86,30 @@ def fourier_coeffs(fhat_vals: np.ndarray, N: int) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"oracle_fourier_coeffs failed (rc={rc})")
     return a_re + 1j * a_im
+
+
+def fourier_coeffs_at(fhat_vals: np.ndarray, idx) -> np.ndarray:
+    """:func:`fourier_coeffs` for the listed indices only."""
+    fh = np.asarray(fhat_vals)
+    re = np.ascontiguousarray(fh.real, dtype=LD)
+    im = np.ascontiguousarray(fh.imag, dtype=LD)
+    ii = np.ascontiguousarray(idx, dtype=np.int64)
+    a_re = np.empty(ii.size, dtype=LD)
+    a_im = np.empty(ii.size, dtype=LD)
+    rc = _lib.load().oracle_fourier_coeffs_idx(re.size, re.ctypes.data, im.ctypes.data, ii.size,
+                                               ii.ctypes.data, a_re.ctypes.data, a_im.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle_fourier_coeffs_idx failed (rc={rc})")
+    return a_re + 1j * a_im
+
+
+def method_coeffs_at(f, idx, M: int, Q: int) -> np.ndarray:
+    """:func:`method_coeffs` evaluated only at the indices ``idx``."""
+    y = y_grid(M)
+    fh = abel_fhat(f, y, Q)
+    a = fourier_coeffs_at(fh, idx)
+    n = np.asarray(idx, dtype=LD)
+    return (2 * n + 1) * a.real
 
 
 def y_grid(M: int) -> np.ndarray:

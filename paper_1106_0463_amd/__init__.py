@@ -1,0 +1,145 @@
+"""MI355X-native Legendre coefficients by the Abel-transform + FFT method of
+De Micheli & Viano (arXiv 1106.0463).
+
+Thin Python binding over the C ABI of ``include/lc.h``.  torch is used for
+device memory and streams only; every step of the method runs in the HIP
+library ``liblc.so`` (built for gfx950).  There is no CPU fallback: without
+the library, or without a GPU, calls raise.
+
+Typical use::
+
+    import torch, paper_1106_0463_amd as lc
+    p = lc.plan(N=64, M=256, Q=32)          # nodes x[H][Q] on the GPU
+    f = my_function(p.nodes)                # sample f at the nodes (torch)
+    c = p.execute(f)                        # c_0..c_{N-1}, float64 tensor
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from ._lib import (GEMM_MODES, LC_FP32_QUAD, LC_FP64, PRECISIONS, LCError,  # noqa: F401
+                   PlanDesc, check, load)
+
+__all__ = ["grid_size", "plan", "plan_batch", "plan_gemm", "Plan", "LCError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def grid_size(M: int) -> int:
+    """Effective y-grid size the library uses for a requested M."""
+    out = C.c_int64()
+    check(load().lc_grid_size(int(M), C.byref(out)), "lc_grid_size")
+    return int(out.value)
+
+
+class _DevArray:
+    """Zero-copy view of library-owned device memory for torch."""
+
+    def __init__(self, ptr: int, shape, typestr: str, owner):
+        self._owner = owner
+        self.__cuda_array_interface__ = {
+            "shape": tuple(int(s) for s in shape), "typestr": typestr,
+            "data": (int(ptr), True), "version": 2, "strides": None}
+
+
+def _view(ptr: int, shape, owner, dtype="float64"):
+    torch = _torch()
+    typestr = {"float64": "<f8"}[dtype]
+    t = torch.as_tensor(_DevArray(ptr, shape, typestr, owner), device="cuda")
+    return t
+
+
+class Plan:
+    """A plan created by :func:`plan`, :func:`plan_batch` or :func:`plan_gemm`."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+        self._lib = load()
+
+    # -- lifetime -----------------------------------------------------
+    def destroy(self) -> None:
+        if self._h:
+            self._lib.lc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.destroy()
+
+    # -- description --------------------------------------------------
+    @property
+    def info(self) -> dict:
+        d = PlanDesc()
+        check(self._lib.lc_plan_info(self._h, C.byref(d)), "lc_plan_info")
+        return {k: getattr(d, k) for k, _ in PlanDesc._fields_}
+
+    @property
+    def nodes(self):
+        """Device nodes (float64 tensor view owned by the plan): [H, Q] for a
+        single plan, the flat node arena for a batch plan, [P] for GEMM."""
+        ptr, rows, q = C.c_void_p(), C.c_int64(), C.c_int32()
+        check(self._lib.lc_plan_nodes(self._h, C.byref(ptr), C.byref(rows), C.byref(q)),
+              "lc_plan_nodes")
+        info = self.info
+        if info["kind"] == 0:
+            return _view(ptr.value, (rows.value, q.value), self)
+        return _view(ptr.value, (rows.value,), self)
+
+    # -- execution ----------------------------------------------------
+    def execute(self, f, out=None, stream=None):
+        """c_0..c_{N-1} from samples f[H][Q] (float64, or float32 for an
+        'fp32' plan) on the GPU; asynchronous on ``stream``."""
+        torch = _torch()
+        info = self.info
+        want = torch.float64 if info["precision"] == LC_FP64 else torch.float32
+        if f.dtype != want or not f.is_cuda or not f.is_contiguous():
+            raise ValueError(f"f must be a contiguous {want} CUDA tensor")
+        if f.numel() != info["samples"]:
+            raise ValueError(f"f has {f.numel()} samples, plan expects {info['samples']}")
+        if out is None:
+            out = torch.empty(info["N"], dtype=torch.float64, device=f.device)
+        elif out.dtype != torch.float64 or out.numel() < info["N"] or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of N elements")
+        check(self._lib.lc_execute(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   _stream_handle(stream)), "lc_execute")
+        return out
+
+    def set_timing(self, enable: bool = True) -> None:
+        check(self._lib.lc_plan_set_timing(self._h, 1 if enable else 0), "lc_plan_set_timing")
+
+    def kernel_ms(self) -> tuple[float, int]:
+        ms, n = C.c_double(), C.c_int32()
+        check(self._lib.lc_plan_kernel_ms(self._h, C.byref(ms), C.byref(n)), "lc_plan_kernel_ms")
+        return float(ms.value), int(n.value)
+
+    def autotune(self, stream=None) -> None:
+        check(self._lib.lc_autotune(self._h, _stream_handle(stream)), "lc_autotune")
+
+
+def plan(N: int, M: int, Q: int, precision: str = "fp64") -> Plan:
+    """Single-function plan: N coefficients, M-point y-grid, Q Abel nodes."""
+    h = C.c_void_p()
+    check(load().lc_plan(int(N), int(M), int(Q), PRECISIONS[precision], C.byref(h)), "lc_plan")
+    return Plan(h)
+
+
+from .batch import BatchPlan, plan_batch  # noqa: E402,F401
+from .gemm import GemmPlan, plan_gemm  # noqa: E402,F401

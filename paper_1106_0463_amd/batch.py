@@ -1,0 +1,63 @@
+"""Batched plans: many functions of uneven N/M/Q in one graph-captured
+execution (binding of lc_plan_batch / lc_execute_batch)."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import Plan, _stream_handle, _view
+from ._lib import PRECISIONS, check, load
+
+
+class BatchPlan(Plan):
+    def offsets(self):
+        """(f_off bytes, x_off elements, c_off elements), each of length B+1."""
+        B = self.info["B"]
+        f = np.zeros(B + 1, dtype=np.int64)
+        x = np.zeros(B + 1, dtype=np.int64)
+        c = np.zeros(B + 1, dtype=np.int64)
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+        check(self._lib.lc_plan_batch_offsets(self._h, p(f), p(x), p(c)), "lc_plan_batch_offsets")
+        return f, x, c
+
+    @property
+    def nodes(self):
+        ptr, rows, q = C.c_void_p(), C.c_int64(), C.c_int32()
+        check(self._lib.lc_plan_nodes(self._h, C.byref(ptr), C.byref(rows), C.byref(q)),
+              "lc_plan_nodes")
+        return _view(ptr.value, (rows.value,), self)
+
+    def execute(self, f_arena, c_arena=None, stream=None):
+        """f_arena: uint8 (or any dtype) CUDA tensor holding the sample arena
+        (layout of :meth:`offsets`); returns the float64 coefficient arena."""
+        import torch
+        f_off, _, c_off = self.offsets()
+        if not f_arena.is_cuda or f_arena.numel() * f_arena.element_size() < f_off[-1]:
+            raise ValueError("f_arena too small or not on the GPU")
+        if c_arena is None:
+            c_arena = torch.empty(int(c_off[-1]), dtype=torch.float64, device=f_arena.device)
+        check(self._lib.lc_execute_batch(self._h, C.c_void_p(f_arena.data_ptr()),
+                                         C.c_void_p(c_arena.data_ptr()), _stream_handle(stream)),
+              "lc_execute_batch")
+        return c_arena
+
+
+def plan_batch(N, M, Q, precision) -> BatchPlan:
+    """N, M, Q: integer sequences of length B; precision: sequence of
+    'fp64' / 'fp32' (or one string for all)."""
+    N = np.ascontiguousarray(N, dtype=np.int64)
+    M = np.ascontiguousarray(M, dtype=np.int64)
+    Q = np.ascontiguousarray(Q, dtype=np.int32)
+    B = N.size
+    if isinstance(precision, str):
+        precision = [precision] * B
+    pr = np.ascontiguousarray([PRECISIONS[p] for p in precision], dtype=np.int32)
+    if not (M.size == Q.size == pr.size == B):
+        raise ValueError("N, M, Q, precision must have one length")
+    h = C.c_void_p()
+    check(load().lc_plan_batch(int(B), N.ctypes.data_as(C.POINTER(C.c_int64)),
+                               M.ctypes.data_as(C.POINTER(C.c_int64)),
+                               Q.ctypes.data_as(C.POINTER(C.c_int32)),
+                               pr.ctypes.data_as(C.POINTER(C.c_int)), C.byref(h)), "lc_plan_batch")
+    return BatchPlan(h)

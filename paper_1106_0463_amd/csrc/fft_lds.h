@@ -1,0 +1,178 @@
+// LDS-resident Stockham FFT building blocks (FP64 complex, wave64, gfx950)
+// and the DST-III pack/unpack that turns the one FFT of eq. (2.4) into a
+// complex FFT of half length.  Header-only: included by every kernel file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lc_internal.h"
+
+namespace lc {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 mul_i(double2 a) { return make_double2(-a.y, a.x); }
+
+// Small DFTs in the positive-exponent direction: X_s = sum_r v_r e^{+2 pi i r s / R}.
+template <int R> struct Dft;
+
+template <> struct Dft<2> {
+    static __device__ __forceinline__ void run(double2 *v) {
+        double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <> struct Dft<3> {
+    static __device__ __forceinline__ void run(double2 *v) {
+        const double h = 0.86602540378443864676;  // sqrt(3)/2
+        double2 s = cadd(v[1], v[2]);
+        double2 d = csub(v[1], v[2]);
+        double2 m = make_double2(v[0].x - 0.5 * s.x, v[0].y - 0.5 * s.y);
+        double2 t = make_double2(-h * d.y, h * d.x);  // i * (sqrt(3)/2) * d
+        v[0] = cadd(v[0], s);
+        v[1] = cadd(m, t);
+        v[2] = csub(m, t);
+    }
+};
+
+template <> struct Dft<4> {
+    static __device__ __forceinline__ void run(double2 *v) {
+        double2 t0 = cadd(v[0], v[2]);
+        double2 t1 = csub(v[0], v[2]);
+        double2 t2 = cadd(v[1], v[3]);
+        double2 t3 = mul_i(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    }
+};
+
+template <> struct Dft<8> {
+    static __device__ __forceinline__ void run(double2 *v) {
+        const double c = 0.70710678118654752440;  // sqrt(1/2)
+        double2 e[4] = {v[0], v[2], v[4], v[6]};
+        double2 o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4>::run(e);
+        Dft<4>::run(o);
+        // o_s *= e^{+2 pi i s / 8}
+        o[1] = make_double2(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y));
+        o[2] = mul_i(o[2]);
+        o[3] = make_double2(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y));
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            v[s] = cadd(e[s], o[s]);
+            v[s + 4] = csub(e[s], o[s]);
+        }
+    }
+};
+
+// One radix-R Stockham pass over nsub independent transforms of length Lsub
+// stored back to back in LDS (in place: every thread first loads all of its
+// butterflies, then the block synchronizes, then results are stored).
+// Ns is the product of the radices of the previous passes.  Twiddles
+// e^{2 pi i m / Lsub} are read from tw[m * tw_stride].
+// Requires nsub * Lsub <= EPT * T (checked by the host launchers).
+template <int R, int T, int EPT>
+__device__ __forceinline__ void stockham_pass(double2 *__restrict__ lds, int Lsub, int nsub, int Ns,
+                                              const double2 *__restrict__ tw, int64_t tw_stride) {
+    constexpr int MAXB = (EPT + R - 1) / R;
+    const int nbs = Lsub / R;
+    const int total = nsub * nbs;
+    const int tid = threadIdx.x;
+    double2 v[MAXB][R];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * T;
+        if (b < total) {
+            const int sub = b / nbs;
+            const int j = b - sub * nbs;
+            const double2 *x = lds + sub * Lsub;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = x[j + r * nbs];
+        }
+    }
+    __syncthreads();
+    const int span = Ns * R;
+    const int twstep = Lsub / span;
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * T;
+        if (b < total) {
+            const int sub = b / nbs;
+            const int j = b - sub * nbs;
+            const int k = j % Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r)
+                    v[i][r] = cmul(v[i][r], tw[(int64_t)(k * r * twstep) * tw_stride]);
+            }
+            Dft<R>::run(v[i]);
+            double2 *y = lds + sub * Lsub;
+            const int base = (j / Ns) * span + k;
+#pragma unroll
+            for (int s = 0; s < R; ++s) y[base + s * Ns] = v[i][s];
+        }
+    }
+    __syncthreads();
+}
+
+// Unnormalized positive-exponent FFT of nsub transforms of length Lsub in LDS:
+// z_p = sum_k Z_k e^{+2 pi i p k / Lsub}, natural order in and out.
+template <int T, int EPT>
+__device__ void fft_lds(double2 *__restrict__ lds, int Lsub, int nsub, const FftSched &sch,
+                        const double2 *__restrict__ tw, int64_t tw_stride) {
+    int Ns = 1;
+    for (int p = 0; p < sch.npass; ++p) {
+        const int R = sch.radix[p];
+        switch (R) {
+            case 8: stockham_pass<8, T, EPT>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
+            case 4: stockham_pass<4, T, EPT>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
+            case 3: stockham_pass<3, T, EPT>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
+            default: stockham_pass<2, T, EPT>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
+        }
+        Ns *= R;
+    }
+}
+
+// DST-III pack.  With phi_m = phi[m-1] for m = 1..H (H = 2L) and
+//   V_k = e^{i pi k / (2H)} (phi_{H-k} - i phi_k)   (1 <= k < H),  V_0 = phi_H,
+//   Z_k = (V_k + V_{k+L}) + i e^{2 pi i k / H} (V_k - V_{k+L}),  0 <= k < L,
+// the length-L transform z = FFT(Z) carries the sums
+//   v_q = sum_{k<H} V_k e^{2 pi i q k / H}  as  v_{2p} = Re z_p, v_{2p+1} = Im z_p,
+// and the sine sums of eq. (2.4) follow in dst_post.  tw_pre[k] = e^{i pi k/(2H)}
+// (k < H), tw_pack[k] = e^{2 pi i k / H} (k < L).
+template <typename PhiAt>
+__device__ __forceinline__ double2 dst_pack(int64_t k, PhiAt phi, int64_t H, int64_t L,
+                                            const double2 *__restrict__ tw_pre,
+                                            const double2 *__restrict__ tw_pack) {
+    double2 vk;
+    if (k == 0) {
+        vk = make_double2(phi(H), 0.0);
+    } else {
+        vk = cmul(tw_pre[k], make_double2(phi(H - k), -phi(k)));
+    }
+    double2 vkl = cmul(tw_pre[k + L], make_double2(phi(L - k), -phi(L + k)));
+    double2 sum = cadd(vk, vkl);
+    double2 r = cmul(tw_pack[k], csub(vk, vkl));
+    return make_double2(sum.x - r.y, sum.y + r.x);
+}
+
+// DST-III unpack and rescale: c_n = (2n+1) a_n with
+//   a_n = (1/H) [ sum_{j<H} phi_j sin(pi (2n+1) j / (2H)) + (1/2)(-1)^n phi_H ]
+//       = (-1)^n X_n / H,  X_{2m} = v_m / 2,  X_{2m+1} = v_{H-1-m} / 2.
+__device__ __forceinline__ double dst_post(int64_t n, const double2 *z, int64_t H) {
+    const int64_t q = (n & 1) ? (H - 1 - (n >> 1)) : (n >> 1);
+    const double2 zz = z[q >> 1];
+    const double v = (q & 1) ? zz.y : zz.x;
+    const double sgn = (n & 1) ? -1.0 : 1.0;
+    return (double)(2 * n + 1) * sgn * v / (double)(2 * H);
+}
+
+}  // namespace lc

@@ -1,0 +1,539 @@
+// Host runtime of the Legendre-coefficient library: argument validation,
+// the Abel Gauss rule, twiddle tables, plan objects and the C ABI entry
+// points for single-function plans (batch and GEMM plans live in their own
+// files).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lc_internal.h"
+
+namespace lc {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+static lc_status fail(lc_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+static lc_status hip_fail(hipError_t e, const char *what) {
+    return fail(LC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int device_cu_count() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+// ------------------------------------------------------------ sizes ---
+int64_t smooth_len_at_least(int64_t L) {
+    if (L <= 1) return 1;
+    int64_t best = INT64_MAX;
+    for (int64_t p3 = 1; p3 < (int64_t)1 << 50; p3 *= 3) {
+        int64_t v = p3;
+        while (v < L) v *= 2;
+        best = std::min(best, v);
+        if (p3 > L) break;
+    }
+    return best;
+}
+
+FftSched make_sched(int L, const int *order) {
+    FftSched s{};
+    s.n = L;
+    int n = L, c8 = 0, c4 = 0, c2 = 0, c3 = 0;
+    while (n % 3 == 0) { n /= 3; ++c3; }
+    while (n % 8 == 0) { n /= 8; ++c8; }
+    if (n % 4 == 0) { n /= 4; ++c4; }
+    if (n % 2 == 0) { n /= 2; ++c2; }
+    // default order: largest radices first
+    std::vector<int> r;
+    if (order) {
+        for (int i = 0; order[i]; ++i) r.push_back(order[i]);
+    } else {
+        for (int i = 0; i < c8; ++i) r.push_back(8);
+        for (int i = 0; i < c4; ++i) r.push_back(4);
+        for (int i = 0; i < c3; ++i) r.push_back(3);
+        for (int i = 0; i < c2; ++i) r.push_back(2);
+    }
+    s.npass = (int)r.size();
+    for (int i = 0; i < s.npass && i < kMaxPasses; ++i) s.radix[i] = r[i];
+    return s;
+}
+
+// ------------------------------------------------------- Gauss rule ---
+// Positive half of the n = 2Q point Gauss-Legendre rule on [-1, 1]: the
+// folded rule for integral_0^1 g(t) dt with g even, sum w_q = 1, exact for
+// polynomials of degree <= 4Q-1 in t (degree <= 2Q-1 in x for the Abel map).
+// Newton iteration on P_n in long double with Tricomi's initial guesses.
+static void legendre_and_derivative(int n, long double x, long double &pn, long double &dpn) {
+    long double pkm1 = 1.0L, pk = x;
+    for (int k = 2; k <= n; ++k) {
+        long double pk1 = ((long double)(2 * k - 1) * x * pk - (long double)(k - 1) * pkm1) / (long double)k;
+        pkm1 = pk;
+        pk = pk1;
+    }
+    pn = pk;
+    dpn = (long double)n * (x * pk - pkm1) / (x * x - 1.0L);
+}
+
+void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w, std::vector<double> &omt2) {
+    const int n = 2 * Q;
+    t.assign(Q, 0.0);
+    w.assign(Q, 0.0);
+    omt2.assign(Q, 0.0);
+    const long double PI = 3.141592653589793238462643383279502884L;
+    auto work = [&](int i0, int i1) {
+        for (int i = i0; i < i1; ++i) {
+            const int k = i + 1;  // k-th largest root
+            const long double nn = (long double)n;
+            long double x = (1.0L - 1.0L / (8.0L * nn * nn) + 1.0L / (8.0L * nn * nn * nn)) *
+                            cosl(PI * (4.0L * k - 1.0L) / (4.0L * nn + 2.0L));
+            long double p, dp;
+            for (int it = 0; it < 60; ++it) {
+                legendre_and_derivative(n, x, p, dp);
+                long double dx = p / dp;
+                x -= dx;
+                if (fabsl(dx) <= 2.0L * 1.0842e-19L * fabsl(x)) break;
+            }
+            legendre_and_derivative(n, x, p, dp);
+            t[i] = (double)x;
+            w[i] = (double)(2.0L / ((1.0L - x * x) * dp * dp));
+            omt2[i] = (double)((1.0L - x) * (1.0L + x));
+        }
+    };
+    const long long cost = (long long)Q * n;
+    int nth = 1;
+    if (cost > 4000000LL) nth = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if (nth == 1) {
+        work(0, Q);
+    } else {
+        std::vector<std::thread> th;
+        const int chunk = (Q + nth - 1) / nth;
+        for (int a = 0; a < Q; a += chunk) th.emplace_back(work, a, std::min(Q, a + chunk));
+        for (auto &x : th) x.join();
+    }
+}
+
+// --------------------------------------------------------- twiddles ---
+// cos and sin of 2 pi num / den with exact integer reduction to an angle of
+// at most pi/4 before calling the long-double routines.
+static void sincos_turns(int64_t num, int64_t den, double *c, double *s) {
+    const long double HALF_PI = 1.570796326794896619231321691639751442L;
+    num %= den;
+    if (num < 0) num += den;
+    const int64_t q = (4 * num) / den;        // quadrant
+    const int64_t r = 4 * num - q * den;      // angle = (pi/2) (q + r/den)
+    long double cs, sn;
+    if (2 * r > den) {
+        const long double th = HALF_PI * (long double)(den - r) / (long double)den;
+        cs = sinl(th);
+        sn = cosl(th);
+    } else {
+        const long double th = HALF_PI * (long double)r / (long double)den;
+        cs = cosl(th);
+        sn = sinl(th);
+    }
+    long double rc, rs;
+    switch (q & 3) {
+        case 0: rc = cs; rs = sn; break;
+        case 1: rc = -sn; rs = cs; break;
+        case 2: rc = -cs; rs = -sn; break;
+        default: rc = sn; rs = -cs; break;
+    }
+    *c = (double)rc;
+    *s = (double)rs;
+}
+
+void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack, std::vector<double2> &fft) {
+    const int64_t L = H / 2;
+    pre.resize(H);
+    pack.resize(L);
+    fft.resize(L);
+    for (int64_t k = 0; k < H; ++k) sincos_turns(k, 4 * H, &pre[k].x, &pre[k].y);
+    for (int64_t k = 0; k < L; ++k) sincos_turns(k, H, &pack[k].x, &pack[k].y);
+    for (int64_t k = 0; k < L; ++k) sincos_turns(k, L, &fft[k].x, &fft[k].y);
+}
+
+// -------------------------------------------------- launch configs ---
+static bool fit_key_ok(int cpl, int u) {
+    const int key = cpl * 16 + u;
+    const int ok[] = {17, 18, 20, 33, 34, 36, 49, 50, 65, 66, 97, 129};
+    for (int k : ok)
+        if (k == key) return true;
+    return false;
+}
+
+QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu) {
+    QuadCfg c{};
+    c.block = 256;
+    const int esz = prec == LC_FP64 ? 8 : 4;
+    const int vfit = 16 / esz;
+    bool fit = false;
+    if (Q % vfit == 0) {
+        const int nc = Q / vfit;
+        for (int G : {8, 16, 4}) {
+            if (nc % G) continue;
+            const int cpl = nc / G;
+            int u = cpl <= 2 ? 4 : (cpl <= 4 ? 2 : 1);
+            while (u > 1 && !fit_key_ok(cpl, u)) u /= 2;
+            if (!fit_key_ok(cpl, u)) continue;
+            c.vec = vfit;
+            c.G = G;
+            c.cpl = cpl;
+            c.unroll = u;
+            fit = true;
+            break;
+        }
+    }
+    if (!fit) {
+        c.cpl = 0;
+        c.unroll = 1;
+        if (esz == 8 && Q % 2 == 0 && Q >= 32) {
+            c.vec = 2;
+            const int nc = Q / 2;
+            c.G = nc >= 64 ? 64 : (nc >= 32 ? 32 : 16);
+        } else {
+            c.vec = 1;
+            c.G = Q >= 64 ? 64 : (Q >= 32 ? 32 : (Q >= 16 ? 16 : (Q >= 8 ? 8 : 4)));
+        }
+    }
+    const int64_t rows_per_block = (int64_t)(c.block / 64) * (64 / c.G) * c.unroll;
+    int64_t grid = (rows + rows_per_block - 1) / rows_per_block;
+    grid = std::min<int64_t>(grid, (int64_t)num_cu * 8);
+    c.grid = (int)std::max<int64_t>(1, grid);
+    return c;
+}
+
+DstCfg default_dst_cfg(int64_t L) {
+    DstCfg d{};
+    if (L <= kLdsFftMax) {
+        d.threads = L <= 512 ? 64 : (L <= 2048 ? 256 : 1024);
+        d.sched = make_sched((int)L);
+        return d;
+    }
+    // four-step split: L1 the largest divisor <= sqrt(L), both <= 2048
+    int64_t best = 0;
+    for (int64_t a = 1; a * a <= L; ++a)
+        if (L % a == 0 && a <= 2048 && L / a <= 2048) best = a;
+    d.threads = 256;
+    if (best == 0) return d;  // unsupported (checked by the planner)
+    d.L1 = (int)best;
+    d.L2 = (int)(L / best);
+    d.s1 = make_sched(d.L1);
+    d.s2 = make_sched(d.L2);
+    return d;
+}
+
+}  // namespace lc
+
+using namespace lc;
+
+// ================================================================ C ABI ===
+extern "C" {
+
+const char *lc_status_string(lc_status s) {
+    switch (s) {
+        case LC_OK: return "LC_OK";
+        case LC_ERR_INVALID: return "LC_ERR_INVALID: invalid argument";
+        case LC_ERR_NOMEM: return "LC_ERR_NOMEM: allocation failed";
+        case LC_ERR_HIP: return "LC_ERR_HIP: HIP runtime error";
+        case LC_ERR_UNSUPPORTED: return "LC_ERR_UNSUPPORTED: not supported by this build";
+        case LC_ERR_INTERNAL: return "LC_ERR_INTERNAL: internal error";
+    }
+    return "unknown lc_status";
+}
+
+const char *lc_last_error(void) { return g_err.c_str(); }
+
+lc_status lc_grid_size(int64_t M, int64_t *M_eff) {
+    if (!M_eff) return fail(LC_ERR_INVALID, "lc_grid_size: M_eff is null");
+    if (M < 2) return fail(LC_ERR_INVALID, "lc_grid_size: M=%lld < 2", (long long)M);
+    if (M > ((int64_t)1 << 40)) return fail(LC_ERR_INVALID, "lc_grid_size: M=%lld too large", (long long)M);
+    const int64_t L = smooth_len_at_least((std::max<int64_t>(M, 4) + 3) / 4);
+    *M_eff = 4 * L;
+    return LC_OK;
+}
+
+}  // extern "C"
+
+namespace lc {
+
+static void free_single(lc_plan_s *p) {
+    hipFree(p->x);
+    hipFree(p->w);
+    hipFree(p->omt2);
+    hipFree(p->s2);
+    hipFree(p->tw_pre);
+    hipFree(p->tw_pack);
+    hipFree(p->tw_fft);
+    hipFree(p->phi);
+    hipFree(p->zA);
+    hipFree(p->zB);
+    for (auto e : p->ev) hipEventDestroy(e);
+    p->ev.clear();
+}
+
+template <typename T>
+static hipError_t dalloc(T **ptr, size_t count, int64_t *acc) {
+    *ptr = nullptr;
+    if (count == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void **)ptr, count * sizeof(T));
+    if (e == hipSuccess && acc) *acc += (int64_t)(count * sizeof(T));
+    return e;
+}
+
+lc_status validate_request(int64_t N, int64_t M, int32_t Q, int prec, const char *who) {
+    if (N < 1) return fail(LC_ERR_INVALID, "%s: N=%lld must be >= 1", who, (long long)N);
+    if (M < 2 || (M & 1)) return fail(LC_ERR_INVALID, "%s: M=%lld must be even and >= 2", who, (long long)M);
+    if (N > M / 2) return fail(LC_ERR_INVALID, "%s: N=%lld exceeds M/2=%lld", who, (long long)N, (long long)(M / 2));
+    if (Q < 1 || Q > 65536) return fail(LC_ERR_INVALID, "%s: Q=%d outside [1, 65536]", who, (int)Q);
+    if (prec != LC_FP64 && prec != LC_FP32_QUAD) return fail(LC_ERR_INVALID, "%s: bad precision %d", who, prec);
+    return LC_OK;
+}
+
+}  // namespace lc
+
+extern "C" {
+
+lc_status lc_plan(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t *out) {
+    if (!out) return fail(LC_ERR_INVALID, "lc_plan: out is null");
+    lc_status st = validate_request(N, M, Q, (int)prec, "lc_plan");
+    if (st != LC_OK) return st;
+    int64_t M_eff = 0;
+    if ((st = lc_grid_size(M, &M_eff)) != LC_OK) return st;
+    const int64_t H = M_eff / 2, L = H / 2;
+    DstCfg dcfg = default_dst_cfg(L);
+    if (L > kLdsFftMax && dcfg.L1 == 0)
+        return fail(LC_ERR_UNSUPPORTED, "lc_plan: FFT length %lld has no supported four-step split",
+                    (long long)L);
+    if ((double)H * (double)Q > 4.0e10)
+        return fail(LC_ERR_UNSUPPORTED, "lc_plan: H*Q=%.3g samples exceeds this build's limit",
+                    (double)H * (double)Q);
+
+    lc_plan_s *p = new (std::nothrow) lc_plan_s();
+    if (!p) return fail(LC_ERR_NOMEM, "lc_plan: host allocation failed");
+    p->kind = LC_PLAN_SINGLE;
+    hipGetDevice(&p->device);
+    p->fn.N = N;
+    p->fn.M = M;
+    p->fn.M_eff = M_eff;
+    p->fn.H = H;
+    p->fn.L = L;
+    p->fn.Q = Q;
+    p->fn.prec = (int)prec;
+
+    std::vector<double> t, w, omt2;
+    gauss_half_rule(Q, t, w, omt2);
+    std::vector<double2> pre, pack, fft;
+    twiddles(H, pre, pack, fft);
+
+    int64_t ws = 0;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    chk(dalloc(&p->x, (size_t)H * Q, &ws));
+    chk(dalloc(&p->w, (size_t)Q, &ws));
+    chk(dalloc(&p->omt2, (size_t)Q, &ws));
+    chk(dalloc(&p->s2, (size_t)H, &ws));
+    chk(dalloc(&p->tw_pre, (size_t)H, &ws));
+    chk(dalloc(&p->tw_pack, (size_t)L, &ws));
+    chk(dalloc(&p->tw_fft, (size_t)L, &ws));
+    chk(dalloc(&p->phi, (size_t)H, &ws));
+    if (L > kLdsFftMax) {
+        chk(dalloc(&p->zA, (size_t)L, &ws));
+        chk(dalloc(&p->zB, (size_t)L, &ws));
+    }
+    if (e != hipSuccess) {
+        free_single(p);
+        delete p;
+        return e == hipErrorOutOfMemory ? fail(LC_ERR_NOMEM, "lc_plan: device allocation failed")
+                                        : hip_fail(e, "lc_plan: hipMalloc");
+    }
+    p->workspace_bytes = ws;
+    chk(hipMemcpy(p->w, w.data(), Q * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(p->omt2, omt2.data(), Q * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(p->tw_pre, pre.data(), H * sizeof(double2), hipMemcpyHostToDevice));
+    chk(hipMemcpy(p->tw_pack, pack.data(), L * sizeof(double2), hipMemcpyHostToDevice));
+    chk(hipMemcpy(p->tw_fft, fft.data(), L * sizeof(double2), hipMemcpyHostToDevice));
+    if (e == hipSuccess) chk(launch_nodes(H, Q, p->omt2, p->x, p->s2, 0));
+    if (e == hipSuccess) chk(hipDeviceSynchronize());
+    if (e != hipSuccess) {
+        free_single(p);
+        delete p;
+        return hip_fail(e, "lc_plan: building nodes");
+    }
+    p->quad = default_quad_cfg((int)prec, Q, H, device_cu_count());
+    p->dst = dcfg;
+    const int esz = prec == LC_FP64 ? 8 : 4;
+    const double bytes = (double)H * Q * esz;
+    p->fused_small = (bytes <= 256.0 * 1024 && H <= 4096 && fused_small_lds_bytes(H, Q) <= 65536);
+    p->fused_threads = L <= 2048 ? 256 : 1024;
+    *out = p;
+    return LC_OK;
+}
+
+lc_status lc_plan_info(lc_plan_t p, lc_plan_desc *d);
+lc_status lc_plan_nodes(lc_plan_t p, const double **x_dev, int64_t *rows, int32_t *Q);
+
+}  // extern "C"
+
+// Shared helpers for timing (used by all plan kinds).
+namespace lc {
+hipError_t timing_begin(lc_plan_s *p, hipStream_t s, int *slot) {
+    *slot = -1;
+    if (!p->timing) return hipSuccess;
+    if (p->ev_used >= 4096) return hipSuccess;
+    if ((int)p->ev.size() < 2 * (p->ev_used + 1)) {
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) { hipEventDestroy(a); return e; }
+        p->ev.push_back(a);
+        p->ev.push_back(b);
+    }
+    *slot = p->ev_used++;
+    return hipEventRecord(p->ev[2 * *slot], s);
+}
+hipError_t timing_end(lc_plan_s *p, hipStream_t s, int slot) {
+    if (slot < 0) return hipSuccess;
+    return hipEventRecord(p->ev[2 * slot + 1], s);
+}
+}  // namespace lc
+
+extern "C" {
+
+lc_status lc_execute(lc_plan_t p, const void *f_dev, double *c_dev, hipStream_t stream) {
+    if (!p) return fail(LC_ERR_INVALID, "lc_execute: plan is null");
+    if (p->kind != LC_PLAN_SINGLE) return fail(LC_ERR_INVALID, "lc_execute: not a single-function plan");
+    if (!f_dev || !c_dev) return fail(LC_ERR_INVALID, "lc_execute: null f_dev or c_dev");
+    if (((uintptr_t)f_dev) & 15) return fail(LC_ERR_INVALID, "lc_execute: f_dev must be 16-byte aligned");
+    const FnDesc &d = p->fn;
+    int slot = -1;
+    hipError_t e = timing_begin(p, stream, &slot);
+    if (e != hipSuccess) return hip_fail(e, "lc_execute: timing event");
+    if (p->fused_small) {
+        e = launch_fused_small(p->fused_threads, d.prec, f_dev, p->w, p->s2, d.H, d.Q, d.N, p->dst.sched,
+                               p->tw_pre, p->tw_pack, p->tw_fft, c_dev, stream);
+        if (e != hipSuccess) return hip_fail(e, "lc_execute: fused kernel launch");
+        e = timing_end(p, stream, slot);
+        if (e != hipSuccess) return hip_fail(e, "lc_execute: timing event");
+        return LC_OK;
+    }
+    e = launch_quad(p->quad, d.prec, f_dev, p->w, p->s2, d.H, d.Q, p->phi, stream);
+    if (e != hipSuccess) return hip_fail(e, "lc_execute: quadrature kernel launch");
+    e = timing_end(p, stream, slot);
+    if (e != hipSuccess) return hip_fail(e, "lc_execute: timing event");
+    e = launch_dst(p->dst, p->phi, d.H, d.L, d.N, p->tw_pre, p->tw_pack, p->tw_fft, p->zA, p->zB, c_dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "lc_execute: FFT kernel launch");
+    return LC_OK;
+}
+
+lc_status lc_plan_set_timing(lc_plan_t p, int32_t enable) {
+    if (!p) return fail(LC_ERR_INVALID, "lc_plan_set_timing: plan is null");
+    p->timing = enable != 0;
+    p->ev_used = 0;
+    return LC_OK;
+}
+
+lc_status lc_plan_kernel_ms(lc_plan_t p, double *avg_ms, int32_t *count) {
+    if (!p || !avg_ms) return fail(LC_ERR_INVALID, "lc_plan_kernel_ms: null argument");
+    if (!p->timing || p->ev_used == 0) return fail(LC_ERR_INVALID, "lc_plan_kernel_ms: nothing recorded");
+    double sum = 0.0;
+    for (int i = 0; i < p->ev_used; ++i) {
+        hipError_t e = hipEventSynchronize(p->ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "lc_plan_kernel_ms: hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "lc_plan_kernel_ms: hipEventElapsedTime");
+        sum += ms;
+    }
+    *avg_ms = sum / p->ev_used;
+    if (count) *count = p->ev_used;
+    return LC_OK;
+}
+
+}  // extern "C"
+
+namespace lc {
+// Implemented in host_batch.cpp / host_gemm.cpp.
+void destroy_batch(lc_plan_s *p);
+void destroy_gemm(lc_plan_s *p);
+void info_batch(lc_plan_s *p, lc_plan_desc *d);
+void info_gemm(lc_plan_s *p, lc_plan_desc *d);
+lc_status nodes_batch(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
+lc_status nodes_gemm(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
+}  // namespace lc
+
+extern "C" {
+
+lc_status lc_plan_info(lc_plan_t p, lc_plan_desc *d) {
+    if (!p || !d) return fail(LC_ERR_INVALID, "lc_plan_info: null argument");
+    lc_plan_desc o{};
+    o.kind = p->kind;
+    if (p->kind == LC_PLAN_SINGLE) {
+        o.precision = p->fn.prec;
+        o.N = p->fn.N;
+        o.M = p->fn.M;
+        o.M_eff = p->fn.M_eff;
+        o.H = p->fn.H;
+        o.Q = p->fn.Q;
+        o.samples = p->fn.H * (int64_t)p->fn.Q;
+        o.sample_bytes = o.samples * (p->fn.prec == LC_FP64 ? 8 : 4);
+        o.workspace_bytes = p->workspace_bytes;
+    } else if (p->kind == LC_PLAN_BATCH) {
+        info_batch(p, &o);
+    } else {
+        info_gemm(p, &o);
+    }
+    *d = o;
+    return LC_OK;
+}
+
+lc_status lc_plan_nodes(lc_plan_t p, const double **x_dev, int64_t *rows, int32_t *Q) {
+    if (!p || !x_dev) return fail(LC_ERR_INVALID, "lc_plan_nodes: null argument");
+    if (p->kind == LC_PLAN_BATCH) return nodes_batch(p, x_dev, rows, Q);
+    if (p->kind == LC_PLAN_GEMM) return nodes_gemm(p, x_dev, rows, Q);
+    *x_dev = p->x;
+    if (rows) *rows = p->fn.H;
+    if (Q) *Q = p->fn.Q;
+    return LC_OK;
+}
+
+lc_status lc_plan_destroy(lc_plan_t p) {
+    if (!p) return LC_OK;
+    hipDeviceSynchronize();
+    if (p->kind == LC_PLAN_BATCH) destroy_batch(p);
+    else if (p->kind == LC_PLAN_GEMM) destroy_gemm(p);
+    free_single(p);
+    delete p;
+    return LC_OK;
+}
+
+}  // extern "C"
+
+namespace lc {
+lc_status fail_status(lc_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+}  // namespace lc

@@ -1,0 +1,461 @@
+// HIP kernels of the single-function path (gfx950, wave64):
+//   * node construction  x_{jq} = 1 - 2 s_j^2 (1 - t_q^2)   (FP64, half-angle form)
+//   * Abel quadrature reduction  phi_j = 2 s_j sum_q w_q f[j][q]   (HBM-bound)
+//   * DST-III of eq. (2.4) through an LDS Stockham FFT of length H/2, fused
+//     with the twist and the (2n+1) rescale; four-step form for long FFTs.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+#include "lc_internal.h"
+
+namespace lc {
+
+// ---------------------------------------------------------------- nodes ---
+// Row r (r = 0..H-1) is y_j = pi j / H with j = r + 1; s_j = sin(y_j / 2)
+// = sinpi(j / (2H)).  The half-angle form keeps 1 - x = 2 s^2 (1 - t^2)
+// accurate near y = 0 (no cancellation in cos y).
+__global__ __launch_bounds__(256) void k_nodes(int64_t H, int Q, const double *__restrict__ omt2,
+                                               double *__restrict__ x, double *__restrict__ s2) {
+    const int64_t total = H * (int64_t)Q;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = idx / Q;
+        const int q = (int)(idx - r * Q);
+        const double s = sinpi((double)(r + 1) / (double)(2 * H));
+        x[idx] = fma(-2.0 * (s * s), omt2[q], 1.0);
+        if (q == 0) s2[r] = 2.0 * s;
+    }
+}
+
+hipError_t launch_nodes(int64_t H, int Q, const double *omt2, double *x, double *s2, hipStream_t s) {
+    const int64_t total = H * (int64_t)Q;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_nodes, dim3((unsigned)blocks), dim3(256), 0, s, H, Q, omt2, x, s2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------- quadrature reduction ---
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int VEC> struct VecOf;
+template <> struct VecOf<double, 1> { using type = double; };
+template <> struct VecOf<double, 2> { using type = dv2; };
+template <> struct VecOf<float, 1> { using type = float; };
+template <> struct VecOf<float, 2> { using type = fv2; };
+template <> struct VecOf<float, 4> { using type = fv4; };
+
+__device__ __forceinline__ void to_d(double v, double *o) { o[0] = v; }
+__device__ __forceinline__ void to_d(dv2 v, double *o) { o[0] = v.x; o[1] = v.y; }
+__device__ __forceinline__ void to_d(float v, double *o) { o[0] = (double)v; }
+__device__ __forceinline__ void to_d(fv2 v, double *o) { o[0] = (double)v.x; o[1] = (double)v.y; }
+__device__ __forceinline__ void to_d(fv4 v, double *o) {
+    o[0] = (double)v.x; o[1] = (double)v.y; o[2] = (double)v.z; o[3] = (double)v.w;
+}
+
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+template <int G>
+__device__ __forceinline__ double group_sum(double acc) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    return acc;
+}
+
+// Exact-fit variant: a row of Q = G*CPL*VEC samples is read by G lanes, each
+// lane always owning the same CPL chunks of VEC samples, so its weights stay
+// in registers.  Each wave handles 64/G rows per step, U steps unrolled, so a
+// lane keeps U*CPL 16-byte loads in flight.  Accumulation is FP64 with a
+// fixed-order butterfly reduction over the G lanes (deterministic).
+template <typename T, int VEC, int G, int CPL, int U>
+__global__ __launch_bounds__(256) void k_quad_fit(const T *__restrict__ f, const double *__restrict__ w,
+                                                  const double *__restrict__ s2, int64_t rows,
+                                                  double *__restrict__ phi) {
+    using V = typename VecOf<T, VEC>::type;
+    constexpr int Q = G * CPL * VEC;
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int rg = lane / G;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    double wr[CPL][VEC];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) wr[c][e] = w[(g + c * G) * VEC + e];
+
+    for (int64_t r0 = wave * (RPW * U); r0 < rows; r0 += nwaves * (RPW * U)) {
+        V val[U][CPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = r0 + u * RPW + rg;
+            if (row < rows) {
+                const V *p = reinterpret_cast<const V *>(f + row * Q) + g;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) val[u][c] = ld_stream(p + c * G);
+            } else {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) val[u][c] = (V)(T)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                double d[VEC];
+                to_d(val[u][c], d);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc = fma(wr[c][e], d[e], acc);
+            }
+            acc = group_sum<G>(acc);
+            const int64_t row = r0 + u * RPW + rg;
+            if (g == 0 && row < rows) phi[row] = s2[row] * acc;
+        }
+    }
+}
+
+// Generic variant for any Q: G lanes per row stride over the Q/VEC chunks
+// with bounds checks, 4 chunks in flight per lane; weights from global
+// memory (L1/L2 resident: every row reuses them).
+template <typename T, int VEC, int G>
+__device__ __forceinline__ double row_partial(const T *__restrict__ frow, const double *__restrict__ w,
+                                              int NC, int g) {
+    using V = typename VecOf<T, VEC>::type;
+    const V *p = reinterpret_cast<const V *>(frow);
+    double acc0 = 0.0, acc1 = 0.0;
+    int c = g;
+    for (; c + 3 * G < NC; c += 4 * G) {
+        V a = ld_stream(p + c), b = ld_stream(p + c + G), cc = ld_stream(p + c + 2 * G),
+          dd = ld_stream(p + c + 3 * G);
+        double da[VEC], db[VEC], dc[VEC], dd_[VEC];
+        to_d(a, da); to_d(b, db); to_d(cc, dc); to_d(dd, dd_);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            acc0 = fma(w[c * VEC + e], da[e], acc0);
+            acc1 = fma(w[(c + G) * VEC + e], db[e], acc1);
+            acc0 = fma(w[(c + 2 * G) * VEC + e], dc[e], acc0);
+            acc1 = fma(w[(c + 3 * G) * VEC + e], dd_[e], acc1);
+        }
+    }
+    for (; c < NC; c += G) {
+        V a = ld_stream(p + c);
+        double da[VEC];
+        to_d(a, da);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc0 = fma(w[c * VEC + e], da[e], acc0);
+    }
+    return acc0 + acc1;
+}
+
+template <typename T, int VEC, int G>
+__global__ __launch_bounds__(256) void k_quad_gen(const T *__restrict__ f, const double *__restrict__ w,
+                                                  const double *__restrict__ s2, int64_t rows, int Q,
+                                                  double *__restrict__ phi) {
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int rg = lane / G;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int NC = Q / VEC;
+    for (int64_t r0 = wave * RPW; r0 < rows; r0 += nwaves * RPW) {
+        const int64_t row = r0 + rg;
+        double acc = 0.0;
+        if (row < rows) acc = row_partial<T, VEC, G>(f + row * Q, w, NC, g);
+        acc = group_sum<G>(acc);
+        if (g == 0 && row < rows) phi[row] = s2[row] * acc;
+    }
+}
+
+template <typename T, int VEC, int G, int CPL, int U>
+static hipError_t go_fit(const QuadCfg &c, const void *f, const double *w, const double *s2, int64_t rows,
+                         double *phi, hipStream_t s) {
+    hipLaunchKernelGGL((k_quad_fit<T, VEC, G, CPL, U>), dim3(c.grid), dim3(c.block), 0, s,
+                       (const T *)f, w, s2, rows, phi);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC, int G>
+static hipError_t go_gen(const QuadCfg &c, const void *f, const double *w, const double *s2, int64_t rows,
+                         int Q, double *phi, hipStream_t s) {
+    hipLaunchKernelGGL((k_quad_gen<T, VEC, G>), dim3(c.grid), dim3(c.block), 0, s, (const T *)f, w, s2,
+                       rows, Q, phi);
+    return hipGetLastError();
+}
+
+// Dispatch tables over the instantiated variants.
+#define LC_FIT_CASES(TT, VV, GG)                                                                  \
+    if (c.G == GG && c.vec == VV) {                                                              \
+        switch (c.cpl * 16 + c.unroll) {                                                         \
+            case 1 * 16 + 1: return go_fit<TT, VV, GG, 1, 1>(c, f, w, s2, rows, phi, s);          \
+            case 1 * 16 + 2: return go_fit<TT, VV, GG, 1, 2>(c, f, w, s2, rows, phi, s);          \
+            case 1 * 16 + 4: return go_fit<TT, VV, GG, 1, 4>(c, f, w, s2, rows, phi, s);          \
+            case 2 * 16 + 1: return go_fit<TT, VV, GG, 2, 1>(c, f, w, s2, rows, phi, s);          \
+            case 2 * 16 + 2: return go_fit<TT, VV, GG, 2, 2>(c, f, w, s2, rows, phi, s);          \
+            case 2 * 16 + 4: return go_fit<TT, VV, GG, 2, 4>(c, f, w, s2, rows, phi, s);          \
+            case 3 * 16 + 1: return go_fit<TT, VV, GG, 3, 1>(c, f, w, s2, rows, phi, s);          \
+            case 3 * 16 + 2: return go_fit<TT, VV, GG, 3, 2>(c, f, w, s2, rows, phi, s);          \
+            case 4 * 16 + 1: return go_fit<TT, VV, GG, 4, 1>(c, f, w, s2, rows, phi, s);          \
+            case 4 * 16 + 2: return go_fit<TT, VV, GG, 4, 2>(c, f, w, s2, rows, phi, s);          \
+            case 6 * 16 + 1: return go_fit<TT, VV, GG, 6, 1>(c, f, w, s2, rows, phi, s);          \
+            case 8 * 16 + 1: return go_fit<TT, VV, GG, 8, 1>(c, f, w, s2, rows, phi, s);          \
+            default: break;                                                                      \
+        }                                                                                        \
+    }
+
+template <typename T>
+static hipError_t dispatch_quad(const QuadCfg &c, const void *f, const double *w, const double *s2,
+                                int64_t rows, int Q, double *phi, hipStream_t s) {
+    if (c.cpl > 0) {
+        if constexpr (sizeof(T) == 8) {
+            LC_FIT_CASES(T, 2, 4)
+            LC_FIT_CASES(T, 2, 8)
+            LC_FIT_CASES(T, 2, 16)
+        } else {
+            LC_FIT_CASES(T, 4, 4)
+            LC_FIT_CASES(T, 4, 8)
+            LC_FIT_CASES(T, 4, 16)
+        }
+        return hipErrorInvalidValue;
+    }
+    switch (c.vec * 1000 + c.G) {
+        case 1004: return go_gen<T, 1, 4>(c, f, w, s2, rows, Q, phi, s);
+        case 1008: return go_gen<T, 1, 8>(c, f, w, s2, rows, Q, phi, s);
+        case 1016: return go_gen<T, 1, 16>(c, f, w, s2, rows, Q, phi, s);
+        case 1032: return go_gen<T, 1, 32>(c, f, w, s2, rows, Q, phi, s);
+        case 1064: return go_gen<T, 1, 64>(c, f, w, s2, rows, Q, phi, s);
+        case 2016: return go_gen<T, 2, 16>(c, f, w, s2, rows, Q, phi, s);
+        case 2032: return go_gen<T, 2, 32>(c, f, w, s2, rows, Q, phi, s);
+        case 2064: return go_gen<T, 2, 64>(c, f, w, s2, rows, Q, phi, s);
+        default: break;
+    }
+    return hipErrorInvalidValue;
+}
+#undef LC_FIT_CASES
+
+bool quad_cfg_supported(const QuadCfg &c, int prec, int Q) {
+    const int esz = prec == LC_FP64 ? 8 : 4;
+    if (c.block != 256 || c.grid < 1) return false;
+    if (Q % c.vec) return false;
+    if (c.cpl > 0) {
+        const int vec_ok = esz == 8 ? 2 : 4;
+        if (c.vec != vec_ok) return false;
+        if (!(c.G == 4 || c.G == 8 || c.G == 16)) return false;
+        if (c.G * c.cpl * c.vec != Q) return false;
+        const int key = c.cpl * 16 + c.unroll;
+        const int ok[] = {17, 18, 20, 33, 34, 36, 49, 50, 65, 66, 97, 129};
+        for (int k : ok)
+            if (k == key) return true;
+        return false;
+    }
+    if (c.vec == 1) return c.G == 4 || c.G == 8 || c.G == 16 || c.G == 32 || c.G == 64;
+    if (c.vec == 2) return c.G == 16 || c.G == 32 || c.G == 64;
+    return false;
+}
+
+hipError_t launch_quad(const QuadCfg &cfg, int prec, const void *f, const double *w, const double *s2,
+                       int64_t rows, int Q, double *phi, hipStream_t s) {
+    if (!quad_cfg_supported(cfg, prec, Q)) return hipErrorInvalidValue;
+    if (prec == LC_FP64) return dispatch_quad<double>(cfg, f, w, s2, rows, Q, phi, s);
+    return dispatch_quad<float>(cfg, f, w, s2, rows, Q, phi, s);
+}
+
+// ------------------------------------------------------------------ DST ---
+struct GlobalPhi {
+    const double *p;
+    __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
+};
+struct LdsPhi {
+    const double *p;
+    __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
+};
+
+// Whole DST in one workgroup: pack phi into Z (LDS), Stockham FFT of length
+// L = H/2, unpack + rescale into c.
+template <int T>
+__global__ __launch_bounds__(T) void k_dst_lds(const double *__restrict__ phi, int64_t H, int L, int64_t N,
+                                               const double2 *__restrict__ tw_pre,
+                                               const double2 *__restrict__ tw_pack,
+                                               const double2 *__restrict__ tw_fft, FftSched sch,
+                                               double *__restrict__ c) {
+    extern __shared__ double2 lds[];
+    GlobalPhi ph{phi};
+    for (int k = threadIdx.x; k < L; k += T) lds[k] = dst_pack(k, ph, H, L, tw_pre, tw_pack);
+    __syncthreads();
+    fft_lds<T, 8>(lds, L, 1, sch, tw_fft, 1);
+    for (int64_t n = threadIdx.x; n < N; n += T) c[n] = dst_post(n, lds, H);
+}
+
+// Four-step FFT of length L = L1 * L2 (k = L2 k1 + k2, p = p1 + L1 p2):
+// columns:  A[p1][k2] = e^{2 pi i p1 k2 / L} sum_{k1} Z[L2 k1 + k2] e^{2 pi i p1 k1 / L1}
+// rows:     z[p1 + L1 p2] = sum_{k2} A[p1][k2] e^{2 pi i p2 k2 / L2}
+template <int T>
+__global__ __launch_bounds__(T) void k_fft_cols(const double *__restrict__ phi, int64_t H, int L1, int L2,
+                                                int CB, FftSched s1, const double2 *__restrict__ tw_pre,
+                                                const double2 *__restrict__ tw_pack,
+                                                const double2 *__restrict__ tw_fft, double2 *__restrict__ A) {
+    extern __shared__ double2 lds[];
+    const int64_t L = (int64_t)L1 * L2;
+    const int k20 = blockIdx.x * CB;
+    GlobalPhi ph{phi};
+    for (int e = threadIdx.x; e < CB * L1; e += T) {
+        const int k1 = e / CB, cb = e - k1 * CB;
+        lds[cb * L1 + k1] = dst_pack((int64_t)L2 * k1 + k20 + cb, ph, H, L, tw_pre, tw_pack);
+    }
+    __syncthreads();
+    fft_lds<T, 8>(lds, L1, CB, s1, tw_fft, L2);
+    for (int e = threadIdx.x; e < CB * L1; e += T) {
+        const int p1 = e / CB, cb = e - p1 * CB;
+        const int k2 = k20 + cb;
+        A[(int64_t)p1 * L2 + k2] = cmul(lds[cb * L1 + p1], tw_fft[(int64_t)p1 * k2]);
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_fft_rows(const double2 *__restrict__ A, int L1, int L2, int RB,
+                                                FftSched s2, const double2 *__restrict__ tw_fft,
+                                                double2 *__restrict__ z) {
+    extern __shared__ double2 lds[];
+    const int p10 = blockIdx.x * RB;
+    for (int e = threadIdx.x; e < RB * L2; e += T) lds[e] = A[(int64_t)p10 * L2 + e];
+    __syncthreads();
+    fft_lds<T, 8>(lds, L2, RB, s2, tw_fft, L1);
+    for (int e = threadIdx.x; e < RB * L2; e += T) {
+        const int p2 = e / RB, rb = e - p2 * RB;
+        z[(int64_t)(p10 + rb) + (int64_t)L1 * p2] = lds[rb * L2 + p2];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dst_post(const double2 *__restrict__ z, int64_t H, int64_t N,
+                                                  double *__restrict__ c) {
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * blockDim.x)
+        c[n] = dst_post(n, z, H);
+}
+
+template <typename K>
+static hipError_t allow_lds(K kern, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_dst(const DstCfg &cfg, const double *phi, int64_t H, int64_t L, int64_t N,
+                      const double2 *tw_pre, const double2 *tw_pack, const double2 *tw_fft, double2 *zA,
+                      double2 *zB, double *c, hipStream_t s) {
+    hipError_t e;
+    if (L <= kLdsFftMax) {
+        const size_t lds = (size_t)L * sizeof(double2);
+        if (L > 8 * cfg.threads) return hipErrorInvalidValue;
+        switch (cfg.threads) {
+            case 64:
+                hipLaunchKernelGGL(k_dst_lds<64>, dim3(1), dim3(64), lds, s, phi, H, (int)L, N, tw_pre,
+                                   tw_pack, tw_fft, cfg.sched, c);
+                break;
+            case 256:
+                if ((e = allow_lds(k_dst_lds<256>, lds)) != hipSuccess) return e;
+                hipLaunchKernelGGL(k_dst_lds<256>, dim3(1), dim3(256), lds, s, phi, H, (int)L, N, tw_pre,
+                                   tw_pack, tw_fft, cfg.sched, c);
+                break;
+            case 1024:
+                if ((e = allow_lds(k_dst_lds<1024>, lds)) != hipSuccess) return e;
+                hipLaunchKernelGGL(k_dst_lds<1024>, dim3(1), dim3(1024), lds, s, phi, H, (int)L, N, tw_pre,
+                                   tw_pack, tw_fft, cfg.sched, c);
+                break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    // four-step through global memory (256 threads, <= 2048 elements per block)
+    const int L1 = cfg.L1, L2 = cfg.L2;
+    if ((int64_t)L1 * L2 != L || L1 > 2048 || L2 > 2048) return hipErrorInvalidValue;
+    const int CB = (2048 / L1) < L2 ? (2048 / L1) : L2;
+    const int RB = (2048 / L2) < L1 ? (2048 / L2) : L1;
+    if (L2 % CB || L1 % RB) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fft_cols<256>, dim3(L2 / CB), dim3(256), (size_t)CB * L1 * sizeof(double2), s, phi, H,
+                       L1, L2, CB, cfg.s1, tw_pre, tw_pack, tw_fft, zA);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fft_rows<256>, dim3(L1 / RB), dim3(256), (size_t)RB * L2 * sizeof(double2), s, zA, L1,
+                       L2, RB, cfg.s2, tw_fft, zB);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int64_t blocks = (N + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_dst_post, dim3((unsigned)blocks), dim3(256), 0, s, zB, H, N, c);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ fused small path ---
+// One workgroup does everything (quadrature into LDS, pack, FFT, unpack):
+// one launch for problems whose samples are a few hundred KiB at most.
+size_t fused_small_lds_bytes(int64_t H, int Q) {
+    (void)Q;
+    return (size_t)H * sizeof(double) + (size_t)(H / 2) * sizeof(double2);
+}
+
+template <typename T, int TH>
+__global__ __launch_bounds__(TH) void k_fused_small(const T *__restrict__ f, const double *__restrict__ w,
+                                                    const double *__restrict__ s2, int64_t H, int Q,
+                                                    int64_t N, FftSched sch,
+                                                    const double2 *__restrict__ tw_pre,
+                                                    const double2 *__restrict__ tw_pack,
+                                                    const double2 *__restrict__ tw_fft,
+                                                    double *__restrict__ c) {
+    extern __shared__ double2 lds[];
+    const int L = (int)(H / 2);
+    double *phs = reinterpret_cast<double *>(lds + L);
+    constexpr int G = 16;
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int rg = lane / G;
+    const int wave = threadIdx.x >> 6;
+    constexpr int NW = TH / 64;
+    for (int64_t r0 = (int64_t)wave * RPW; r0 < H; r0 += NW * RPW) {
+        const int64_t row = r0 + rg;
+        double acc = 0.0;
+        if (row < H) acc = row_partial<T, 1, G>(f + row * Q, w, Q, g);
+        acc = group_sum<G>(acc);
+        if (g == 0 && row < H) phs[row] = s2[row] * acc;
+    }
+    __syncthreads();
+    LdsPhi ph{phs};
+    for (int k = threadIdx.x; k < L; k += TH) lds[k] = dst_pack(k, ph, H, L, tw_pre, tw_pack);
+    __syncthreads();
+    fft_lds<TH, 8>(lds, L, 1, sch, tw_fft, 1);
+    for (int64_t n = threadIdx.x; n < N; n += TH) c[n] = dst_post(n, lds, H);
+}
+
+hipError_t launch_fused_small(int threads, int prec, const void *f, const double *w, const double *s2,
+                              int64_t H, int Q, int64_t N, const FftSched &sch, const double2 *tw_pre,
+                              const double2 *tw_pack, const double2 *tw_fft, double *c, hipStream_t s) {
+    const size_t lds = fused_small_lds_bytes(H, Q);
+    if (H / 2 > 8 * threads || lds > 65536) return hipErrorInvalidValue;
+    if (prec == LC_FP64) {
+        if (threads == 256)
+            hipLaunchKernelGGL((k_fused_small<double, 256>), dim3(1), dim3(256), lds, s, (const double *)f, w,
+                               s2, H, Q, N, sch, tw_pre, tw_pack, tw_fft, c);
+        else if (threads == 1024)
+            hipLaunchKernelGGL((k_fused_small<double, 1024>), dim3(1), dim3(1024), lds, s, (const double *)f,
+                               w, s2, H, Q, N, sch, tw_pre, tw_pack, tw_fft, c);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        if (threads == 256)
+            hipLaunchKernelGGL((k_fused_small<float, 256>), dim3(1), dim3(256), lds, s, (const float *)f, w,
+                               s2, H, Q, N, sch, tw_pre, tw_pack, tw_fft, c);
+        else if (threads == 1024)
+            hipLaunchKernelGGL((k_fused_small<float, 1024>), dim3(1), dim3(1024), lds, s, (const float *)f, w,
+                               s2, H, Q, N, sch, tw_pre, tw_pack, tw_fft, c);
+        else
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lc

@@ -1,0 +1,121 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the Legendre-coefficient library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lc.h"
+
+namespace lc {
+
+// Longest complex FFT that one workgroup keeps resident in LDS
+// (8192 complex doubles = 128 KiB of the 160 KiB per CU).
+constexpr int kLdsFftMax = 8192;
+constexpr int kMaxPasses = 24;
+
+// Radix schedule of a Stockham FFT, passed to kernels by value.
+struct FftSched {
+    int n;                   // transform length
+    int npass;
+    int radix[kMaxPasses];
+};
+
+// Quadrature-reduction launch configuration.
+struct QuadCfg {
+    int vec;        // elements per lane load (16 B loads where the row allows)
+    int G;          // lanes per row (power of two, <= 64)
+    int cpl;        // chunks per lane (0: generic loop with bounds checks)
+    int unroll;     // rows per row-group per iteration
+    int block;      // threads per block
+    int grid;       // blocks
+};
+
+struct DstCfg {
+    int threads;    // threads per workgroup of the LDS FFT kernels
+    FftSched sched; // schedule for the whole length (single pass)
+    int L1, L2;     // four-step split (L1 * L2 = L) when L > kLdsFftMax
+    FftSched s1, s2;
+};
+
+// One function's worth of plan data (single plans use one; batch plans many).
+struct FnDesc {
+    int64_t N, M, M_eff, H, L;
+    int32_t Q;
+    int32_t prec;        // lc_precision
+    int64_t f_off;       // byte offset in the sample arena (batch)
+    int64_t x_off;       // element offset in the node arena (batch)
+    int64_t c_off;       // element offset in the coefficient arena (batch)
+    int64_t phi_off;     // element offset in the phi arena (batch)
+    int32_t tw_id;       // index of its twiddle set (batch)
+    int32_t w_id;        // index of its Gauss rule (batch)
+};
+
+// Device-side descriptor of a batch function (plain data for kernels).
+struct DevFn {
+    int64_t N, H, L;
+    int64_t f_off, c_off, phi_off, row0;
+    const double2 *tw_pre, *tw_pack, *tw_fft;
+    int32_t Q, prec;
+};
+
+}  // namespace lc
+
+struct lc_plan_s {
+    int kind = LC_PLAN_SINGLE;
+    int device = 0;
+    lc::FnDesc fn{};
+    // device buffers (single plans)
+    double *x = nullptr;      // [H][Q] nodes
+    double *w = nullptr;      // [Q] folded Gauss weights
+    double *omt2 = nullptr;   // [Q] 1 - t_q^2
+    double *s2 = nullptr;     // [H] 2 sin(y_j / 2)
+    double2 *tw_pre = nullptr, *tw_pack = nullptr, *tw_fft = nullptr;
+    double *phi = nullptr;    // [H] workspace
+    double2 *zA = nullptr, *zB = nullptr;  // [L] four-step workspace
+    lc::QuadCfg quad{};
+    lc::DstCfg dst{};
+    bool fused_small = false;
+    int fused_threads = 256;
+    int64_t workspace_bytes = 0;
+    // timing of the dominant kernel
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pairs
+    int ev_used = 0;
+    // batch and GEMM plans keep their own state here
+    void *ext = nullptr;
+};
+
+namespace lc {
+
+// --- launchers (kernels_single.hip) ---------------------------------------
+hipError_t launch_nodes(int64_t H, int Q, const double *omt2, double *x, double *s2,
+                        hipStream_t s);
+hipError_t launch_quad(const QuadCfg &cfg, int prec, const void *f, const double *w,
+                       const double *s2, int64_t rows, int Q, double *phi, hipStream_t s);
+hipError_t launch_dst(const DstCfg &cfg, const double *phi, int64_t H, int64_t L, int64_t N,
+                      const double2 *tw_pre, const double2 *tw_pack, const double2 *tw_fft,
+                      double2 *zA, double2 *zB, double *c, hipStream_t s);
+hipError_t launch_fused_small(int threads, int prec, const void *f, const double *w,
+                              const double *s2, int64_t H, int Q, int64_t N, const FftSched &sch,
+                              const double2 *tw_pre, const double2 *tw_pack,
+                              const double2 *tw_fft, double *c, hipStream_t s);
+bool quad_cfg_supported(const QuadCfg &cfg, int prec, int Q);
+size_t fused_small_lds_bytes(int64_t H, int Q);
+
+// --- host helpers (host.cpp) ---------------------------------------------
+void set_error(const std::string &msg);
+int64_t smooth_len_at_least(int64_t L);           // smallest 2^a 3^b >= L
+FftSched make_sched(int L, const int *order = nullptr);
+void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w,
+                     std::vector<double> &omt2);
+void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack,
+              std::vector<double2> &fft);
+QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu);
+DstCfg default_dst_cfg(int64_t L);
+int device_cu_count();
+
+}  // namespace lc

@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+that include/lc.h declares, reports statuses, applies its grid-size rule and
+rejects invalid arguments before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "lc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lc_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1106_0463_amd as lc
+    return lc.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_symbols()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_every_symbol():
+    from paper_1106_0463_amd._lib import SIGNATURES
+    assert sorted(n for n, _, _ in SIGNATURES) == _declared_symbols()
+
+
+def test_status_strings(lib):
+    for s in range(6):
+        assert lib.lc_status_string(s).decode().startswith("LC_")
+
+
+def _smooth_at_least(L):
+    best = None
+    p3 = 1
+    while True:
+        v = p3
+        while v < L:
+            v *= 2
+        best = v if best is None else min(best, v)
+        if p3 > L:
+            break
+        p3 *= 3
+    return best
+
+
+@pytest.mark.parametrize("M", [2, 4, 6, 256, 300, 1200, 4 * 257, 4 * 8191, 262144, 4 * 3001, 10**6])
+def test_grid_size_rule(M):
+    import paper_1106_0463_amd as lc
+    Me = lc.grid_size(M)
+    L = Me // 4
+    assert Me >= M and Me % 4 == 0
+    assert L == _smooth_at_least(max(1, -(-max(M, 4) // 4)))
+    n = L
+    while n % 2 == 0:
+        n //= 2
+    while n % 3 == 0:
+        n //= 3
+    assert n == 1
+
+
+@pytest.mark.parametrize("args", [(0, 256, 32), (200, 256, 32), (8, 255, 32), (8, 256, 0),
+                                  (8, 256, 70000), (8, 0, 4)])
+def test_plan_rejects_invalid(args):
+    import paper_1106_0463_amd as lc
+    with pytest.raises(lc.LCError) as ei:
+        lc.plan(*args)
+    assert ei.value.status == 1
+
+
+def test_null_arguments_rejected(lib):
+    assert lib.lc_plan(8, 256, 32, 0, None) == 1
+    assert lib.lc_execute(None, None, None, None) == 1
+    assert lib.lc_plan_info(None, None) == 1
+    assert lib.lc_plan_destroy(None) == 0
+    assert "null" in lib.lc_last_error().decode() or lib.lc_last_error().decode() != ""
+    assert lib.lc_grid_size(1, C.byref(C.c_int64())) == 1

@@ -1,0 +1,143 @@
+"""GPU parity of the single-function path against the CPU oracle.
+
+Tolerance (FP64 class): max |c_gpu - c_oracle| <= 1e-12 * max |c_oracle|.
+Against the method oracle at the same (N, M_eff, Q) the difference is pure
+rounding; against the definition oracle it also contains the discretization
+error, so those cases use (M, Q) that resolve f."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import banner, expected_grid, rel_err
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lc():
+    import torch
+    import paper_1106_0463_amd as lc
+    torch.cuda.set_device(0)
+    return lc
+
+
+def run_gpu(lc, f, N, M, Q, precision="fp64"):
+    import torch
+    p = lc.plan(N, M, Q, precision)
+    x = p.nodes
+    fx = f.torch(x).contiguous()
+    if precision == "fp32":
+        fx = fx.float().contiguous()
+    c = p.execute(fx)
+    torch.cuda.synchronize()
+    info = p.info
+    out = c.cpu().numpy()
+    p.destroy()
+    return out, info
+
+
+@pytest.mark.parametrize("wl", W.single_small(), ids=lambda w: w.name)
+def test_small_workload_vs_oracles(lc, wl):
+    banner(f"[gpu] small workload {wl.name} N={wl.N} M={wl.M} Q={wl.Q}")
+    got, info = run_gpu(lc, wl.f, wl.N, wl.M, wl.Q)
+    assert info["M_eff"] == expected_grid(wl.M) == wl.M
+    cm = np.array(oracle.method_coeffs(wl.f, wl.N, wl.M, wl.Q), dtype=float)
+    cd = np.array(oracle.legendre_coeffs(wl.f, wl.N, 128), dtype=float)
+    assert rel_err(got, cm) <= TOL
+    assert rel_err(got, cd) <= TOL
+    if wl.name.startswith("genfn"):
+        assert np.max(np.abs(got - 0.5 ** np.arange(wl.N))) <= TOL
+
+
+# (N, M, Q): several FFT tiles and ragged tails; odd Q exercises the generic
+# quadrature kernel, L > 8192 the four-step FFT.
+CASES = [(100, 300, 17), (1000, 2400, 48), (4096, 8192, 64), (3000, 12000, 40),
+         (5000, 40000, 33), (700, 82000, 12), (8192, 16384, 32), (1, 2, 1), (2, 4, 3)]
+
+
+@pytest.mark.parametrize("N,M,Q", CASES)
+def test_method_parity_sizes(lc, N, M, Q):
+    banner(f"[gpu] method parity N={N} M={M} Q={Q}")
+    f = W.Sum(W.Exponential(0.7), W.GeneratingFunction(0.6))
+    got, info = run_gpu(lc, f, N, M, Q)
+    Me = expected_grid(M)
+    assert info["M_eff"] == Me and info["H"] == Me // 2
+    cm = np.array(oracle.method_coeffs(f, N, Me, Q), dtype=float)
+    assert rel_err(got, cm) <= TOL, (N, M, Q)
+
+
+@pytest.mark.parametrize("m", [0, 1, 7, 63, 200])
+def test_legendre_polynomial_delta(lc, m):
+    # f = P_m, resolving Q and M: c = delta_{nm} (pins nodes, weights, twist
+    # and DST end to end)
+    banner(f"[gpu] P_{m} delta")
+    cm = np.zeros(m + 1)
+    cm[m] = 1.0
+    f = W.LegendreSeries(cm)
+
+    class F:
+        def torch(self, x):
+            import torch
+            return torch.from_numpy(f(x.cpu().numpy())).to(x.device)
+    N = 256
+    got, _ = run_gpu(lc, F(), N, 2 * (N + m + 2), m // 2 + 2)
+    e = np.zeros(N)
+    e[m] = 1.0
+    assert np.max(np.abs(got - e)) <= TOL
+
+
+def test_nodes_match_oracle_grid(lc):
+    import torch
+    N, M, Q = 64, 256, 32
+    p = lc.plan(N, M, Q)
+    x = p.nodes.cpu().numpy().astype(np.longdouble)
+    H = M // 2
+    y = np.pi * np.arange(1, H + 1, dtype=np.longdouble) / H
+    T, _ = oracle.gauss_legendre(2 * Q)
+    tpos = np.sort(T[T > 0])
+    cy = np.cos(y)
+    ref = cy[:, None] + (1 - cy)[:, None] * tpos[None, :] ** 2
+    # the library's row order of t is its own; compare sorted rows
+    assert np.max(np.abs(np.sort(x, axis=1) - np.sort(ref, axis=1))) < 4e-16
+    p.destroy()
+
+
+def test_fp32_samples_mixed_class(lc):
+    # FP32 samples: a_n = c_n/(2n+1) within 1e-7 of the FP64 oracle (relative
+    # to max |a|)
+    N, M, Q = 2048, 8192, 48
+    f = W.Sum(W.Exponential(-2.0), W.GeneratingFunction(0.8))
+    got, _ = run_gpu(lc, f, N, M, Q, "fp32")
+    cd = np.array(oracle.legendre_coeffs(f, N, 2048 + 512), dtype=float)
+    n = np.arange(N)
+    assert rel_err(got / (2 * n + 1), cd / (2 * n + 1)) <= 1e-7
+
+
+def test_deterministic_repeat(lc):
+    import torch
+    N, M, Q = 4096, 16384, 48
+    f = W.Exponential(3.0)
+    p = lc.plan(N, M, Q)
+    fx = f.torch(p.nodes).contiguous()
+    a = p.execute(fx).clone()
+    b = p.execute(fx).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    p.destroy()
+
+
+def test_table1_abs_pow_error_level(lc):
+    # |x|^{3/2}: Table 1's True column; the global rule converges slowly at the
+    # kink x = 0 (the paper's own errors are 7e-13 .. 1.6e-9), so this checks
+    # the computed values lie within 1e-6 and improve with Q.
+    import os
+    from closed_forms import load_table1
+    ns, vals = load_table1(os.path.join(os.path.dirname(__file__), "golden", "table1_abs_x_3_2.txt"))
+    errs = []
+    for Q in (64, 512):
+        got, _ = run_gpu(lc, W.AbsPower(1.5), 32, 4096, Q)
+        errs.append(max(abs(got[n] - float(v)) for n, v in zip(ns, vals)))
+    assert errs[1] < errs[0] < 1e-5
+    assert errs[1] < 1e-7
