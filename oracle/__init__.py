@@ -23,6 +23,6 @@ from ._lib import build, load, threads  # noqa: F401
 from .definition import (gauss_legendre, legendre_coeffs,  # noqa: F401
                          legendre_coeffs_from_samples,
                          legendre_coeffs_piecewise, legendre_eval)
-from .method import (abel_fhat, abel_phi, coeffs_from_fhat,  # noqa: F401
+from .method import (abel_fhat, abel_nodes, abel_phi, coeffs_from_fhat,  # noqa: F401
                      fhat_from_phi, fourier_coeffs, fourier_coeffs_at,
-                     method_coeffs, method_coeffs_at, y_grid)
+                     method_coeffs, method_coeffs_at, positive_half_samples, y_grid)

@@ -37,21 +37,34 @@ LD = np.longdouble
 PI = LD("3.141592653589793238462643383279502884")
 
 
-def abel_phi(f, y: np.ndarray, Q: int, chunk: int = 2048) -> np.ndarray:
+def abel_nodes(y: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """Abel nodes x = cos y + (1 - cos y) T^2 for each y (rows) and each
+    Gauss node T (columns), long double."""
+    y = np.asarray(y, dtype=LD)
+    cy = np.cos(y)
+    L = 1 - cy                              # length of [cos y, 1]
+    return cy[:, None] + L[:, None] * (np.asarray(T, dtype=LD)[None, :] ** 2)
+
+
+def abel_phi(f, y: np.ndarray, Q: int, chunk: int = 2048, fp64_nodes: bool = False) -> np.ndarray:
     """phi(y) of eq. (2.14) for y in [-pi, pi] (even in y), with the
     (2Q)-point Gauss-Legendre rule after x = cos y + (1 - cos y) t^2
-    (evaluated in blocks of ``chunk`` y values to bound memory)."""
+    (evaluated in blocks of ``chunk`` y values to bound memory).
+
+    fp64_nodes=True rounds every node to the nearest FP64 value before f is
+    evaluated (in long double) there: the samples an FP64 caller provides.
+    """
     y = np.asarray(y, dtype=LD)
     T, W = gauss_legendre(2 * int(Q))
     out = np.empty(y.shape, dtype=LD)
     for a in range(0, y.size, chunk):
         yy = y[a:a + chunk]
-        cy = np.cos(yy)
-        L = 1 - cy                              # length of [cos y, 1]
-        x = cy[:, None] + L[:, None] * (T[None, :] ** 2)
+        x = abel_nodes(yy, T)
+        if fp64_nodes:
+            x = x.astype(np.float64).astype(LD)
         fx = np.asarray(f(x), dtype=LD)
         integral = LD(0.5) * (fx * W[None, :]).sum(axis=1)
-        out[a:a + chunk] = np.sqrt(2 * L) * integral
+        out[a:a + chunk] = np.sqrt(2 * (1 - np.cos(yy))) * integral
     return out
 
 
@@ -65,10 +78,10 @@ def fhat_from_phi(phi_abs_y: np.ndarray, y: np.ndarray) -> np.ndarray:
     return (-1j) * mag * (np.cos(y / 2) + 1j * np.sin(y / 2))
 
 
-def abel_fhat(f, y: np.ndarray, Q: int) -> np.ndarray:
+def abel_fhat(f, y: np.ndarray, Q: int, fp64_nodes: bool = False) -> np.ndarray:
     """fhat(y) of eq. (2.5) with phi from :func:`abel_phi`."""
     y = np.asarray(y, dtype=LD)
-    return fhat_from_phi(abel_phi(f, np.abs(y), Q), y)
+    return fhat_from_phi(abel_phi(f, np.abs(y), Q, fp64_nodes=fp64_nodes), y)
 
 
 def fourier_coeffs(fhat_vals: np.ndarray, N: int) -> np.ndarray:
@@ -103,13 +116,30 @@ def fourier_coeffs_at(fhat_vals: np.ndarray, idx) -> np.ndarray:
     return a_re + 1j * a_im
 
 
-def method_coeffs_at(f, idx, M: int, Q: int) -> np.ndarray:
+def method_coeffs_at(f, idx, M: int, Q: int, fp64_nodes: bool = False) -> np.ndarray:
     """:func:`method_coeffs` evaluated only at the indices ``idx``."""
     y = y_grid(M)
-    fh = abel_fhat(f, y, Q)
+    fh = abel_fhat(f, y, Q, fp64_nodes)
     a = fourier_coeffs_at(fh, idx)
     n = np.asarray(idx, dtype=LD)
     return (2 * n + 1) * a.real
+
+
+def positive_half_samples(f, M: int, Q: int) -> np.ndarray:
+    """Samples f(x) at the FP64-rounded Abel nodes of the positive half of
+    the grid, y = pi j / (M/2), j = 1..M/2 (rows), and the positive Gauss
+    nodes in decreasing order (columns): the [M/2][Q] layout an FP64 caller
+    hands to a single-function execution.  Uses the same grid values and
+    nodes as :func:`method_coeffs` with ``fp64_nodes=True``."""
+    H = int(M) // 2
+    yg = np.abs(y_grid(M))
+    y = np.concatenate([yg[H + 1:], yg[:1]])   # pi j / H for j = 1..H-1, then pi
+    T, _ = gauss_legendre(2 * int(Q))
+    out = np.empty((H, int(Q)), dtype=np.float64)
+    for a in range(0, H, 2048):
+        x = abel_nodes(y[a:a + 2048], T[:int(Q)]).astype(np.float64).astype(LD)
+        out[a:a + 2048] = np.asarray(f(x), dtype=LD).astype(np.float64)
+    return out
 
 
 def y_grid(M: int) -> np.ndarray:
@@ -128,7 +158,8 @@ def coeffs_from_fhat(fhat_vals: np.ndarray, N: int, return_imag: bool = False):
     return c
 
 
-def method_coeffs(f, N: int, M: int, Q: int, return_imag: bool = False):
+def method_coeffs(f, N: int, M: int, Q: int, return_imag: bool = False,
+                  fp64_nodes: bool = False):
     """c_0..c_{N-1} by the paper's method with an M-point y-grid and the
     (2Q)-point Gauss-Legendre rule for the Abel integral.
 
@@ -138,5 +169,5 @@ def method_coeffs(f, N: int, M: int, Q: int, return_imag: bool = False):
     request as a consistency check.
     """
     y = y_grid(M)
-    fh = abel_fhat(f, y, Q)
+    fh = abel_fhat(f, y, Q, fp64_nodes)
     return coeffs_from_fhat(fh, N, return_imag)

@@ -49,7 +49,7 @@ class _DevArray:
         self._owner = owner
         self.__cuda_array_interface__ = {
             "shape": tuple(int(s) for s in shape), "typestr": typestr,
-            "data": (int(ptr), True), "version": 2, "strides": None}
+            "data": (int(ptr), False), "version": 2, "strides": None}
 
 
 def _view(ptr: int, shape, owner, dtype="float64"):

@@ -96,11 +96,16 @@ static void legendre_and_derivative(int n, long double x, long double &pn, long 
     dpn = (long double)n * (x * pk - pkm1) / (x * x - 1.0L);
 }
 
-void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w, std::vector<double> &omt2) {
+static double2 dd_split(long double v) {
+    const double hi = (double)v;
+    return make_double2(hi, (double)(v - (long double)hi));
+}
+
+void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w, std::vector<double2> &omt2) {
     const int n = 2 * Q;
     t.assign(Q, 0.0);
     w.assign(Q, 0.0);
-    omt2.assign(Q, 0.0);
+    omt2.assign(Q, make_double2(0.0, 0.0));
     const long double PI = 3.141592653589793238462643383279502884L;
     auto work = [&](int i0, int i1) {
         for (int i = i0; i < i1; ++i) {
@@ -118,7 +123,7 @@ void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w, std:
             legendre_and_derivative(n, x, p, dp);
             t[i] = (double)x;
             w[i] = (double)(2.0L / ((1.0L - x * x) * dp * dp));
-            omt2[i] = (double)((1.0L - x) * (1.0L + x));
+            omt2[i] = dd_split((1.0L - x) * (1.0L + x));
         }
     };
     const long long cost = (long long)Q * n;
@@ -172,6 +177,21 @@ void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack, 
     for (int64_t k = 0; k < H; ++k) sincos_turns(k, 4 * H, &pre[k].x, &pre[k].y);
     for (int64_t k = 0; k < L; ++k) sincos_turns(k, H, &pack[k].x, &pack[k].y);
     for (int64_t k = 0; k < L; ++k) sincos_turns(k, L, &fft[k].x, &fft[k].y);
+}
+
+// Row factors of the node formula: A_j = 2 sin^2(pi j / (2H)) as a
+// double-double pair, and 2 sin(pi j / (2H)) (the Abel Jacobian), j = 1..H.
+void row_factors(int64_t H, std::vector<double2> &A, std::vector<double> &s2) {
+    const long double HALF_PI = 1.570796326794896619231321691639751442L;
+    A.resize(H);
+    s2.resize(H);
+    for (int64_t r = 0; r < H; ++r) {
+        const int64_t j = r + 1;                      // angle y/2 = (pi/2) j / H
+        const long double sj = (2 * j <= H) ? sinl(HALF_PI * (long double)j / (long double)H)
+                                            : cosl(HALF_PI * (long double)(H - j) / (long double)H);
+        A[r] = dd_split(2.0L * sj * sj);
+        s2[r] = (double)(2.0L * sj);
+    }
 }
 
 // -------------------------------------------------- launch configs ---
@@ -282,6 +302,7 @@ static void free_single(lc_plan_s *p) {
     hipFree(p->x);
     hipFree(p->w);
     hipFree(p->omt2);
+    hipFree(p->rowA);
     hipFree(p->s2);
     hipFree(p->tw_pre);
     hipFree(p->tw_pack);
@@ -342,8 +363,10 @@ lc_status lc_plan(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t 
     p->fn.Q = Q;
     p->fn.prec = (int)prec;
 
-    std::vector<double> t, w, omt2;
+    std::vector<double> t, w, s2h;
+    std::vector<double2> omt2, rowA;
     gauss_half_rule(Q, t, w, omt2);
+    row_factors(H, rowA, s2h);
     std::vector<double2> pre, pack, fft;
     twiddles(H, pre, pack, fft);
 
@@ -353,6 +376,7 @@ lc_status lc_plan(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t 
     chk(dalloc(&p->x, (size_t)H * Q, &ws));
     chk(dalloc(&p->w, (size_t)Q, &ws));
     chk(dalloc(&p->omt2, (size_t)Q, &ws));
+    chk(dalloc(&p->rowA, (size_t)H, &ws));
     chk(dalloc(&p->s2, (size_t)H, &ws));
     chk(dalloc(&p->tw_pre, (size_t)H, &ws));
     chk(dalloc(&p->tw_pack, (size_t)L, &ws));
@@ -370,11 +394,13 @@ lc_status lc_plan(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t 
     }
     p->workspace_bytes = ws;
     chk(hipMemcpy(p->w, w.data(), Q * sizeof(double), hipMemcpyHostToDevice));
-    chk(hipMemcpy(p->omt2, omt2.data(), Q * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(p->omt2, omt2.data(), Q * sizeof(double2), hipMemcpyHostToDevice));
+    chk(hipMemcpy(p->rowA, rowA.data(), H * sizeof(double2), hipMemcpyHostToDevice));
+    chk(hipMemcpy(p->s2, s2h.data(), H * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemcpy(p->tw_pre, pre.data(), H * sizeof(double2), hipMemcpyHostToDevice));
     chk(hipMemcpy(p->tw_pack, pack.data(), L * sizeof(double2), hipMemcpyHostToDevice));
     chk(hipMemcpy(p->tw_fft, fft.data(), L * sizeof(double2), hipMemcpyHostToDevice));
-    if (e == hipSuccess) chk(launch_nodes(H, Q, p->omt2, p->x, p->s2, 0));
+    if (e == hipSuccess) chk(launch_nodes(H, Q, p->rowA, p->omt2, p->x, 0));
     if (e == hipSuccess) chk(hipDeviceSynchronize());
     if (e != hipSuccess) {
         free_single(p);

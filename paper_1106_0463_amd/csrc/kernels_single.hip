@@ -11,27 +11,38 @@
 namespace lc {
 
 // ---------------------------------------------------------------- nodes ---
-// Row r (r = 0..H-1) is y_j = pi j / H with j = r + 1; s_j = sin(y_j / 2)
-// = sinpi(j / (2H)).  The half-angle form keeps 1 - x = 2 s^2 (1 - t^2)
-// accurate near y = 0 (no cancellation in cos y).
-__global__ __launch_bounds__(256) void k_nodes(int64_t H, int Q, const double *__restrict__ omt2,
-                                               double *__restrict__ x, double *__restrict__ s2) {
+// Row r (r = 0..H-1) is y_j = pi j / H with j = r + 1, column q the q-th
+// largest positive Gauss node t_q.  x_{jq} = 1 - A_j B_q with
+// A_j = 2 sin^2(y_j / 2) and B_q = 1 - t_q^2 (the half-angle form: no
+// cancellation in cos y near y = 0), both given as double-double pairs
+// (hi + lo, from long-double host values).  The product and the
+// subtraction are carried out in double-double with FMA, so x is the FP64
+// value nearest the exact node in all but rare half-way cases.
+__global__ __launch_bounds__(256) void k_nodes(int64_t H, int Q, const double2 *__restrict__ A,
+                                               const double2 *__restrict__ B, double *__restrict__ x) {
+    // the error-free transformations below must not be contracted into FMAs
+#pragma clang fp contract(off)
     const int64_t total = H * (int64_t)Q;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = idx / Q;
         const int q = (int)(idx - r * Q);
-        const double s = sinpi((double)(r + 1) / (double)(2 * H));
-        x[idx] = fma(-2.0 * (s * s), omt2[q], 1.0);
-        if (q == 0) s2[r] = 2.0 * s;
+        const double2 a = A[r], b = B[q];
+        const double p = a.x * b.x;
+        double e = fma(a.x, b.x, -p);                 // exact low part of a.x b.x
+        e = fma(a.x, b.y, fma(a.y, b.x, e));          // + cross terms
+        const double s = 1.0 - p;                     // two-sum(1, -p)
+        const double bb = s - 1.0;
+        const double err = (1.0 - (s - bb)) + (-p - bb);
+        x[idx] = s + (err - e);
     }
 }
 
-hipError_t launch_nodes(int64_t H, int Q, const double *omt2, double *x, double *s2, hipStream_t s) {
+hipError_t launch_nodes(int64_t H, int Q, const double2 *A, const double2 *B, double *x, hipStream_t s) {
     const int64_t total = H * (int64_t)Q;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_nodes, dim3((unsigned)blocks), dim3(256), 0, s, H, Q, omt2, x, s2);
+    hipLaunchKernelGGL(k_nodes, dim3((unsigned)blocks), dim3(256), 0, s, H, Q, A, B, x);
     return hipGetLastError();
 }
 
@@ -375,9 +386,12 @@ hipError_t launch_dst(const DstCfg &cfg, const double *phi, int64_t H, int64_t L
     // four-step through global memory (256 threads, <= 2048 elements per block)
     const int L1 = cfg.L1, L2 = cfg.L2;
     if ((int64_t)L1 * L2 != L || L1 > 2048 || L2 > 2048) return hipErrorInvalidValue;
-    const int CB = (2048 / L1) < L2 ? (2048 / L1) : L2;
-    const int RB = (2048 / L2) < L1 ? (2048 / L2) : L1;
-    if (L2 % CB || L1 % RB) return hipErrorInvalidValue;
+    // columns (rows) per block: the largest divisor of L2 (L1) that fits
+    int CB = 2048 / L1 < L2 ? 2048 / L1 : L2;
+    while (CB > 1 && L2 % CB) --CB;
+    int RB = 2048 / L2 < L1 ? 2048 / L2 : L1;
+    while (RB > 1 && L1 % RB) --RB;
+    if (CB < 1 || RB < 1 || CB * L1 > 2048 || RB * L2 > 2048) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fft_cols<256>, dim3(L2 / CB), dim3(256), (size_t)CB * L1 * sizeof(double2), s, phi, H,
                        L1, L2, CB, cfg.s1, tw_pre, tw_pack, tw_fft, zA);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -71,7 +71,8 @@ struct lc_plan_s {
     // device buffers (single plans)
     double *x = nullptr;      // [H][Q] nodes
     double *w = nullptr;      // [Q] folded Gauss weights
-    double *omt2 = nullptr;   // [Q] 1 - t_q^2
+    double2 *omt2 = nullptr;  // [Q] 1 - t_q^2 (double-double)
+    double2 *rowA = nullptr;  // [H] 2 sin^2(y_j/2) (double-double)
     double *s2 = nullptr;     // [H] 2 sin(y_j / 2)
     double2 *tw_pre = nullptr, *tw_pack = nullptr, *tw_fft = nullptr;
     double *phi = nullptr;    // [H] workspace
@@ -92,7 +93,7 @@ struct lc_plan_s {
 namespace lc {
 
 // --- launchers (kernels_single.hip) ---------------------------------------
-hipError_t launch_nodes(int64_t H, int Q, const double *omt2, double *x, double *s2,
+hipError_t launch_nodes(int64_t H, int Q, const double2 *A, const double2 *B, double *x,
                         hipStream_t s);
 hipError_t launch_quad(const QuadCfg &cfg, int prec, const void *f, const double *w,
                        const double *s2, int64_t rows, int Q, double *phi, hipStream_t s);
@@ -111,7 +112,8 @@ void set_error(const std::string &msg);
 int64_t smooth_len_at_least(int64_t L);           // smallest 2^a 3^b >= L
 FftSched make_sched(int L, const int *order = nullptr);
 void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w,
-                     std::vector<double> &omt2);
+                     std::vector<double2> &omt2);
+void row_factors(int64_t H, std::vector<double2> &A, std::vector<double> &s2);
 void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack,
               std::vector<double2> &fft);
 QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu);

@@ -37,10 +37,22 @@ def _gpu(Q):
 
 
 def test_large_stated_q_method_parity():
+    # Samples at the oracle's own FP64-rounded nodes go to both sides, so the
+    # comparison is arithmetic only (sampling cos(16384 x) at nodes that
+    # differ by one ulp moves c_n by up to ~1e-12 max|c| by itself).
+    import torch
+    import paper_1106_0463_amd as lc
     banner("[gpu] large single function, stated Q=64, method oracle on 512 indices")
-    wl, got = _gpu(64)
+    torch.cuda.set_device(0)
+    wl = W.single_large(Q=64)
+    fx = torch.from_numpy(oracle.positive_half_samples(wl.f, wl.M, 64)).cuda().contiguous()
+    p = lc.plan(wl.N, wl.M, 64)
+    c = p.execute(fx)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy()
+    p.destroy()
     idx = W.subset_indices()
-    ref = np.array(oracle.method_coeffs_at(wl.f, idx, wl.M, 64), dtype=float)
+    ref = np.array(oracle.method_coeffs_at(wl.f, idx, wl.M, 64, fp64_nodes=True), dtype=float)
     scale = np.max(np.abs(ref))
     err = np.max(np.abs(got[idx] - ref)) / scale
     banner(f"    rel err {err:.3e} (max|c| on subset {scale:.3f})")
