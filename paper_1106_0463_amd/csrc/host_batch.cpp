@@ -1,0 +1,405 @@
+// Batched plans: B independent functions of uneven N/M/Q/precision.
+//
+// Layout: one sample arena (per function [H_b][Q_b] FP64 or FP32 at a
+// 256-byte aligned byte offset), one node arena (per function [H_b][Q_b]
+// FP64), one coefficient arena (N_b doubles each, packed) and a phi
+// workspace arena (H_b doubles each).  Gauss rules are shared by all
+// functions with the same Q, twiddles and row factors by all functions with
+// the same H.
+//
+// Execution: the Abel quadrature reduction of every function runs as one
+// launch per (Q, precision) class over a table of row tiles (each tile a run
+// of rows of one function), then one LDS DST launch per FFT-length class
+// (one workgroup per function, longest first), then the four-step DST for
+// the few functions whose FFT exceeds the LDS.  The sequence is captured
+// once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lc_internal.h"
+
+namespace lc {
+
+lc_status fail_status(lc_status s, const std::string &msg);
+lc_status validate_request(int64_t N, int64_t M, int32_t Q, int prec, const char *who);
+hipError_t timing_begin(lc_plan_s *p, hipStream_t s, int *slot);
+hipError_t timing_end(lc_plan_s *p, hipStream_t s, int slot);
+
+namespace {
+
+struct HSet {
+    int64_t H = 0, L = 0;
+    double *s2 = nullptr;
+    double2 *rowA = nullptr, *tw_pre = nullptr, *tw_pack = nullptr, *tw_fft = nullptr;
+    DstCfg dcfg{};
+};
+struct QSet {
+    int Q = 0;
+    double *w = nullptr;
+    double2 *omt2 = nullptr;
+};
+struct QuadClass {
+    int Q = 0, prec = 0;
+    QuadCfg cfg{};
+    double *w = nullptr;
+    BatchTile *tiles = nullptr;
+    int ntiles = 0;
+    int64_t rows = 0;
+};
+struct DstGroup {
+    int threads = 0, Lmax = 0, n = 0;
+    int32_t *list = nullptr;
+};
+
+struct BatchState {
+    int B = 0;
+    std::vector<FnDesc> fn;
+    BatchFn *dfn = nullptr;
+    std::map<int64_t, HSet> hs;
+    std::map<int, QSet> qs;
+    std::vector<QuadClass> classes;
+    std::vector<DstGroup> groups;
+    std::vector<int> large;
+    double *x_arena = nullptr, *phi_arena = nullptr;
+    double2 *zA = nullptr, *zB = nullptr;
+    int64_t f_bytes = 0, x_elems = 0, c_elems = 0, phi_elems = 0, ws_bytes = 0;
+    std::vector<void *> allocs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void *gf = nullptr;
+    double *gc = nullptr;
+    hipStream_t gs = nullptr;
+};
+
+template <typename T>
+hipError_t balloc(BatchState *st, T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e == hipSuccess) {
+        st->allocs.push_back(*p);
+        st->ws_bytes += (int64_t)(n * sizeof(T));
+    }
+    return e;
+}
+
+template <typename T>
+hipError_t upload(BatchState *st, T **p, const std::vector<T> &v) {
+    hipError_t e = balloc(st, p, v.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_state(BatchState *st) {
+    if (!st) return;
+    if (st->gexec) hipGraphExecDestroy(st->gexec);
+    if (st->graph) hipGraphDestroy(st->graph);
+    for (void *p : st->allocs) hipFree(p);
+    delete st;
+}
+
+hipError_t launch_all(lc_plan_s *p, BatchState *st, const void *f_arena, double *c_arena, hipStream_t s,
+                      bool timed) {
+    hipError_t e;
+    int slot = -1;
+    if (timed && (e = timing_begin(p, s, &slot)) != hipSuccess) return e;
+    for (auto &qc : st->classes) {
+        e = launch_bquad(qc.cfg, qc.prec, f_arena, qc.w, qc.tiles, qc.ntiles, st->dfn, st->phi_arena, s);
+        if (e != hipSuccess) return e;
+    }
+    if (timed && (e = timing_end(p, s, slot)) != hipSuccess) return e;
+    for (auto &g : st->groups) {
+        e = launch_bdst(g.threads, g.Lmax, st->phi_arena, st->dfn, g.list, g.n, c_arena, s);
+        if (e != hipSuccess) return e;
+    }
+    for (int b : st->large) {
+        const FnDesc &d = st->fn[b];
+        const HSet &h = st->hs.at(d.H);
+        e = launch_dst(h.dcfg, st->phi_arena + d.phi_off, d.H, d.L, d.N, h.tw_pre, h.tw_pack, h.tw_fft, st->zA,
+                       st->zB, c_arena + d.c_off, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+void destroy_batch(lc_plan_s *p) {
+    free_state((BatchState *)p->ext);
+    p->ext = nullptr;
+}
+
+void info_batch(lc_plan_s *p, lc_plan_desc *d) {
+    BatchState *st = (BatchState *)p->ext;
+    d->B = st->B;
+    int64_t samples = 0, N = 0;
+    for (auto &f : st->fn) {
+        samples += f.H * f.Q;
+        N += f.N;
+    }
+    d->N = N;
+    d->samples = samples;
+    d->sample_bytes = st->f_bytes;
+    d->workspace_bytes = st->ws_bytes;
+}
+
+lc_status nodes_batch(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q) {
+    BatchState *st = (BatchState *)p->ext;
+    *x = st->x_arena;
+    if (rows) *rows = st->x_elems;
+    if (Q) *Q = 0;
+    return LC_OK;
+}
+
+}  // namespace lc
+
+using namespace lc;
+
+extern "C" {
+
+lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int32_t *Q, const lc_precision *prec,
+                        lc_plan_t *out) {
+    if (!out || !N || !M || !Q || !prec) return fail_status(LC_ERR_INVALID, "lc_plan_batch: null argument");
+    if (B < 1) return fail_status(LC_ERR_INVALID, "lc_plan_batch: B must be >= 1");
+    for (int b = 0; b < B; ++b) {
+        char who[64];
+        snprintf(who, sizeof who, "lc_plan_batch[%d]", b);
+        lc_status s = validate_request(N[b], M[b], Q[b], (int)prec[b], who);
+        if (s != LC_OK) return s;
+    }
+    BatchState *st = new (std::nothrow) BatchState();
+    if (!st) return fail_status(LC_ERR_NOMEM, "lc_plan_batch: host allocation failed");
+    st->B = B;
+    st->fn.resize(B);
+    const int cu = device_cu_count();
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+
+    // ---- sizes and offsets
+    int64_t foff = 0, xoff = 0, coff = 0, poff = 0;
+    for (int b = 0; b < B; ++b) {
+        FnDesc &d = st->fn[b];
+        int64_t Me = 0;
+        lc_grid_size(M[b], &Me);
+        d.N = N[b];
+        d.M = M[b];
+        d.M_eff = Me;
+        d.H = Me / 2;
+        d.L = d.H / 2;
+        d.Q = Q[b];
+        d.prec = (int)prec[b];
+        const int esz = d.prec == LC_FP64 ? 8 : 4;
+        d.f_off = foff;
+        foff += (d.H * d.Q * esz + 255) / 256 * 256;
+        d.x_off = xoff;
+        xoff += (d.H * d.Q + 31) / 32 * 32;
+        d.c_off = coff;
+        coff += d.N;
+        d.phi_off = poff;
+        poff += d.H;
+        if (d.L > kLdsFftMax && default_dst_cfg(d.L).L1 == 0) {
+            free_state(st);
+            return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_batch: an FFT length has no four-step split");
+        }
+    }
+    st->f_bytes = foff;
+    st->x_elems = xoff;
+    st->c_elems = coff;
+    st->phi_elems = poff;
+
+    // ---- shared tables
+    for (auto &d : st->fn) {
+        if (!st->hs.count(d.H)) {
+            HSet h;
+            h.H = d.H;
+            h.L = d.L;
+            std::vector<double2> pre, pack, fft, rowA;
+            std::vector<double> s2;
+            twiddles(d.H, pre, pack, fft);
+            row_factors(d.H, rowA, s2);
+            chk(upload(st, &h.tw_pre, pre));
+            chk(upload(st, &h.tw_pack, pack));
+            chk(upload(st, &h.tw_fft, fft));
+            chk(upload(st, &h.rowA, rowA));
+            chk(upload(st, &h.s2, s2));
+            h.dcfg = default_dst_cfg(d.L);
+            st->hs[d.H] = h;
+        }
+        if (!st->qs.count(d.Q)) {
+            QSet q;
+            q.Q = d.Q;
+            std::vector<double> t, w;
+            std::vector<double2> omt2;
+            gauss_half_rule(d.Q, t, w, omt2);
+            chk(upload(st, &q.w, w));
+            chk(upload(st, &q.omt2, omt2));
+            st->qs[d.Q] = q;
+        }
+    }
+    chk(balloc(st, &st->x_arena, (size_t)st->x_elems));
+    chk(balloc(st, &st->phi_arena, (size_t)st->phi_elems));
+    int64_t Lbig = 0;
+    for (int b = 0; b < B; ++b)
+        if (st->fn[b].L > kLdsFftMax) Lbig = std::max(Lbig, st->fn[b].L);
+    if (Lbig) {
+        chk(balloc(st, &st->zA, (size_t)Lbig));
+        chk(balloc(st, &st->zB, (size_t)Lbig));
+    }
+    if (e != hipSuccess) {
+        free_state(st);
+        return fail_status(e == hipErrorOutOfMemory ? LC_ERR_NOMEM : LC_ERR_HIP,
+                           std::string("lc_plan_batch: allocation/upload failed: ") + hipGetErrorString(e));
+    }
+    // ---- nodes
+    for (auto &d : st->fn) {
+        if (e != hipSuccess) break;
+        chk(launch_nodes(d.H, d.Q, st->hs[d.H].rowA, st->qs[d.Q].omt2, st->x_arena + d.x_off, 0));
+    }
+    chk(hipDeviceSynchronize());
+    // ---- device descriptors
+    std::vector<BatchFn> hfn(B);
+    for (int b = 0; b < B; ++b) {
+        const FnDesc &d = st->fn[b];
+        const HSet &h = st->hs[d.H];
+        BatchFn &f = hfn[b];
+        f.f_off = d.f_off;
+        f.phi_off = d.phi_off;
+        f.c_off = d.c_off;
+        f.N = d.N;
+        f.H = d.H;
+        f.L = d.L;
+        f.s2 = h.s2;
+        f.tw_pre = h.tw_pre;
+        f.tw_pack = h.tw_pack;
+        f.tw_fft = h.tw_fft;
+        if (d.L <= kLdsFftMax) f.sched = make_sched((int)d.L);
+    }
+    chk(upload(st, &st->dfn, hfn));
+    // ---- quadrature classes and their tiles
+    std::map<std::pair<int, int>, std::vector<int>> cls;
+    for (int b = 0; b < B; ++b) cls[{st->fn[b].Q, st->fn[b].prec}].push_back(b);
+    for (auto &kv : cls) {
+        QuadClass qc;
+        qc.Q = kv.first.first;
+        qc.prec = kv.first.second;
+        for (int b : kv.second) qc.rows += st->fn[b].H;
+        qc.cfg = default_quad_cfg(qc.prec, qc.Q, qc.rows, cu);
+        qc.cfg.Qv = qc.Q;
+        qc.w = st->qs[qc.Q].w;
+        const int rpt = quad_rows_per_block(qc.cfg);
+        std::vector<BatchTile> tiles;
+        for (int b : kv.second)
+            for (int64_t r = 0; r < st->fn[b].H; r += rpt)
+                tiles.push_back({b, (int32_t)r, (int32_t)std::min<int64_t>(rpt, st->fn[b].H - r), 0});
+        qc.ntiles = (int)tiles.size();
+        qc.cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>(qc.ntiles, (int64_t)cu * 8));
+        chk(upload(st, &qc.tiles, tiles));
+        st->classes.push_back(qc);
+    }
+    // ---- DST groups (one workgroup per function, longest first)
+    std::map<int, std::vector<int>> grp;
+    for (int b = 0; b < B; ++b) {
+        const int64_t L = st->fn[b].L;
+        if (L > kLdsFftMax) {
+            st->large.push_back(b);
+            continue;
+        }
+        grp[L <= 512 ? 64 : (L <= 2048 ? 256 : 1024)].push_back(b);
+    }
+    for (auto &kv : grp) {
+        DstGroup g;
+        g.threads = kv.first;
+        auto v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return st->fn[a].L > st->fn[b].L; });
+        g.Lmax = (int)st->fn[v[0]].L;
+        g.n = (int)v.size();
+        std::vector<int32_t> list(v.begin(), v.end());
+        chk(upload(st, &g.list, list));
+        chk(prepare_bdst(g.threads, g.Lmax));
+        st->groups.push_back(g);
+    }
+    if (e != hipSuccess) {
+        free_state(st);
+        return fail_status(LC_ERR_HIP, std::string("lc_plan_batch: setup failed: ") + hipGetErrorString(e));
+    }
+    lc_plan_s *p = new (std::nothrow) lc_plan_s();
+    if (!p) {
+        free_state(st);
+        return fail_status(LC_ERR_NOMEM, "lc_plan_batch: host allocation failed");
+    }
+    p->kind = LC_PLAN_BATCH;
+    hipGetDevice(&p->device);
+    p->ext = st;
+    p->workspace_bytes = st->ws_bytes;
+    *out = p;
+    return LC_OK;
+}
+
+lc_status lc_plan_batch_offsets(lc_plan_t p, int64_t *f_off, int64_t *x_off, int64_t *c_off) {
+    if (!p || p->kind != LC_PLAN_BATCH) return fail_status(LC_ERR_INVALID, "lc_plan_batch_offsets: not a batch plan");
+    BatchState *st = (BatchState *)p->ext;
+    for (int b = 0; b < st->B; ++b) {
+        if (f_off) f_off[b] = st->fn[b].f_off;
+        if (x_off) x_off[b] = st->fn[b].x_off;
+        if (c_off) c_off[b] = st->fn[b].c_off;
+    }
+    if (f_off) f_off[st->B] = st->f_bytes;
+    if (x_off) x_off[st->B] = st->x_elems;
+    if (c_off) c_off[st->B] = st->c_elems;
+    return LC_OK;
+}
+
+lc_status lc_execute_batch(lc_plan_t p, const void *f_arena, double *c_arena, hipStream_t stream) {
+    if (!p || p->kind != LC_PLAN_BATCH) return fail_status(LC_ERR_INVALID, "lc_execute_batch: not a batch plan");
+    if (!f_arena || !c_arena) return fail_status(LC_ERR_INVALID, "lc_execute_batch: null arena");
+    if (((uintptr_t)f_arena) & 255) return fail_status(LC_ERR_INVALID, "lc_execute_batch: f_arena must be 256-byte aligned");
+    BatchState *st = (BatchState *)p->ext;
+    hipError_t e;
+    // Timed executions and executions on the null stream run eagerly; every
+    // other execution replays the captured graph.
+    if (p->timing || stream == nullptr) {
+        e = launch_all(p, st, f_arena, c_arena, stream, p->timing);
+        if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_batch: ") + hipGetErrorString(e));
+        return LC_OK;
+    }
+    if (!st->gexec || st->gf != f_arena || st->gc != c_arena || st->gs != stream) {
+        if (st->gexec) {
+            hipGraphExecDestroy(st->gexec);
+            st->gexec = nullptr;
+        }
+        if (st->graph) {
+            hipGraphDestroy(st->graph);
+            st->graph = nullptr;
+        }
+        e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_batch: begin capture: ") + hipGetErrorString(e));
+        hipError_t el = launch_all(p, st, f_arena, c_arena, stream, false);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(stream, &g);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return fail_status(LC_ERR_HIP, std::string("lc_execute_batch: capture: ") +
+                                               hipGetErrorString(el != hipSuccess ? el : e));
+        }
+        st->graph = g;
+        e = hipGraphInstantiate(&st->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            st->gexec = nullptr;
+            return fail_status(LC_ERR_HIP, std::string("lc_execute_batch: instantiate: ") + hipGetErrorString(e));
+        }
+        st->gf = f_arena;
+        st->gc = c_arena;
+        st->gs = stream;
+    }
+    e = hipGraphLaunch(st->gexec, stream);
+    if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_batch: graph launch: ") + hipGetErrorString(e));
+    return LC_OK;
+}
+
+}  // extern "C"

@@ -3,24 +3,12 @@
 
 namespace lc {
 lc_status fail_status(lc_status s, const std::string &msg);
-void destroy_batch(lc_plan_s *) {}
 void destroy_gemm(lc_plan_s *) {}
-void info_batch(lc_plan_s *, lc_plan_desc *) {}
 void info_gemm(lc_plan_s *, lc_plan_desc *) {}
-lc_status nodes_batch(lc_plan_s *, const double **, int64_t *, int32_t *) { return LC_ERR_UNSUPPORTED; }
 lc_status nodes_gemm(lc_plan_s *, const double **, int64_t *, int32_t *) { return LC_ERR_UNSUPPORTED; }
 }  // namespace lc
 
 extern "C" {
-lc_status lc_plan_batch(int32_t, const int64_t *, const int64_t *, const int32_t *, const lc_precision *, lc_plan_t *) {
-    return lc::fail_status(LC_ERR_UNSUPPORTED, "lc_plan_batch: not built yet");
-}
-lc_status lc_plan_batch_offsets(lc_plan_t, int64_t *, int64_t *, int64_t *) {
-    return lc::fail_status(LC_ERR_UNSUPPORTED, "not built yet");
-}
-lc_status lc_execute_batch(lc_plan_t, const void *, double *, hipStream_t) {
-    return lc::fail_status(LC_ERR_UNSUPPORTED, "not built yet");
-}
 lc_status lc_plan_gemm(int32_t, int64_t, int64_t, lc_gemm_mode, lc_plan_t *) {
     return lc::fail_status(LC_ERR_UNSUPPORTED, "not built yet");
 }

@@ -1,0 +1,222 @@
+// Batched kernels: many functions of uneven size in one execution.
+//   * k_bquad_*: the Abel quadrature reduction over a table of row tiles
+//     (each tile a run of rows of one function); one launch per class of
+//     functions sharing (Q, sample precision), weights in registers.
+//   * k_bdst_lds: one workgroup per function, pack + LDS Stockham FFT +
+//     unpack/rescale (the twist and the one FFT of eq. (2.4)), functions
+//     listed longest first so the long ones start early.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+#include "lc_internal.h"
+#include "quad_device.h"
+
+namespace lc {
+
+template <typename T, int VEC, int G, int CPL, int U>
+__global__ __launch_bounds__(256) void k_bquad_fit(const unsigned char *__restrict__ f_arena,
+                                                   const double *__restrict__ w,
+                                                   const BatchTile *__restrict__ tiles, int ntiles,
+                                                   const BatchFn *__restrict__ fns,
+                                                   double *__restrict__ phi_arena) {
+    using V = typename VecOf<T, VEC>::type;
+    constexpr int Q = G * CPL * VEC;
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int rg = lane / G;
+    const int wv = threadIdx.x >> 6;
+    double wr[CPL][VEC];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) wr[c][e] = w[(g + c * G) * VEC + e];
+
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile tl = tiles[t];
+        const BatchFn &fn = fns[tl.fn];
+        const T *f = reinterpret_cast<const T *>(f_arena + fn.f_off);
+        double *phi = phi_arena + fn.phi_off;
+        const double *s2 = fn.s2;
+        const int rend = tl.row0 + tl.nrows;
+        const int r0 = tl.row0 + wv * (RPW * U);
+        V val[U][CPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int row = r0 + u * RPW + rg;
+            if (row < rend) {
+                const V *p = reinterpret_cast<const V *>(f + (int64_t)row * Q) + g;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) val[u][c] = ld_stream(p + c * G);
+            } else {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) val[u][c] = (V)(T)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                double d[VEC];
+                to_d(val[u][c], d);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc = fma(wr[c][e], d[e], acc);
+            }
+            acc = group_sum<G>(acc);
+            const int row = r0 + u * RPW + rg;
+            if (g == 0 && row < rend) phi[row] = s2[row] * acc;
+        }
+    }
+}
+
+template <typename T, int VEC, int G>
+__global__ __launch_bounds__(256) void k_bquad_gen(const unsigned char *__restrict__ f_arena,
+                                                   const double *__restrict__ w, int Q,
+                                                   const BatchTile *__restrict__ tiles, int ntiles,
+                                                   const BatchFn *__restrict__ fns,
+                                                   double *__restrict__ phi_arena) {
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int rg = lane / G;
+    const int wv = threadIdx.x >> 6;
+    const int NC = Q / VEC;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile tl = tiles[t];
+        const BatchFn &fn = fns[tl.fn];
+        const T *f = reinterpret_cast<const T *>(f_arena + fn.f_off);
+        const int rend = tl.row0 + tl.nrows;
+        const int row = tl.row0 + wv * RPW + rg;
+        double acc = 0.0;
+        if (row < rend) acc = row_partial<T, VEC, G>(f + (int64_t)row * Q, w, NC, g);
+        acc = group_sum<G>(acc);
+        if (g == 0 && row < rend) phi_arena[fn.phi_off + row] = fn.s2[row] * acc;
+    }
+}
+
+template <typename T, int VEC, int G, int CPL, int U>
+static hipError_t bfit(const QuadCfg &c, const void *f, const double *w, const BatchTile *tiles, int ntiles,
+                       const BatchFn *fns, double *phi, hipStream_t s) {
+    hipLaunchKernelGGL((k_bquad_fit<T, VEC, G, CPL, U>), dim3(c.grid), dim3(c.block), 0, s,
+                       (const unsigned char *)f, w, tiles, ntiles, fns, phi);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC, int G>
+static hipError_t bgen(const QuadCfg &c, const void *f, const double *w, int Q, const BatchTile *tiles,
+                       int ntiles, const BatchFn *fns, double *phi, hipStream_t s) {
+    hipLaunchKernelGGL((k_bquad_gen<T, VEC, G>), dim3(c.grid), dim3(c.block), 0, s,
+                       (const unsigned char *)f, w, Q, tiles, ntiles, fns, phi);
+    return hipGetLastError();
+}
+
+#define LC_BFIT_CASES(TT, VV, GG)                                                                 \
+    if (c.G == GG && c.vec == VV) {                                                               \
+        switch (c.cpl * 16 + c.unroll) {                                                          \
+            case 1 * 16 + 1: return bfit<TT, VV, GG, 1, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 1 * 16 + 2: return bfit<TT, VV, GG, 1, 2>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 1 * 16 + 4: return bfit<TT, VV, GG, 1, 4>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 2 * 16 + 1: return bfit<TT, VV, GG, 2, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 2 * 16 + 2: return bfit<TT, VV, GG, 2, 2>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 2 * 16 + 4: return bfit<TT, VV, GG, 2, 4>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 3 * 16 + 1: return bfit<TT, VV, GG, 3, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 3 * 16 + 2: return bfit<TT, VV, GG, 3, 2>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 4 * 16 + 1: return bfit<TT, VV, GG, 4, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 4 * 16 + 2: return bfit<TT, VV, GG, 4, 2>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 6 * 16 + 1: return bfit<TT, VV, GG, 6, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 8 * 16 + 1: return bfit<TT, VV, GG, 8, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
+            default: break;                                                                       \
+        }                                                                                         \
+    }
+
+template <typename T>
+static hipError_t bdispatch(const QuadCfg &c, const void *f, const double *w, int Q, const BatchTile *tiles,
+                            int ntiles, const BatchFn *fns, double *phi, hipStream_t s) {
+    if (c.cpl > 0) {
+        if constexpr (sizeof(T) == 8) {
+            LC_BFIT_CASES(T, 2, 4)
+            LC_BFIT_CASES(T, 2, 8)
+            LC_BFIT_CASES(T, 2, 16)
+        } else {
+            LC_BFIT_CASES(T, 4, 4)
+            LC_BFIT_CASES(T, 4, 8)
+            LC_BFIT_CASES(T, 4, 16)
+        }
+        return hipErrorInvalidValue;
+    }
+    switch (c.vec * 1000 + c.G) {
+        case 1004: return bgen<T, 1, 4>(c, f, w, Q, tiles, ntiles, fns, phi, s);
+        case 1008: return bgen<T, 1, 8>(c, f, w, Q, tiles, ntiles, fns, phi, s);
+        case 1016: return bgen<T, 1, 16>(c, f, w, Q, tiles, ntiles, fns, phi, s);
+        case 1032: return bgen<T, 1, 32>(c, f, w, Q, tiles, ntiles, fns, phi, s);
+        case 1064: return bgen<T, 1, 64>(c, f, w, Q, tiles, ntiles, fns, phi, s);
+        case 2016: return bgen<T, 2, 16>(c, f, w, Q, tiles, ntiles, fns, phi, s);
+        case 2032: return bgen<T, 2, 32>(c, f, w, Q, tiles, ntiles, fns, phi, s);
+        case 2064: return bgen<T, 2, 64>(c, f, w, Q, tiles, ntiles, fns, phi, s);
+        default: break;
+    }
+    return hipErrorInvalidValue;
+}
+#undef LC_BFIT_CASES
+
+hipError_t launch_bquad(const QuadCfg &cfg, int prec, const void *f_arena, const double *w, const BatchTile *tiles,
+                        int ntiles, const BatchFn *fns, double *phi_arena, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    if (prec == LC_FP64) return bdispatch<double>(cfg, f_arena, w, cfg.Qv, tiles, ntiles, fns, phi_arena, s);
+    return bdispatch<float>(cfg, f_arena, w, cfg.Qv, tiles, ntiles, fns, phi_arena, s);
+}
+
+// One workgroup per listed function.
+template <int T>
+__global__ __launch_bounds__(T) void k_bdst_lds(const double *__restrict__ phi_arena,
+                                                const BatchFn *__restrict__ fns,
+                                                const int32_t *__restrict__ list,
+                                                double *__restrict__ c_arena) {
+    extern __shared__ double2 lds[];
+    const BatchFn &fn = fns[list[blockIdx.x]];
+    const int64_t H = fn.H;
+    const int L = (int)fn.L;
+    const FftSched sch = fn.sched;
+    struct Phi {
+        const double *p;
+        __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
+    } ph{phi_arena + fn.phi_off};
+    for (int k = threadIdx.x; k < L; k += T) lds[k] = dst_pack(k, ph, H, L, fn.tw_pre, fn.tw_pack);
+    __syncthreads();
+    fft_lds<T, 8>(lds, L, 1, sch, fn.tw_fft, 1);
+    double *c = c_arena + fn.c_off;
+    for (int64_t n = threadIdx.x; n < fn.N; n += T) c[n] = dst_post(n, lds, H);
+}
+
+hipError_t prepare_bdst(int threads, int Lmax) {
+    const size_t lds = (size_t)Lmax * sizeof(double2);
+    if (lds <= 65536) return hipSuccess;
+    if (threads == 256)
+        return hipFuncSetAttribute((const void *)k_bdst_lds<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (threads == 1024)
+        return hipFuncSetAttribute((const void *)k_bdst_lds<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipSuccess;
+}
+
+hipError_t launch_bdst(int threads, int Lmax, const double *phi_arena, const BatchFn *fns, const int32_t *list,
+                       int nlist, double *c_arena, hipStream_t s) {
+    if (nlist <= 0) return hipSuccess;
+    if (Lmax > 8 * threads) return hipErrorInvalidValue;
+    const size_t lds = (size_t)Lmax * sizeof(double2);
+    switch (threads) {
+        case 64:
+            hipLaunchKernelGGL(k_bdst_lds<64>, dim3(nlist), dim3(64), lds, s, phi_arena, fns, list, c_arena);
+            break;
+        case 256:
+            hipLaunchKernelGGL(k_bdst_lds<256>, dim3(nlist), dim3(256), lds, s, phi_arena, fns, list, c_arena);
+            break;
+        case 1024:
+            hipLaunchKernelGGL(k_bdst_lds<1024>, dim3(nlist), dim3(1024), lds, s, phi_arena, fns, list, c_arena);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lc

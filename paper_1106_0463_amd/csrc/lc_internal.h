@@ -32,6 +32,7 @@ struct QuadCfg {
     int unroll;     // rows per row-group per iteration
     int block;      // threads per block
     int grid;       // blocks
+    int Qv;         // Q (used by the batched generic kernel)
 };
 
 struct DstCfg {
@@ -55,11 +56,23 @@ struct FnDesc {
 };
 
 // Device-side descriptor of a batch function (plain data for kernels).
-struct DevFn {
+struct BatchFn {
+    int64_t f_off;     // bytes into the sample arena
+    int64_t phi_off;   // elements into the phi arena
+    int64_t c_off;     // elements into the coefficient arena
     int64_t N, H, L;
-    int64_t f_off, c_off, phi_off, row0;
+    const double *s2;  // 2 sin(y_j / 2), j = 1..H
     const double2 *tw_pre, *tw_pack, *tw_fft;
-    int32_t Q, prec;
+    FftSched sched;    // LDS schedule for L (when L <= kLdsFftMax)
+};
+
+// A run of rows of one function handled by one block of the batched
+// quadrature kernel.
+struct BatchTile {
+    int32_t fn;
+    int32_t row0;
+    int32_t nrows;
+    int32_t pad;
 };
 
 }  // namespace lc
@@ -105,6 +118,15 @@ hipError_t launch_fused_small(int threads, int prec, const void *f, const double
                               const double2 *tw_pre, const double2 *tw_pack,
                               const double2 *tw_fft, double *c, hipStream_t s);
 bool quad_cfg_supported(const QuadCfg &cfg, int prec, int Q);
+int quad_rows_per_block(const QuadCfg &cfg);
+
+// --- batched launchers (kernels_batch.hip) ---------------------------------
+hipError_t launch_bquad(const QuadCfg &cfg, int prec, const void *f_arena, const double *w,
+                        const BatchTile *tiles, int ntiles, const BatchFn *fns, double *phi_arena,
+                        hipStream_t s);
+hipError_t launch_bdst(int threads, int Lmax, const double *phi_arena, const BatchFn *fns,
+                       const int32_t *list, int nlist, double *c_arena, hipStream_t s);
+hipError_t prepare_bdst(int threads, int Lmax);
 size_t fused_small_lds_bytes(int64_t H, int Q);
 
 // --- host helpers (host.cpp) ---------------------------------------------

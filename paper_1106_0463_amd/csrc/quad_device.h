@@ -1,0 +1,75 @@
+// Device helpers of the Abel quadrature reduction shared by the single and
+// batched kernels: vector loads of FP64/FP32 samples, FP64 accumulation and
+// fixed-order wave reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lc {
+
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int VEC> struct VecOf;
+template <> struct VecOf<double, 1> { using type = double; };
+template <> struct VecOf<double, 2> { using type = dv2; };
+template <> struct VecOf<float, 1> { using type = float; };
+template <> struct VecOf<float, 2> { using type = fv2; };
+template <> struct VecOf<float, 4> { using type = fv4; };
+
+__device__ __forceinline__ void to_d(double v, double *o) { o[0] = v; }
+__device__ __forceinline__ void to_d(dv2 v, double *o) { o[0] = v.x; o[1] = v.y; }
+__device__ __forceinline__ void to_d(float v, double *o) { o[0] = (double)v; }
+__device__ __forceinline__ void to_d(fv2 v, double *o) { o[0] = (double)v.x; o[1] = (double)v.y; }
+__device__ __forceinline__ void to_d(fv4 v, double *o) {
+    o[0] = (double)v.x; o[1] = (double)v.y; o[2] = (double)v.z; o[3] = (double)v.w;
+}
+
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+template <int G>
+__device__ __forceinline__ double group_sum(double acc) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    return acc;
+}
+
+// Generic variant for any Q: G lanes per row stride over the Q/VEC chunks
+// with bounds checks, 4 chunks in flight per lane; weights from global
+// memory (L1/L2 resident: every row reuses them).
+template <typename T, int VEC, int G>
+__device__ __forceinline__ double row_partial(const T *__restrict__ frow, const double *__restrict__ w,
+                                              int NC, int g) {
+    using V = typename VecOf<T, VEC>::type;
+    const V *p = reinterpret_cast<const V *>(frow);
+    double acc0 = 0.0, acc1 = 0.0;
+    int c = g;
+    for (; c + 3 * G < NC; c += 4 * G) {
+        V a = ld_stream(p + c), b = ld_stream(p + c + G), cc = ld_stream(p + c + 2 * G),
+          dd = ld_stream(p + c + 3 * G);
+        double da[VEC], db[VEC], dc[VEC], dd_[VEC];
+        to_d(a, da); to_d(b, db); to_d(cc, dc); to_d(dd, dd_);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            acc0 = fma(w[c * VEC + e], da[e], acc0);
+            acc1 = fma(w[(c + G) * VEC + e], db[e], acc1);
+            acc0 = fma(w[(c + 2 * G) * VEC + e], dc[e], acc0);
+            acc1 = fma(w[(c + 3 * G) * VEC + e], dd_[e], acc1);
+        }
+    }
+    for (; c < NC; c += G) {
+        V a = ld_stream(p + c);
+        double da[VEC];
+        to_d(a, da);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc0 = fma(w[c * VEC + e], da[e], acc0);
+    }
+    return acc0 + acc1;
+}
+
+}  // namespace lc

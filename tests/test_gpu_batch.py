@@ -1,0 +1,188 @@
+"""GPU parity of the batched path (ragged batches in one graph launch)
+against the CPU oracle, the single-function path and the exact
+coefficients of random finite Legendre series."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import banner, expected_grid, rel_err
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lc():
+    import torch
+    import paper_1106_0463_amd as lc
+    torch.cuda.set_device(0)
+    return lc
+
+
+def _build(lc, funcs, N, M, Q, prec):
+    import torch
+    from workloads.gpu import fill_closed_form_arena
+    bp = lc.plan_batch(N, M, Q, prec)
+    f_off, x_off, c_off = bp.offsets()
+    nodes = bp.nodes
+    H = [expected_grid(m) // 2 for m in M]
+    arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
+    fill_closed_form_arena(nodes, arena, x_off, f_off, H, Q, funcs, [p == "fp32" for p in prec])
+    return bp, arena, c_off
+
+
+SMALL = [  # (family, N, M, Q, precision)
+    (W.GeneratingFunction(0.5), 64, 256, 32, "fp64"),
+    (W.Exponential(1.0), 64, 256, 32, "fp64"),
+    (W.Exponential(-3.0), 700, 2000, 48, "fp64"),
+    (W.GeneratingFunction(0.8), 1, 2, 1, "fp64"),
+    (W.Cosine(40.0), 3000, 12000, 48, "fp32"),
+    (W.Sum(W.Exponential(0.7), W.GeneratingFunction(0.6)), 5000, 40000, 33, "fp64"),
+    (W.Rational(2.0), 333, 1000, 7, "fp32"),
+    (W.GeneratingFunction(0.3), 4096, 8192, 64, "fp64"),
+    (W.Exponential(5.0), 100, 300, 16, "fp32"),
+    (W.Cosine(10.0), 129, 600, 48, "fp64"),
+    (W.GeneratingFunction(0.9), 9000, 36000, 48, "fp64"),
+    (W.Exponential(-1.0), 2, 4, 3, "fp64"),
+]
+
+
+def test_small_ragged_batch(lc):
+    import torch
+    banner(f"[gpu] ragged batch of {len(SMALL)}")
+    funcs = [s[0] for s in SMALL]
+    N = [s[1] for s in SMALL]
+    M = [s[2] for s in SMALL]
+    Q = [s[3] for s in SMALL]
+    prec = [s[4] for s in SMALL]
+    bp, arena, c_off = _build(lc, funcs, N, M, Q, prec)
+    c = bp.execute(arena)
+    torch.cuda.synchronize()
+    c = c.cpu().numpy()
+    for b, (f, n, m, q, pr) in enumerate(SMALL):
+        got = c[c_off[b]:c_off[b + 1]]
+        ref = np.array(oracle.method_coeffs(f, n, expected_grid(m), q), dtype=float)
+        if pr == "fp64":
+            assert rel_err(got, ref) <= TOL, b
+        else:
+            k = 2 * np.arange(n) + 1
+            assert rel_err(got / k, ref / k) <= 1e-7, b
+    bp.destroy()
+
+
+def test_batch_matches_single_plans(lc):
+    import torch
+    banner("[gpu] batch vs single plans")
+    funcs = [s[0] for s in SMALL]
+    N = [s[1] for s in SMALL]
+    M = [s[2] for s in SMALL]
+    Q = [s[3] for s in SMALL]
+    prec = [s[4] for s in SMALL]
+    bp, arena, c_off = _build(lc, funcs, N, M, Q, prec)
+    c = bp.execute(arena).cpu().numpy()
+    for b, (f, n, m, q, pr) in enumerate(SMALL):
+        p = lc.plan(n, m, q, pr)
+        fx = f.torch(p.nodes).contiguous()
+        if pr == "fp32":
+            fx = fx.float().contiguous()
+        cs = p.execute(fx)
+        torch.cuda.synchronize()
+        assert rel_err(c[c_off[b]:c_off[b + 1]], cs.cpu().numpy()) <= 1e-14, b
+        p.destroy()
+    bp.destroy()
+
+
+def test_graph_replay_and_eager_identical(lc):
+    import torch
+    banner("[gpu] graph replay / eager / re-capture")
+    funcs = [s[0] for s in SMALL]
+    N = [s[1] for s in SMALL]
+    M = [s[2] for s in SMALL]
+    Q = [s[3] for s in SMALL]
+    prec = [s[4] for s in SMALL]
+    bp, arena, c_off = _build(lc, funcs, N, M, Q, prec)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        outs = []
+        for _ in range(3):
+            c = torch.full((int(c_off[-1]),), float("nan"), dtype=torch.float64, device="cuda")
+            outs.append(bp.execute(arena, c, stream=s))
+            s.synchronize()
+        bp.set_timing(True)           # eager path (events around the quadrature)
+        ce = bp.execute(arena, stream=s)
+        s.synchronize()
+        ms, cnt = bp.kernel_ms()
+        bp.set_timing(False)
+        arena2 = arena.clone()        # new pointer: re-capture
+        c2 = bp.execute(arena2, stream=s)
+        s.synchronize()
+    for o in outs[1:] + [ce, c2]:
+        assert torch.equal(outs[0], o)
+    assert cnt == 1 and ms > 0
+    bp.destroy()
+
+
+def _series_subset_parity(lc, sb, idx, Qfun, resolving):
+    import torch
+    from workloads.gpu import series_ragged
+    B = len(idx)
+    N = sb.N[idx]
+    M = sb.M[idx]
+    Q = np.array([Qfun(int(n)) for n in N], dtype=np.int32)
+    coeffs = [sb.coeffs[i] for i in idx]
+    bp = lc.plan_batch(N, M, Q, "fp64")
+    f_off, x_off, c_off = bp.offsets()
+    arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
+    series_ragged(coeffs, bp.nodes, x_off, arena, f_off, np.zeros(B, dtype=np.int32))
+    c = bp.execute(arena)
+    torch.cuda.synchronize()
+    c = c.cpu().numpy()
+    bp.destroy()
+    return N, M, Q, coeffs, c, c_off
+
+
+def test_uneven_series_resolving_q_exact(lc):
+    # random Legendre series of degree N_b - 1 with M_b = 4 N_b >= 2 N_b and
+    # Q_b >= N_b / 2: the method is exact, so the batch returns the series'
+    # own coefficients
+    banner("[gpu] uneven series batch at resolving Q: exact coefficients")
+    sb = W.batch_uneven(B=4096)
+    rng = np.random.default_rng(33)
+    idx = np.sort(rng.choice(4096, 16, replace=False))
+    N, M, Q, coeffs, c, c_off = _series_subset_parity(lc, sb, idx, lambda n: n // 2 + 2, True)
+    for k in range(len(idx)):
+        got = c[c_off[k]:c_off[k + 1]]
+        assert rel_err(got, coeffs[k]) <= TOL, (k, int(N[k]))
+
+
+def test_uneven_series_full_batch_stated_q(lc):
+    # the full 4096-function batch at the stated Q = 48 (under-resolving):
+    # arithmetic parity on a seeded subset of small functions against the
+    # method oracle at the same discretization and the same FP64 nodes
+    import torch
+    from workloads.gpu import series_ragged
+    banner("[gpu] uneven series batch B=4096, Q=48")
+    sb = W.batch_uneven(B=4096)
+    bp = lc.plan_batch(sb.N, sb.M, sb.Q, "fp64")
+    f_off, x_off, c_off = bp.offsets()
+    arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
+    series_ragged(sb.coeffs, bp.nodes, x_off, arena, f_off, np.zeros(4096, dtype=np.int32))
+    c = bp.execute(arena)
+    torch.cuda.synchronize()
+    c = c.cpu().numpy()
+    bp.destroy()
+    del arena
+    torch.cuda.empty_cache()
+    small = np.where(sb.N <= 400)[0]
+    pick = np.random.default_rng(35).choice(small, 4, replace=False)
+    for b in pick:
+        n, m = int(sb.N[b]), int(sb.M[b])
+        f = W.LegendreSeries(sb.coeffs[b])
+        ref = np.array(oracle.method_coeffs(f, n, expected_grid(m), 48, fp64_nodes=True), dtype=float)
+        got = c[c_off[b]:c_off[b + 1]]
+        err = rel_err(got, ref)
+        banner(f"    fn {b} N={n}: rel err {err:.2e}; vs truth {rel_err(got, sb.coeffs[b]):.2e}")
+        assert err <= TOL

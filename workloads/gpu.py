@@ -71,3 +71,20 @@ def series_grid(coef: np.ndarray, x_nodes, device="cuda"):
         raise RuntimeError(f"synth_series_grid failed ({rc})")
     torch.cuda.synchronize()
     return F
+
+
+def fill_closed_form_arena(nodes, f_arena, x_off, f_off, H, Q, funcs, fp32):
+    """Samples closed-form families f_b (objects with a .torch method) at
+    their slices of the node arena into the byte arena (FP32 where fp32[b])."""
+    import torch
+    for b, f in enumerate(funcs):
+        n = int(H[b]) * int(Q[b])
+        x = nodes[int(x_off[b]):int(x_off[b]) + n]
+        v = f.torch(x)
+        if fp32[b]:
+            dst = f_arena[int(f_off[b]):int(f_off[b]) + 4 * n].view(torch.float32)
+            dst.copy_(v.float())
+        else:
+            dst = f_arena[int(f_off[b]):int(f_off[b]) + 8 * n].view(torch.float64)
+            dst.copy_(v)
+    torch.cuda.synchronize()
