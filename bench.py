@@ -183,6 +183,132 @@ def run_single_small(args):
     return line
 
 
+def stream_request(ms, b):
+    """(M_b, Q_b) for one request of the mixed stream: M_b = 4 N_b, enlarged
+    for the generating function so that the aliased tail t^{n+M} is below
+    1e-13 (M_b >= N_b + ln(1e-13)/ln t + 1); Q_b = 48."""
+    N = int(ms.N[b])
+    M = 4 * N
+    if ms.kind[b] == 0:
+        t = float(ms.param[b])
+        M = max(M, N + int(math.ceil(math.log(1e-13) / math.log(t))) + 1)
+    M += M % 2
+    return M, 48
+
+
+def _batch_common(args, bp, arena, Nsum, alg_bytes, workload_cfg, cpu):
+    import torch
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        c = torch.empty(int(bp.offsets()[2][-1]), dtype=torch.float64, device="cuda")
+        step = lambda: bp.execute(arena, c, stream=s)
+        sec = time_steps(step, args.steps, args.warmup)
+        bp.set_timing(True)
+        for _ in range(min(args.steps, 10)):
+            step()
+        s.synchronize()
+        kms, cnt = bp.kernel_ms()
+        bp.set_timing(False)
+    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    line = {"metric": METRIC, "value": Nsum / sec, "unit": "coefficients/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": workload_cfg.pop("dtype"), "data": "synthetic", "config": workload_cfg,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_bquad_* (batched Abel quadrature reduction)",
+                         "kernel_ms": kms, "alg_bytes_per_launch": alg_bytes}}
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    return line
+
+
+def cpu_baseline_series(sb, idx):
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    t0 = time.perf_counter()
+    n = 0
+    for b in idx:
+        N = int(sb.N[b])
+        oracle.legendre_coeffs(W.LegendreSeries(sb.coeffs[b]), N, N + 32)
+        n += N
+        if time.perf_counter() - t0 > 20:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "coefficients/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n} coefficients of seeded functions of the same batch, eq. (2.3) by an "
+                      f"(N_b+32)-point long-double Gauss-Legendre rule, {dt:.2f} s"}
+
+
+def run_batch(args):
+    import numpy as np
+    import torch
+
+    import paper_1106_0463_amd as lc
+    import workloads as W
+    from workloads.gpu import series_ragged
+    sb = W.batch_uneven(B=4096)
+    prec = args.precision
+    bp = lc.plan_batch(sb.N, sb.M, sb.Q, prec)
+    f_off, x_off, c_off = bp.offsets()
+    arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
+    series_ragged(sb.coeffs, bp.nodes, x_off, arena, f_off,
+                  np.full(4096, 1 if prec == "fp32" else 0, dtype=np.int32))
+    esz = 8 if prec == "fp64" else 4
+    Hs = sb.M // 2
+    alg = float(np.sum(esz * Hs * sb.Q) + 16 * np.sum(Hs))
+    cfg = {"workload": f"batched uneven random Legendre series, B=4096, N_b log-uniform in [256,8192], "
+                       f"M_b=4N_b, Q=48, {prec.upper()} samples",
+           "B": 4096, "sum_N": int(sb.N.sum()), "Q": 48, "precision": prec,
+           "dtype": "f64" if prec == "fp64" else "f32 samples / f64 arithmetic"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_series(sb, np.random.default_rng(3).choice(4096, 64, replace=False))
+    line = _batch_common(args, bp, arena, int(sb.N.sum()), alg, cfg, cpu)
+    bp.destroy()
+    return line
+
+
+def run_stream(args):
+    import numpy as np
+    import torch
+
+    import paper_1106_0463_amd as lc
+    import workloads as W
+    from workloads.gpu import fill_closed_form_arena
+    ms = W.mixed_stream(B=args.stream_b)
+    B = ms.N.size
+    MQ = [stream_request(ms, b) for b in range(B)]
+    M = np.array([m for m, _ in MQ], dtype=np.int64)
+    Q = np.array([q for _, q in MQ], dtype=np.int32)
+    prec = ["fp64" if ms.fp64[b] else "fp32" for b in range(B)]
+    bp = lc.plan_batch(ms.N, M, Q, prec)
+    if args.autotune:
+        bp.autotune()
+    f_off, x_off, c_off = bp.offsets()
+    arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
+    funcs = [W.stream_function(ms, b) for b in range(B)]
+    Heff = np.diff(x_off)  # upper bound only for fill; exact rows from the plan grid
+    import paper_1106_0463_amd as _lc
+    H = np.array([_lc.grid_size(int(m)) // 2 for m in M], dtype=np.int64)
+    fill_closed_form_arena(bp.nodes, arena, x_off, f_off, H, Q, funcs, [p == "fp32" for p in prec])
+    esz = np.where(ms.fp64, 8, 4)
+    alg = float(np.sum(esz * (M // 2) * Q) + 16 * np.sum(M // 2))
+    cfg = {"workload": f"mixed stream, B={B}, N Pareto(1.2) in [32,65536], generating functions "
+                       f"t~U(0.1,0.999) and e^(ax) a~U(-20,20), FP64 and FP32-sample requests alternating, Q=48",
+           "B": B, "sum_N": int(ms.N.sum()), "Q": 48, "autotuned": bool(args.autotune),
+           "dtype": "f64 (half the requests with f32 samples)"}
+    line = _batch_common(args, bp, arena, int(ms.N.sum()), alg, cfg, None)
+    bp.destroy()
+    return line
+
+
+def run_gemm(args):
+    raise NotImplementedError("gemm workload")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +319,10 @@ def main():
     ap.add_argument("--q", type=int, default=0, help="override Q (single_large)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-stated", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--stream-b", type=int, default=65536)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--mode", default="bf16x3", help="gemm mode")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -207,9 +337,12 @@ def main():
         line = run_single_large(args)
     elif args.workload == "single_small":
         line = run_single_small(args)
+    elif args.workload == "batch":
+        line = run_batch(args)
+    elif args.workload == "stream":
+        line = run_stream(args)
     else:
-        import bench_workloads
-        line = bench_workloads.run(args)
+        line = run_gemm(args)
     print(json.dumps(line), flush=True)
 
 

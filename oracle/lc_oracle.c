@@ -73,7 +73,9 @@ int oracle_gauss_legendre(long K, ld *x, ld *w)
             dp = (ld)K * (xi * pk - pkm1) / (xi * xi - 1.0L);
             ld dx = pk / dp;
             xi -= dx;
-            if (fabsl(dx) <= 4.0L * LDBL_EPSILON * fabsl(xi) + 1e-4900L) { ok = 1; break; }
+            /* relative test, with an absolute floor for the node at x = 0 of
+             * odd K (nodes are ~pi/K apart, so 1e-3 is far below spacing) */
+            if (fabsl(dx) <= 4.0L * LDBL_EPSILON * fmaxl(fabsl(xi), 1e-3L)) { ok = 1; break; }
             /* quadratic convergence has stopped: the step is at the rounding
              * level of P_K (grows like K eps near the ends) */
             if (it >= 3 && fabsl(dx) > 0.25L * prev && fabsl(dx) < 1e-15L) { ok = 1; break; }

@@ -118,7 +118,7 @@ void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w, std:
                 legendre_and_derivative(n, x, p, dp);
                 long double dx = p / dp;
                 x -= dx;
-                if (fabsl(dx) <= 2.0L * 1.0842e-19L * fabsl(x)) break;
+                if (fabsl(dx) <= 4.0L * 1.0842e-19L * std::max(fabsl(x), 1e-3L)) break;
             }
             legendre_and_derivative(n, x, p, dp);
             t[i] = (double)x;

@@ -90,7 +90,8 @@ def test_batch_matches_single_plans(lc):
             fx = fx.float().contiguous()
         cs = p.execute(fx)
         torch.cuda.synchronize()
-        assert rel_err(c[c_off[b]:c_off[b + 1]], cs.cpu().numpy()) <= 1e-14, b
+        # different reduction orders (fused small path vs batched kernels)
+        assert rel_err(c[c_off[b]:c_off[b + 1]], cs.cpu().numpy()) <= 5e-14, b
         p.destroy()
     bp.destroy()
 

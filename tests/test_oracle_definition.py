@@ -83,6 +83,16 @@ def test_gauss_legendre_large_matches_mpmath_nodes():
     assert abs(float(np.sum(w)) - 2.0) < 1e-16
 
 
+def test_gauss_legendre_converges_for_every_size():
+    # odd and even K, small to large: a valid rule (nodes strictly inside
+    # (-1, 1), decreasing, symmetric; weights positive, summing to 2)
+    for K in list(range(1, 160)) + [957, 1001, 4097, 20000]:
+        x, w = oracle.gauss_legendre(K)
+        assert np.all(np.diff(x) < 0) and x[0] < 1 and x[-1] > -1
+        assert np.all(w > 0) and abs(float(np.sum(w)) - 2.0) < 1e-15
+        assert np.all(x + x[::-1] == 0)
+
+
 # --------------------------------------------------------- fixed cases ----
 
 @pytest.mark.parametrize("m", [0, 1, 5, 40, 63])
