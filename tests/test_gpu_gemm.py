@@ -1,0 +1,120 @@
+"""GPU checks of the Abel-as-GEMM form (fixed Chebyshev-Gauss sample grid).
+
+* the FP64 product-integration matrix A against the closed form of the
+  Abel transform of P_m (eq. (2.14) for f = P_m: 2 sin((m+1/2) y)/(2m+1),
+  itself pinned to mpmath quadrature in the oracle tests);
+* FP64 mode: random Legendre series of degree < P, M >= N + degree + 1:
+  the method is exact, so C equals the series' own coefficients (FP64
+  class, 1e-12 max|c|);
+* split modes (FP32 accumulation): E_a = max|da_n| / max|a| with
+  a_n = c_n/(2n+1), the mixed class bound 1e-7 for the three- and
+  six-product modes.
+"""
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+
+import workloads as W
+from helpers import banner, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lc():
+    import torch
+    import paper_1106_0463_amd as lc
+    torch.cuda.set_device(0)
+    return lc
+
+
+def _errors(C, coef, N):
+    n = np.arange(N)
+    ref = np.zeros((coef.shape[0], N))
+    k = min(N, coef.shape[1])
+    ref[:, :k] = coef[:, :k]
+    E_c = np.max(np.abs(C - ref)) / np.max(np.abs(ref))
+    a, ar = C / (2 * n + 1), ref / (2 * n + 1)
+    E_a = np.max(np.abs(a - ar)) / np.max(np.abs(ar))
+    return E_c, E_a
+
+
+def test_amat_closed_form(lc):
+    banner("[gpu] product-integration matrix vs closed form")
+    P, M = 256, 512
+    g = lc.plan_gemm(P, M, 64, "fp64")
+    A = g.matrix.cpu().numpy()
+    x = W.chebyshev_gauss_nodes(P)
+    H = M // 2
+    y = np.pi * np.arange(H + 1) / H
+    for m in (0, 1, 5, 100, 255):
+        cm = np.zeros(m + 1)
+        cm[m] = 1.0
+        phi = A @ npleg.legval(x, cm)
+        ref = 2 * np.sin((m + 0.5) * y) / (2 * m + 1)
+        assert np.max(np.abs(phi - ref)) < 1e-13, m
+    g.destroy()
+
+
+def _run(lc, mode, P, M, N, B, degree, seed=4, flat=False):
+    import torch
+    from workloads.gpu import series_grid
+    coef = W.gemm_batch_coeffs(B, degree, seed=seed, flat=flat)
+    g = lc.plan_gemm(P, M, N, mode)
+    F = series_grid(coef, g.nodes)
+    C = g.execute(F)
+    torch.cuda.synchronize()
+    out = C.cpu().numpy()
+    g.destroy()
+    return out, coef
+
+
+def test_gemm_fp64_exact(lc):
+    banner("[gpu] gemm fp64: exact coefficients")
+    C, coef = _run(lc, "fp64", 512, 1024, 512, 64, 300)
+    E_c, E_a = _errors(C, coef, 512)
+    banner(f"    E_c {E_c:.2e} E_a {E_a:.2e}")
+    assert E_c <= 1e-12
+
+
+@pytest.mark.parametrize("mode,bound", [("bf16x6", 1e-7), ("fp16x3", 1e-7), ("bf16x3", 5e-7), ("fp16x1", 1e-3)])
+def test_gemm_split_modes(lc, mode, bound):
+    banner(f"[gpu] gemm {mode}")
+    C, coef = _run(lc, mode, 1024, 2048, 1024, 256, 700)
+    E_c, E_a = _errors(C, coef, 1024)
+    banner(f"    {mode}: E_c {E_c:.2e} E_a {E_a:.2e}")
+    assert E_a <= bound
+
+
+def test_gemm_split_matches_fp64_path(lc):
+    # ragged sizes (P not a multiple of 32, B not a multiple of the tile)
+    banner("[gpu] gemm ragged sizes")
+    Cm, coef = _run(lc, "bf16x6", 1000, 1600, 777, 77, 500, seed=9)
+    Cd, _ = _run(lc, "fp64", 1000, 1600, 777, 77, 500, seed=9)
+    E_c, E_a = _errors(Cd, coef, 777)
+    assert E_c <= 1e-12
+    n = np.arange(777)
+    assert rel_err(Cm / (2 * n + 1), Cd / (2 * n + 1)) <= 1e-7
+
+
+def test_gemm_full_size_sampled(lc):
+    # P = 4096 Chebyshev-Gauss samples, M = 8192, N = 4096, B = 16384 series of
+    # degree 3000: E_a on every function for the six-product and fp16 modes
+    import torch
+    from workloads.gpu import series_grid
+    banner("[gpu] gemm full size B=16384")
+    B, P, M, N, deg = 16384, 4096, 8192, 4096, 3000
+    coef = W.gemm_batch_coeffs(B, deg, seed=4)
+    for mode, bound in (("fp16x3", 1e-7), ("bf16x6", 1e-7)):
+        g = lc.plan_gemm(P, M, N, mode)
+        F = series_grid(coef, g.nodes)
+        C = g.execute(F)
+        torch.cuda.synchronize()
+        sel = np.random.default_rng(41).choice(B, 256, replace=False)
+        Cs = C[torch.from_numpy(sel).cuda()].cpu().numpy()
+        E_c, E_a = _errors(Cs, coef[sel], N)
+        banner(f"    {mode}: E_c {E_c:.2e} E_a {E_a:.2e} (256 sampled functions)")
+        assert E_a <= bound
+        g.destroy()
+        del F, C
+        torch.cuda.empty_cache()
