@@ -127,12 +127,28 @@ hipError_t launch_amat(int H, int P, int QA, const double *xc, const double *lam
 // value of the remainder.  FP16 uses a power-of-two scale 2^-e per row (A)
 // or per function (F) so that |v 2^-e| < 1; BF16 has FP32's exponent range
 // and needs none.
+// Round-to-nearest-even FP32 -> 16-bit conversions written out on the bit
+// pattern, so that the pieces do not depend on the default conversion mode.
+template <typename H16> struct Round16;
+template <> struct Round16<__bf16> {
+    static __device__ __forceinline__ __bf16 from(float f) {
+        unsigned u = __builtin_bit_cast(unsigned, f);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return __builtin_bit_cast(__bf16, (unsigned short)(u >> 16));
+    }
+};
+template <> struct Round16<_Float16> {
+    static __device__ __forceinline__ _Float16 from(float f) { return (_Float16)f; }  // IEEE RNE
+};
+
 template <typename H16>
 __device__ __forceinline__ void split_value(double v, int npc, H16 *out) {
     double r = v;
     for (int i = 0; i < npc; ++i) {
-        const H16 h = (H16)(float)r;  // rounding through FP32 is exact-enough: the
-                                      // remainder carries what FP32 dropped
+        // the remainder r - piece is exact in FP64, so a piece that is not the
+        // nearest 16-bit value (double rounding through FP32) only shifts a
+        // few bits to the next piece
+        const H16 h = Round16<H16>::from((float)r);
         out[i] = h;
         r -= (double)(float)h;
     }
@@ -312,17 +328,35 @@ __global__ __launch_bounds__(256) void k_mgemm(const H16 *__restrict__ X, int64_
         }
     };
 
-    f32x16 acc[2][2];
+    // Two-level accumulation: the MFMA accumulator covers one K chunk of
+    // KCH stages and is then added into a second FP32 total and cleared, so
+    // that no FP32 chain runs over more than KCH*GBK/16 MFMA steps per
+    // product (long chains of same-sign partial sums lose accuracy).
+    constexpr int KCH = 4;
+    f32x16 acc[2][2], tot[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+            for (int v = 0; v < 16; ++v) {
+                acc[a][b][v] = 0.f;
+                tot[a][b][v] = 0.f;
+            }
 
     const int nk = P / GBK;
     gload(0);
     for (int kt = 0; kt < nk; ++kt) {
+        if (kt % KCH == 0 && kt > 0) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    tot[a][b] += acc[a][b];
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+                }
+        }
         __syncthreads();
         sstore();
         __syncthreads();
@@ -351,6 +385,10 @@ __global__ __launch_bounds__(256) void k_mgemm(const H16 *__restrict__ X, int64_
                         acc[a][b] = Mfma<H16>::run(fx[PR::u[pi]][a], fy[PR::v[pi]][b], acc[a][b]);
         }
     }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) tot[a][b] += acc[a][b];
     // D layout: lane l, register v -> row 8 (v/4) + 4 (l/32) + (v%4), col l%32
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -360,7 +398,7 @@ __global__ __launch_bounds__(256) void k_mgemm(const H16 *__restrict__ X, int64_
             for (int v = 0; v < 16; ++v) {
                 const int row = bm0 + wm + 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int col = bn0 + wn + 32 * b + (lane & 31);
-                if (row < Bn && col < Hn) Out[(int64_t)row * ldo + col] = acc[a][b][v];
+                if (row < Bn && col < Hn) Out[(int64_t)row * ldo + col] = tot[a][b][v];
             }
 }
 
