@@ -66,6 +66,9 @@ struct BatchState {
     std::vector<QuadClass> classes;
     std::vector<DstGroup> groups;
     std::vector<int> large;
+    BigFn *dbig = nullptr;
+    BigTile *ctiles = nullptr, *rtiles = nullptr, *ptiles = nullptr;
+    int nct = 0, nrt = 0, npt = 0;
     double *x_arena = nullptr, *phi_arena = nullptr;
     double2 *zA = nullptr, *zB = nullptr;
     int64_t f_bytes = 0, x_elems = 0, c_elems = 0, phi_elems = 0, ws_bytes = 0;
@@ -118,14 +121,8 @@ hipError_t launch_all(lc_plan_s *p, BatchState *st, const void *f_arena, double 
         e = launch_bdst(g.threads, g.Lmax, st->phi_arena, st->dfn, g.list, g.n, c_arena, s);
         if (e != hipSuccess) return e;
     }
-    for (int b : st->large) {
-        const FnDesc &d = st->fn[b];
-        const HSet &h = st->hs.at(d.H);
-        e = launch_dst(h.dcfg, st->phi_arena + d.phi_off, d.H, d.L, d.N, h.tw_pre, h.tw_pack, h.tw_fft, st->zA,
-                       st->zB, c_arena + d.c_off, s);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return launch_bbig(st->phi_arena, st->dbig, st->ctiles, st->nct, st->rtiles, st->nrt, st->ptiles, st->npt,
+                       c_arena, s);
 }
 
 }  // namespace
@@ -244,22 +241,30 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
     }
     chk(balloc(st, &st->x_arena, (size_t)st->x_elems));
     chk(balloc(st, &st->phi_arena, (size_t)st->phi_elems));
-    int64_t Lbig = 0;
+    int64_t Lsum = 0;
     for (int b = 0; b < B; ++b)
-        if (st->fn[b].L > kLdsFftMax) Lbig = std::max(Lbig, st->fn[b].L);
-    if (Lbig) {
-        chk(balloc(st, &st->zA, (size_t)Lbig));
-        chk(balloc(st, &st->zB, (size_t)Lbig));
+        if (st->fn[b].L > kLdsFftMax) Lsum += st->fn[b].L;
+    if (Lsum) {
+        chk(balloc(st, &st->zA, (size_t)Lsum));
+        chk(balloc(st, &st->zB, (size_t)Lsum));
     }
     if (e != hipSuccess) {
         free_state(st);
         return fail_status(e == hipErrorOutOfMemory ? LC_ERR_NOMEM : LC_ERR_HIP,
                            std::string("lc_plan_batch: allocation/upload failed: ") + hipGetErrorString(e));
     }
-    // ---- nodes
-    for (auto &d : st->fn) {
-        if (e != hipSuccess) break;
-        chk(launch_nodes(d.H, d.Q, st->hs[d.H].rowA, st->qs[d.Q].omt2, st->x_arena + d.x_off, 0));
+    // ---- nodes: one launch over blocks of 4096 nodes of one function each
+    if (e == hipSuccess) {
+        std::vector<NodeTile> nt;
+        for (auto &d : st->fn) {
+            const int64_t n = d.H * d.Q;
+            for (int64_t a = 0; a < n; a += 4096)
+                nt.push_back({st->x_arena + d.x_off, st->hs[d.H].rowA, st->qs[d.Q].omt2, a,
+                              std::min<int64_t>(n, a + 4096), d.Q});
+        }
+        NodeTile *dnt = nullptr;
+        chk(upload(st, &dnt, nt));
+        if (e == hipSuccess) chk(launch_bnodes(dnt, (int64_t)nt.size(), 0));
     }
     chk(hipDeviceSynchronize());
     // ---- device descriptors
@@ -310,11 +315,54 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
             st->large.push_back(b);
             continue;
         }
-        grp[L <= 512 ? 64 : (L <= 2048 ? 256 : 1024)].push_back(b);
+        // group by power-of-two length class so that the LDS reserved per
+        // workgroup (the group's longest FFT) stays close to what it needs
+        int cls = 512;
+        while (cls < L) cls *= 2;
+        grp[cls].push_back(b);
+    }
+    // long functions: batched four-step descriptors and block tables
+    if (!st->large.empty()) {
+        std::vector<BigFn> big;
+        std::vector<BigTile> ct, rt, pt;
+        int64_t zoff = 0;
+        for (int b : st->large) {
+            const FnDesc &d = st->fn[b];
+            const HSet &h = st->hs[d.H];
+            BigFn f{};
+            f.H = d.H;
+            f.L = d.L;
+            f.N = d.N;
+            f.L1 = h.dcfg.L1;
+            f.L2 = h.dcfg.L2;
+            four_step_blocks(f.L1, f.L2, &f.CB, &f.RB);
+            f.phi_off = d.phi_off;
+            f.c_off = d.c_off;
+            f.tw_pre = h.tw_pre;
+            f.tw_pack = h.tw_pack;
+            f.tw_fft = h.tw_fft;
+            f.zA = st->zA + zoff;
+            f.zB = st->zB + zoff;
+            zoff += d.L;
+            f.s1 = h.dcfg.s1;
+            f.s2 = h.dcfg.s2;
+            const int id = (int)big.size();
+            for (int k = 0; k < f.L2; k += f.CB) ct.push_back({id, k});
+            for (int k = 0; k < f.L1; k += f.RB) rt.push_back({id, k});
+            for (int64_t n = 0; n < f.N; n += 1024) pt.push_back({id, (int32_t)n});
+            big.push_back(f);
+        }
+        chk(upload(st, &st->dbig, big));
+        chk(upload(st, &st->ctiles, ct));
+        chk(upload(st, &st->rtiles, rt));
+        chk(upload(st, &st->ptiles, pt));
+        st->nct = (int)ct.size();
+        st->nrt = (int)rt.size();
+        st->npt = (int)pt.size();
     }
     for (auto &kv : grp) {
         DstGroup g;
-        g.threads = kv.first;
+        g.threads = kv.first <= 512 ? 64 : (kv.first <= 2048 ? 256 : 1024);
         auto v = kv.second;
         std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return st->fn[a].L > st->fn[b].L; });
         g.Lmax = (int)st->fn[v[0]].L;

@@ -219,4 +219,81 @@ hipError_t launch_bdst(int threads, int Lmax, const double *phi_arena, const Bat
     return hipGetLastError();
 }
 
+// ---------------------------------------------------- batched four-step ---
+// The same three passes as the single-function four-step FFT, for every
+// long function of a batch in one launch each: block t works on function
+// tiles[t].fn starting at column (row, coefficient) tiles[t].first.
+__global__ __launch_bounds__(256) void k_bbig_cols(const double *__restrict__ phi_arena,
+                                                   const BigFn *__restrict__ fns,
+                                                   const BigTile *__restrict__ tiles) {
+    extern __shared__ double2 lds[];
+    const BigTile tl = tiles[blockIdx.x];
+    const BigFn &fn = fns[tl.fn];
+    const int L1 = fn.L1, L2 = fn.L2, CB = fn.CB, k20 = tl.first;
+    const FftSched s1 = fn.s1;
+    struct Phi {
+        const double *p;
+        __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
+    } ph{phi_arena + fn.phi_off};
+    for (int e = threadIdx.x; e < CB * L1; e += 256) {
+        const int k1 = e / CB, cb = e - k1 * CB;
+        lds[cb * L1 + k1] = dst_pack((int64_t)L2 * k1 + k20 + cb, ph, fn.H, fn.L, fn.tw_pre, fn.tw_pack);
+    }
+    __syncthreads();
+    fft_lds<256, 8>(lds, L1, CB, s1, fn.tw_fft, L2);
+    for (int e = threadIdx.x; e < CB * L1; e += 256) {
+        const int p1 = e / CB, cb = e - p1 * CB;
+        const int k2 = k20 + cb;
+        fn.zA[(int64_t)p1 * L2 + k2] = cmul(lds[cb * L1 + p1], fn.tw_fft[(int64_t)p1 * k2]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bbig_rows(const BigFn *__restrict__ fns, const BigTile *__restrict__ tiles) {
+    extern __shared__ double2 lds[];
+    const BigTile tl = tiles[blockIdx.x];
+    const BigFn &fn = fns[tl.fn];
+    const int L1 = fn.L1, L2 = fn.L2, RB = fn.RB, p10 = tl.first;
+    const FftSched s2 = fn.s2;
+    for (int e = threadIdx.x; e < RB * L2; e += 256) lds[e] = fn.zA[(int64_t)p10 * L2 + e];
+    __syncthreads();
+    fft_lds<256, 8>(lds, L2, RB, s2, fn.tw_fft, L1);
+    for (int e = threadIdx.x; e < RB * L2; e += 256) {
+        const int p2 = e / RB, rb = e - p2 * RB;
+        fn.zB[(int64_t)(p10 + rb) + (int64_t)L1 * p2] = lds[rb * L2 + p2];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bbig_post(const BigFn *__restrict__ fns, const BigTile *__restrict__ tiles,
+                                                   double *__restrict__ c_arena) {
+    const BigTile tl = tiles[blockIdx.x];
+    const BigFn &fn = fns[tl.fn];
+    const int64_t n0 = tl.first, n1 = min((int64_t)tl.first + 1024, fn.N);
+    double *c = c_arena + fn.c_off;
+    for (int64_t n = n0 + threadIdx.x; n < n1; n += 256) c[n] = dst_post(n, fn.zB, fn.H);
+}
+
+int four_step_blocks(int L1, int L2, int *CB, int *RB) {
+    int cb = 2048 / L1 < L2 ? 2048 / L1 : L2;
+    while (cb > 1 && L2 % cb) --cb;
+    int rb = 2048 / L2 < L1 ? 2048 / L2 : L1;
+    while (rb > 1 && L1 % rb) --rb;
+    *CB = cb;
+    *RB = rb;
+    return (cb >= 1 && rb >= 1 && cb * L1 <= 2048 && rb * L2 <= 2048) ? 0 : -1;
+}
+
+hipError_t launch_bbig(const double *phi_arena, const BigFn *fns, const BigTile *ctiles, int nct,
+                       const BigTile *rtiles, int nrt, const BigTile *ptiles, int npt, double *c_arena,
+                       hipStream_t s) {
+    if (nct <= 0) return hipSuccess;
+    const size_t lds = 2048 * sizeof(double2);
+    hipLaunchKernelGGL(k_bbig_cols, dim3(nct), dim3(256), lds, s, phi_arena, fns, ctiles);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bbig_rows, dim3(nrt), dim3(256), lds, s, fns, rtiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bbig_post, dim3(npt), dim3(256), 0, s, fns, ptiles, c_arena);
+    return hipGetLastError();
+}
+
 }  // namespace lc

@@ -180,14 +180,23 @@ __global__ __launch_bounds__(256) void k_split_rows(const double *__restrict__ A
     }
 }
 
-// per-function max |F[p][b]| over p -> exponent colexp[b]
+// per-function exponent colexp[b] = ilogb(max_p |F[p][b]|) + 1: a fill, then
+// blocks of 256 functions x 64 rows fold their partial maxima in with an
+// integer atomic max (the exponent is monotone in the magnitude).
+__global__ __launch_bounds__(256) void k_colexp_init(int B, int *__restrict__ colexp) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b < B) colexp[b] = -2000;
+}
+
 __global__ __launch_bounds__(256) void k_colmax(const double *__restrict__ F, int P, int B,
                                                 int *__restrict__ colexp) {
     const int b = blockIdx.x * 256 + threadIdx.x;
+    const int p0 = blockIdx.y * 64;
     if (b >= B) return;
     double m = 0.0;
-    for (int p = 0; p < P; ++p) m = fmax(m, fabs(F[(int64_t)p * B + b]));
-    colexp[b] = m > 0.0 ? ilogb(m) + 1 : 0;
+    const int p1 = p0 + 64 < P ? p0 + 64 : P;
+    for (int p = p0; p < p1; ++p) m = fmax(m, fabs(F[(int64_t)p * B + b]));
+    if (m > 0.0) atomicMax(colexp + b, ilogb(m) + 1);
 }
 
 // F [P][B] -> pieces X_i[b][p] through a 64x64 LDS transpose tile.
@@ -206,7 +215,7 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F
     for (int i = ty; i < 64; i += 4) {
         const int b = b0 + i, p = p0 + tx;
         if (b < B && p < P) {
-            const double sc = colexp ? ldexp(1.0, -colexp[b]) : 1.0;
+            const double sc = colexp ? ldexp(1.0, -max(colexp[b], -1000)) : 1.0;
             H16 pcs[3];
             split_value<H16>(tile[tx][i] * sc, npc, pcs);
             for (int k = 0; k < npc; ++k) X[k * piece_stride + (int64_t)b * ldk + p] = pcs[k];
@@ -228,8 +237,11 @@ hipError_t launch_split_rows(int h16, const double *A, int H, int P, int ldk, in
 hipError_t launch_split_cols(int h16, const double *F, int P, int B, int ldk, int npc, void *X,
                              int64_t piece_stride, int *colexp, int scaled, hipStream_t s) {
     if (scaled) {
-        hipLaunchKernelGGL(k_colmax, dim3((B + 255) / 256), dim3(256), 0, s, F, P, B, colexp);
+        hipLaunchKernelGGL(k_colexp_init, dim3((B + 255) / 256), dim3(256), 0, s, B, colexp);
         hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_colmax, dim3((B + 255) / 256, (P + 63) / 64), dim3(256), 0, s, F, P, B, colexp);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     dim3 grid((B + 63) / 64, (P + 63) / 64);
@@ -283,7 +295,7 @@ template <> struct Prods<6> {
 };
 
 template <typename H16, int MODE>
-__global__ __launch_bounds__(256) void k_mgemm(const H16 *__restrict__ X, int64_t xps, const H16 *__restrict__ Y,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mgemm(const H16 *__restrict__ X, int64_t xps, const H16 *__restrict__ Y,
                                                int64_t yps, int Bn, int Hn, int P, float *__restrict__ Out,
                                                int ldo) {
     using PR = Prods<MODE>;
@@ -438,7 +450,7 @@ __global__ __launch_bounds__(T) void k_gdst_lds(const PhiT *__restrict__ Out, in
     extern __shared__ double2 lds[];
     const int b = blockIdx.x;
     const PhiT *row = Out + (int64_t)b * ldo;
-    const int ce = colexp ? colexp[b] : 0;
+    const int ce = colexp ? max(colexp[b], -1000) : 0;
     struct Phi {
         const PhiT *p;
         const int *re;

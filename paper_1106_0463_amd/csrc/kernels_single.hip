@@ -39,6 +39,38 @@ __global__ __launch_bounds__(256) void k_nodes(int64_t H, int Q, const double2 *
     }
 }
 
+// The same construction for many functions at once (batch plans): block t
+// builds nodes [begin, end) of tiles[t].
+__device__ __forceinline__ double node_dd(double2 a, double2 b) {
+#pragma clang fp contract(off)
+    const double p = a.x * b.x;
+    double e = fma(a.x, b.x, -p);
+    e = fma(a.x, b.y, fma(a.y, b.x, e));
+    const double s = 1.0 - p;
+    const double bb = s - 1.0;
+    const double err = (1.0 - (s - bb)) + (-p - bb);
+    return s + (err - e);
+}
+
+__global__ __launch_bounds__(256) void k_bnodes(const NodeTile *__restrict__ tiles) {
+    const NodeTile t = tiles[blockIdx.x];
+    for (int64_t idx = t.begin + threadIdx.x; idx < t.end; idx += 256) {
+        const int64_t r = idx / t.Q;
+        const int q = (int)(idx - r * t.Q);
+        t.x[idx] = node_dd(t.rowA[r], t.omt2[q]);
+    }
+}
+
+hipError_t launch_bnodes(const NodeTile *tiles, int64_t ntiles, hipStream_t s) {
+    for (int64_t a = 0; a < ntiles; a += 1 << 20) {
+        const int64_t n = ntiles - a < (1 << 20) ? ntiles - a : (1 << 20);
+        hipLaunchKernelGGL(k_bnodes, dim3((unsigned)n), dim3(256), 0, s, tiles + a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_nodes(int64_t H, int Q, const double2 *A, const double2 *B, double *x, hipStream_t s) {
     const int64_t total = H * (int64_t)Q;
     int64_t blocks = (total + 255) / 256;

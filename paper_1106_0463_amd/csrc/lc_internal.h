@@ -66,6 +66,31 @@ struct BatchFn {
     FftSched sched;    // LDS schedule for L (when L <= kLdsFftMax)
 };
 
+// A function whose FFT exceeds the LDS: four-step form L = L1 * L2 with its
+// own schedules and workspace (zA, zB: L complex each).
+struct BigFn {
+    int64_t H, L, N;
+    int32_t L1, L2, CB, RB;
+    int64_t phi_off, c_off;
+    const double2 *tw_pre, *tw_pack, *tw_fft;
+    double2 *zA, *zB;
+    FftSched s1, s2;
+};
+// One block of a batched four-step pass: function index and first column
+// (row) of the block.
+struct BigTile {
+    int32_t fn;
+    int32_t first;
+};
+
+// Nodes [begin, end) (flat index r*Q + q) of one function of a batch.
+struct NodeTile {
+    double *x;
+    const double2 *rowA, *omt2;
+    int64_t begin, end;
+    int32_t Q, pad;
+};
+
 // A run of rows of one function handled by one block of the batched
 // quadrature kernel.
 struct BatchTile {
@@ -108,6 +133,7 @@ namespace lc {
 // --- launchers (kernels_single.hip) ---------------------------------------
 hipError_t launch_nodes(int64_t H, int Q, const double2 *A, const double2 *B, double *x,
                         hipStream_t s);
+hipError_t launch_bnodes(const NodeTile *tiles, int64_t ntiles, hipStream_t s);
 hipError_t launch_quad(const QuadCfg &cfg, int prec, const void *f, const double *w,
                        const double *s2, int64_t rows, int Q, double *phi, hipStream_t s);
 hipError_t launch_dst(const DstCfg &cfg, const double *phi, int64_t H, int64_t L, int64_t N,
@@ -127,6 +153,10 @@ hipError_t launch_bquad(const QuadCfg &cfg, int prec, const void *f_arena, const
 hipError_t launch_bdst(int threads, int Lmax, const double *phi_arena, const BatchFn *fns,
                        const int32_t *list, int nlist, double *c_arena, hipStream_t s);
 hipError_t prepare_bdst(int threads, int Lmax);
+hipError_t launch_bbig(const double *phi_arena, const BigFn *fns, const BigTile *ctiles, int nct,
+                       const BigTile *rtiles, int nrt, const BigTile *ptiles, int npt, double *c_arena,
+                       hipStream_t s);
+int four_step_blocks(int L1, int L2, int *CB, int *RB);
 size_t fused_small_lds_bytes(int64_t H, int Q);
 
 // --- host helpers (host.cpp) ---------------------------------------------
