@@ -89,6 +89,8 @@ def bench_single(args, N, M, Q, f, name):
 
     import paper_1106_0463_amd as lc
     p = lc.plan(N, M, Q)
+    if args.autotune:
+        p.autotune()
     info = p.info
     x = p.nodes
     fx = f.torch(x).contiguous()
@@ -252,6 +254,8 @@ def run_batch(args):
     sb = W.batch_uneven(B=4096)
     prec = args.precision
     bp = lc.plan_batch(sb.N, sb.M, sb.Q, prec)
+    if args.autotune:
+        bp.autotune()
     f_off, x_off, c_off = bp.offsets()
     arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
     series_ragged(sb.coeffs, bp.nodes, x_off, arena, f_off,

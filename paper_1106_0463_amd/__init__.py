@@ -65,6 +65,7 @@ class Plan:
     def __init__(self, handle: C.c_void_p):
         self._h = handle
         self._lib = load()
+        self._info = None
 
     # -- lifetime -----------------------------------------------------
     def destroy(self) -> None:
@@ -87,9 +88,13 @@ class Plan:
     # -- description --------------------------------------------------
     @property
     def info(self) -> dict:
-        d = PlanDesc()
-        check(self._lib.lc_plan_info(self._h, C.byref(d)), "lc_plan_info")
-        return {k: getattr(d, k) for k, _ in PlanDesc._fields_}
+        """Plan description (lc_plan_info), cached: single and batch plans
+        never change shape; GEMM plans refresh it on reserve."""
+        if self._info is None:
+            d = PlanDesc()
+            check(self._lib.lc_plan_info(self._h, C.byref(d)), "lc_plan_info")
+            self._info = {k: getattr(d, k) for k, _ in PlanDesc._fields_}
+        return self._info
 
     @property
     def nodes(self):

@@ -13,13 +13,16 @@ from ._lib import PRECISIONS, check, load
 class BatchPlan(Plan):
     def offsets(self):
         """(f_off bytes, x_off elements, c_off elements), each of length B+1."""
+        if getattr(self, "_offsets", None) is not None:
+            return self._offsets
         B = self.info["B"]
         f = np.zeros(B + 1, dtype=np.int64)
         x = np.zeros(B + 1, dtype=np.int64)
         c = np.zeros(B + 1, dtype=np.int64)
         p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
         check(self._lib.lc_plan_batch_offsets(self._h, p(f), p(x), p(c)), "lc_plan_batch_offsets")
-        return f, x, c
+        self._offsets = (f, x, c)
+        return self._offsets
 
     @property
     def nodes(self):
@@ -33,7 +36,7 @@ class BatchPlan(Plan):
         (layout of :meth:`offsets`); returns the float64 coefficient arena."""
         import torch
         f_off, _, c_off = self.offsets()
-        if not f_arena.is_cuda or f_arena.numel() * f_arena.element_size() < f_off[-1]:
+        if f_arena.numel() * f_arena.element_size() < f_off[-1] or not f_arena.is_cuda:
             raise ValueError("f_arena too small or not on the GPU")
         if c_arena is None:
             c_arena = torch.empty(int(c_off[-1]), dtype=torch.float64, device=f_arena.device)

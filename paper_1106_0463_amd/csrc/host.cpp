@@ -12,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <sstream>
 #include <thread>
 #include <vector>
 
@@ -562,4 +563,115 @@ lc_status fail_status(lc_status s, const std::string &msg) {
     g_err = msg;
     return s;
 }
+}  // namespace lc
+
+// ------------------------------------------------------------ autotune ---
+namespace lc {
+
+static std::string sched_to_str(const FftSched &s) {
+    std::string o = std::to_string(s.npass);
+    for (int i = 0; i < s.npass; ++i) o += ' ' + std::to_string(s.radix[i]);
+    return o;
+}
+
+static bool sched_from(std::istringstream &i, FftSched &s, int L) {
+    FftSched t{};
+    t.n = L;
+    if (!(i >> t.npass) || t.npass < 0 || t.npass > kMaxPasses) return false;
+    int64_t prod = 1;
+    for (int k = 0; k < t.npass; ++k) {
+        if (!(i >> t.radix[k])) return false;
+        prod *= t.radix[k];
+    }
+    if (prod != L) return false;
+    s = t;
+    return true;
+}
+
+lc_status tune_single(lc_plan_s *p, hipStream_t s) {
+    const FnDesc &d = p->fn;
+    const std::string key = arch_name() + "|single|" + std::to_string(d.H) + "|" + std::to_string(d.Q) + "|" +
+                            std::to_string(d.prec) + "|" + std::to_string(d.N);
+    std::string val;
+    if (cache_get(key, val)) {
+        std::istringstream in(val);
+        std::string tag;
+        QuadCfg q = p->quad;
+        DstCfg dc = p->dst;
+        int fused = 0, threads = 0;
+        std::string qs;
+        in >> tag;
+        int v[6];
+        bool ok = tag == "quad";
+        for (int k = 0; ok && k < 6; ++k) ok = (bool)(in >> v[k]);
+        if (ok) {
+            q.vec = v[0]; q.G = v[1]; q.cpl = v[2]; q.unroll = v[3]; q.block = v[4]; q.grid = v[5];
+            ok = quad_cfg_supported(q, d.prec, d.Q) && (in >> tag) && tag == "dst" && (in >> threads);
+        }
+        if (ok && d.L <= kLdsFftMax) ok = sched_from(in, dc.sched, (int)d.L) && d.L <= 8 * threads;
+        if (ok && d.L > kLdsFftMax) ok = sched_from(in, dc.s1, dc.L1) && sched_from(in, dc.s2, dc.L2);
+        if (ok) ok = (in >> tag) && tag == "fused" && (in >> fused);
+        if (ok) {
+            p->quad = q;
+            dc.threads = threads;
+            p->dst = dc;
+            p->fused_small = fused != 0 && p->fused_small;
+            return LC_OK;
+        }
+    }
+    hipError_t e = hipSuccess;
+    double *cbuf = nullptr;
+    if ((e = hipMalloc((void **)&cbuf, (size_t)d.N * sizeof(double))) != hipSuccess)
+        return fail_status(LC_ERR_NOMEM, "lc_autotune: workspace");
+    const void *fsrc = p->x;  // same shape as the samples (FP64) or larger (FP32)
+    double best = 1e30;
+    QuadCfg bq = p->quad;
+    for (const QuadCfg &c : quad_candidates(d.prec, d.Q, d.H, device_cu_count())) {
+        hipError_t er;
+        const double t = time_launch([&](hipStream_t st) { return launch_quad(c, d.prec, fsrc, p->w, p->s2, d.H, d.Q, p->phi, st); }, s, 3, &er);
+        if (er == hipSuccess && t < best) { best = t; bq = c; }
+    }
+    const double t_quad = best;
+    DstCfg bd = p->dst;
+    double bt = 1e30;
+    if (d.L <= kLdsFftMax) {
+        for (int T : {64, 256, 1024}) {
+            if (d.L > 8 * T) continue;
+            for (const FftSched &sc : sched_candidates((int)d.L)) {
+                DstCfg c = p->dst;
+                c.threads = T;
+                c.sched = sc;
+                hipError_t er;
+                const double t = time_launch([&](hipStream_t st) { return launch_dst(c, p->phi, d.H, d.L, d.N, p->tw_pre, p->tw_pack, p->tw_fft, p->zA, p->zB, cbuf, st); }, s, 3, &er);
+                if (er == hipSuccess && t < bt) { bt = t; bd = c; }
+            }
+        }
+    } else {
+        for (const FftSched &a : sched_candidates(p->dst.L1))
+            for (const FftSched &b : sched_candidates(p->dst.L2)) {
+                DstCfg c = p->dst;
+                c.s1 = a;
+                c.s2 = b;
+                hipError_t er;
+                const double t = time_launch([&](hipStream_t st) { return launch_dst(c, p->phi, d.H, d.L, d.N, p->tw_pre, p->tw_pack, p->tw_fft, p->zA, p->zB, cbuf, st); }, s, 3, &er);
+                if (er == hipSuccess && t < bt) { bt = t; bd = c; }
+            }
+    }
+    bool fused = false;
+    if (p->fused_small) {
+        hipError_t er;
+        const double t = time_launch([&](hipStream_t st) { return launch_fused_small(p->fused_threads, d.prec, fsrc, p->w, p->s2, d.H, d.Q, d.N, bd.sched, p->tw_pre, p->tw_pack, p->tw_fft, cbuf, st); }, s, 3, &er);
+        fused = er == hipSuccess && t < t_quad + bt;
+    }
+    hipFree(cbuf);
+    p->quad = bq;
+    p->dst = bd;
+    p->fused_small = fused;
+    std::string v = "quad " + quad_to_str(bq) + " dst " + std::to_string(bd.threads) + " ";
+    v += d.L <= kLdsFftMax ? sched_to_str(bd.sched) : sched_to_str(bd.s1) + " " + sched_to_str(bd.s2);
+    v += std::string(" fused ") + (fused ? "1" : "0");
+    cache_put(key, v);
+    return LC_OK;
+}
+
 }  // namespace lc

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <map>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -51,11 +52,20 @@ struct QuadClass {
     BatchTile *tiles = nullptr;
     int ntiles = 0;
     int64_t rows = 0;
+    std::vector<int> fns;
 };
 struct DstGroup {
     int threads = 0, Lmax = 0, n = 0;
     int32_t *list = nullptr;
 };
+
+std::vector<BatchTile> make_tiles(const std::vector<FnDesc> &fn, const std::vector<int> &fns, int rpt) {
+    std::vector<BatchTile> tiles;
+    for (int b : fns)
+        for (int64_t r = 0; r < fn[b].H; r += rpt)
+            tiles.push_back({b, (int32_t)r, (int32_t)std::min<int64_t>(rpt, fn[b].H - r), 0});
+    return tiles;
+}
 
 struct BatchState {
     int B = 0;
@@ -151,6 +161,118 @@ lc_status nodes_batch(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q)
     *x = st->x_arena;
     if (rows) *rows = st->x_elems;
     if (Q) *Q = 0;
+    return LC_OK;
+}
+
+// Autotuning of a batch plan: the launch shape of every quadrature class
+// (tiles rebuilt for each candidate) and the threads of every DST group.
+lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
+    BatchState *st = (BatchState *)p->ext;
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the batch shape
+    auto mix = [&](int64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    for (auto &d : st->fn) {
+        mix(d.N);
+        mix(d.M_eff);
+        mix(d.Q);
+        mix(d.prec);
+    }
+    const std::string key = arch_name() + "|batch|" + std::to_string(st->B) + "|" + std::to_string(h);
+    std::string val;
+    std::vector<QuadCfg> qcfg;
+    std::vector<int> gthreads;
+    bool cached = false;
+    if (cache_get(key, val)) {
+        std::istringstream in(val);
+        size_t nc = 0, ng = 0;
+        cached = (bool)(in >> nc) && nc == st->classes.size();
+        for (size_t i = 0; cached && i < nc; ++i) {
+            QuadCfg c = st->classes[i].cfg;
+            cached = (bool)(in >> c.vec >> c.G >> c.cpl >> c.unroll >> c.block >> c.grid) &&
+                     quad_cfg_supported(c, st->classes[i].prec, st->classes[i].Q);
+            qcfg.push_back(c);
+        }
+        cached = cached && (in >> ng) && ng == st->groups.size();
+        for (size_t i = 0; cached && i < ng; ++i) {
+            int t = 0;
+            cached = (bool)(in >> t) && st->groups[i].Lmax <= 8 * t;
+            gthreads.push_back(t);
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!cached) {
+        qcfg.clear();
+        gthreads.clear();
+        const int cu = device_cu_count();
+        for (auto &qc : st->classes) {
+            double best = 1e30;
+            QuadCfg bc = qc.cfg;
+            for (QuadCfg c : quad_candidates(qc.prec, qc.Q, qc.rows, cu)) {
+                c.Qv = qc.Q;
+                std::vector<BatchTile> tl = make_tiles(st->fn, qc.fns, quad_rows_per_block(c));
+                BatchTile *dt = nullptr;
+                if ((e = hipMalloc((void **)&dt, tl.size() * sizeof(BatchTile))) != hipSuccess) break;
+                e = hipMemcpy(dt, tl.data(), tl.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+                c.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)tl.size(), c.grid * 1));
+                if (e == hipSuccess) {
+                    hipError_t er;
+                    const int nt = (int)tl.size();
+                    const double t = time_launch([&](hipStream_t ss) { return launch_bquad(c, qc.prec, st->x_arena, qc.w, dt, nt, st->dfn, st->phi_arena, ss); }, s, 3, &er);
+                    if (er == hipSuccess && t < best) { best = t; bc = c; }
+                }
+                hipFree(dt);
+            }
+            qcfg.push_back(bc);
+        }
+        double *cbuf = nullptr;
+        if (e == hipSuccess) e = hipMalloc((void **)&cbuf, (size_t)std::max<int64_t>(1, st->c_elems) * sizeof(double));
+        for (auto &g : st->groups) {
+            double best = 1e30;
+            int bt = g.threads;
+            for (int T : {64, 256, 1024}) {
+                if (e != hipSuccess || g.Lmax > 8 * T || prepare_bdst(T, g.Lmax) != hipSuccess) continue;
+                hipError_t er;
+                const double t = time_launch([&](hipStream_t ss) { return launch_bdst(T, g.Lmax, st->phi_arena, st->dfn, g.list, g.n, cbuf, ss); }, s, 3, &er);
+                if (er == hipSuccess && t < best) { best = t; bt = T; }
+            }
+            gthreads.push_back(bt);
+        }
+        hipFree(cbuf);
+        if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_autotune: ") + hipGetErrorString(e));
+        std::string v = std::to_string(qcfg.size());
+        for (auto &c : qcfg) v += " " + quad_to_str(c);
+        v += " " + std::to_string(gthreads.size());
+        for (int t : gthreads) v += " " + std::to_string(t);
+        cache_put(key, v);
+    }
+    // apply: new tiles per class, thread counts per group, fresh graph
+    for (size_t i = 0; i < st->classes.size(); ++i) {
+        QuadClass &qc = st->classes[i];
+        QuadCfg c = qcfg[i];
+        c.Qv = qc.Q;
+        std::vector<BatchTile> tl = make_tiles(st->fn, qc.fns, quad_rows_per_block(c));
+        BatchTile *dt = nullptr;
+        if ((e = upload(st, &dt, tl)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: tiles");
+        qc.tiles = dt;
+        qc.ntiles = (int)tl.size();
+        qc.cfg = c;
+        qc.cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>(qc.ntiles, c.grid));
+    }
+    for (size_t i = 0; i < st->groups.size(); ++i) {
+        if (prepare_bdst(gthreads[i], st->groups[i].Lmax) == hipSuccess) st->groups[i].threads = gthreads[i];
+    }
+    if (st->gexec) {
+        hipGraphExecDestroy(st->gexec);
+        st->gexec = nullptr;
+    }
+    if (st->graph) {
+        hipGraphDestroy(st->graph);
+        st->graph = nullptr;
+    }
     return LC_OK;
 }
 
@@ -297,11 +419,8 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         qc.cfg = default_quad_cfg(qc.prec, qc.Q, qc.rows, cu);
         qc.cfg.Qv = qc.Q;
         qc.w = st->qs[qc.Q].w;
-        const int rpt = quad_rows_per_block(qc.cfg);
-        std::vector<BatchTile> tiles;
-        for (int b : kv.second)
-            for (int64_t r = 0; r < st->fn[b].H; r += rpt)
-                tiles.push_back({b, (int32_t)r, (int32_t)std::min<int64_t>(rpt, st->fn[b].H - r), 0});
+        qc.fns = kv.second;
+        std::vector<BatchTile> tiles = make_tiles(st->fn, qc.fns, quad_rows_per_block(qc.cfg));
         qc.ntiles = (int)tiles.size();
         qc.cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>(qc.ntiles, (int64_t)cu * 8));
         chk(upload(st, &qc.tiles, tiles));

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -171,5 +172,15 @@ void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack,
 QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu);
 DstCfg default_dst_cfg(int64_t L);
 int device_cu_count();
+
+// --- autotuner helpers (autotune.cpp) --------------------------------------
+std::string arch_name();
+bool cache_get(const std::string &key, std::string &val);
+void cache_put(const std::string &key, const std::string &val);
+std::string quad_to_str(const QuadCfg &c);
+bool quad_from_str(const std::string &s, QuadCfg &c);
+std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu);
+std::vector<FftSched> sched_candidates(int L);
+double time_launch(const std::function<hipError_t(hipStream_t)> &f, hipStream_t s, int reps, hipError_t *err);
 
 }  // namespace lc

@@ -19,6 +19,7 @@ class GemmPlan(Plan):
 
     def reserve(self, B: int) -> None:
         check(self._lib.lc_plan_gemm_reserve(self._h, int(B)), "lc_plan_gemm_reserve")
+        self._info = None
 
     def execute(self, F, out=None, stream=None):
         """F: float64 CUDA tensor [P, B]; returns C [B, N] (float64)."""

@@ -84,3 +84,7 @@ def test_null_arguments_rejected(lib):
     assert lib.lc_plan_destroy(None) == 0
     assert "null" in lib.lc_last_error().decode() or lib.lc_last_error().decode() != ""
     assert lib.lc_grid_size(1, C.byref(C.c_int64())) == 1
+
+
+def test_autotune_rejects_null(lib):
+    assert lib.lc_autotune(None, None) == 1
