@@ -363,19 +363,33 @@ def run_gemm(args):
     return line
 
 
+def run_copy(args):
+    """Plain device copy of 4 GiB (torch copy kernel): the reference point
+    that scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = (4 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    sec = time_steps(lambda: dst.copy_(src), args.steps, args.warmup)
+    return {"metric": "device copy", "value": 2 * 8 * n / sec / 1e9, "unit": "GB/s (read+write)",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+            "higher_is_better": True, "bytes_read_per_launch": 8 * n, "bytes_written_per_launch": 8 * n}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_large",
-                    choices=["single_large", "single_small", "batch", "gemm", "stream"])
+                    choices=["single_large", "single_small", "batch", "gemm", "stream", "copy"])
     ap.add_argument("--q", type=int, default=0, help="override Q (single_large)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-stated", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--stream-b", type=int, default=65536)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use the default launch shapes instead of the autotuner's")
     ap.add_argument("--mode", default="bf16x3", help="gemm mode")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -391,6 +405,8 @@ def main():
         line = run_single_large(args)
     elif args.workload == "single_small":
         line = run_single_small(args)
+    elif args.workload == "copy":
+        line = run_copy(args)
     elif args.workload == "batch":
         line = run_batch(args)
     elif args.workload == "stream":
