@@ -33,6 +33,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the dominant kernel from the two rocprofv3 counter passes
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from the 4 GiB copy calibration),
+# with the kernel they were taken on
+TRAFFIC = {"single_large": (8.7939e9, "k_quad_gen<double, 2, 16>"),
+           "batch_fp64": (7.8123e9, "k_bquad_fit<double, 2, 8, 3, 2>")}
 METRIC = "Legendre coeffs/sec at 1 GPU (FP64 ≤1e-12 vs split-BF16 ≤1e-7 rel.)"
 Q_RESOLVING = 8384
 
@@ -142,8 +147,10 @@ def run_single_large(args):
                    "N": N, "M": M, "M_eff": r["info"]["M_eff"], "Q": wl.Q,
                    "Q_stated": 64, "precision_class": "FP64 (<=1e-12 max|c|)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_quad_gen (Abel quadrature reduction)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": TRAFFIC["single_large"][0] if wl.Q == Q_RESOLVING else None,
+                     "traffic_kernel": TRAFFIC["single_large"][1],
+                     "kernel": "k_quad_* (Abel quadrature reduction)",
                      "kernel_ms": kms, "alg_bytes_per_launch": r["alg_bytes"]},
     }
     p.destroy()
@@ -271,6 +278,8 @@ def run_batch(args):
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_series(sb, np.random.default_rng(3).choice(4096, 64, replace=False))
     line = _batch_common(args, bp, arena, int(sb.N.sum()), alg, cfg, cpu)
+    if prec == "fp64":
+        line["roofline"]["traffic"], line["roofline"]["traffic_kernel"] = TRAFFIC["batch_fp64"]
     bp.destroy()
     return line
 
