@@ -11,6 +11,7 @@
 #include <rocblas/rocblas.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 #include <new>
 #include <string>
@@ -140,6 +141,7 @@ lc_status lc_plan_gemm(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_pl
         return fail_status(LC_ERR_INVALID, "lc_plan_gemm: bad mode");
     GemmState *g = new (std::nothrow) GemmState();
     if (!g) return fail_status(LC_ERR_NOMEM, "lc_plan_gemm: host allocation failed");
+    if (const char *wm = getenv("LC_MGEMM_WM")) mgemm_wm = atoi(wm) == 2 ? 2 : 4;
     g->P = P;
     g->ldk = (P + 31) / 32 * 32;
     g->QA = P / 2 + 8;

@@ -294,34 +294,43 @@ template <> struct Prods<6> {
     static constexpr int u[6] = {0, 1, 0, 2, 1, 0}, v[6] = {0, 0, 1, 0, 1, 2};
 };
 
-template <typename H16, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mgemm(const H16 *__restrict__ X, int64_t xps, const H16 *__restrict__ Y,
-                                               int64_t yps, int Bn, int Hn, int P, float *__restrict__ Out,
-                                               int ldo) {
+template <typename H16, int MODE, int WM>
+__global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mgemm(
+    const H16 *__restrict__ X, int64_t xps, const H16 *__restrict__ Y, int64_t yps, int Bn, int Hn, int P,
+    float *__restrict__ Out, int ldo) {
+    // block tile (64 WM) x 128: WM x 2 waves, each wave 64 x 64
     using PR = Prods<MODE>;
     constexpr int NX = PR::nx, NY = PR::ny;
-    __shared__ __attribute__((aligned(16))) H16 sx[NX][GBM * GLD];
-    __shared__ __attribute__((aligned(16))) H16 sy[NY][GBN * GLD];
+    constexpr int BM = 64 * WM, NT = 128 * WM;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    H16 *sx = reinterpret_cast<H16 *>(smem);               // [NX][BM * GLD]
+    H16 *sy = sx + NX * BM * GLD;                            // [NY][GBN * GLD]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
     // tile coordinates, j fastest so that consecutive blocks share the X rows
     const int ntn = (Hn + GBN - 1) / GBN;
-    const int bm0 = (blockIdx.x / ntn) * GBM, bn0 = (blockIdx.x % ntn) * GBN;
+    const int bm0 = (blockIdx.x / ntn) * BM, bn0 = (blockIdx.x % ntn) * GBN;
 
-    // global -> register staging: each operand tile is 128 rows x 32 halves =
-    // 128 x 64 B; 256 threads x 2 chunks of 16 B per piece
-    u32x4 rx[NX][2], ry[NY][2];
+    // global -> register staging: a tile row is 32 halves = 4 chunks of 16 B
+    constexpr int CX = BM * 4 / NT, CY = GBN * 4 / NT;  // chunks per thread
+    u32x4 rx[NX][CX], ry[NY][CY];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int idx = tid + 256 * c;  // 0..511
+        for (int c = 0; c < CX; ++c) {
+            const int idx = tid + NT * c;
             const int row = idx >> 2, col = (idx & 3) * 8;
-            const int gb = bm0 + row, gj = bn0 + row;
+            const int gb = bm0 + row;
 #pragma unroll
             for (int u = 0; u < NX; ++u)
                 rx[u][c] = gb < Bn ? *reinterpret_cast<const u32x4 *>(X + u * xps + (int64_t)gb * P + k0 + col)
                                    : (u32x4)(0u);
+        }
+#pragma unroll
+        for (int c = 0; c < CY; ++c) {
+            const int idx = tid + NT * c;
+            const int row = idx >> 2, col = (idx & 3) * 8;
+            const int gj = bn0 + row;
 #pragma unroll
             for (int v = 0; v < NY; ++v)
                 ry[v][c] = gj < Hn ? *reinterpret_cast<const u32x4 *>(Y + v * yps + (int64_t)gj * P + k0 + col)
@@ -330,13 +339,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     };
     auto sstore = [&]() {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int idx = tid + 256 * c;
+        for (int c = 0; c < CX; ++c) {
+            const int idx = tid + NT * c;
             const int row = idx >> 2, col = (idx & 3) * 8;
 #pragma unroll
-            for (int u = 0; u < NX; ++u) *reinterpret_cast<u32x4 *>(&sx[u][row * GLD + col]) = rx[u][c];
+            for (int u = 0; u < NX; ++u) *reinterpret_cast<u32x4 *>(&sx[u * BM * GLD + row * GLD + col]) = rx[u][c];
+        }
 #pragma unroll
-            for (int v = 0; v < NY; ++v) *reinterpret_cast<u32x4 *>(&sy[v][row * GLD + col]) = ry[v][c];
+        for (int c = 0; c < CY; ++c) {
+            const int idx = tid + NT * c;
+            const int row = idx >> 2, col = (idx & 3) * 8;
+#pragma unroll
+            for (int v = 0; v < NY; ++v) *reinterpret_cast<u32x4 *>(&sy[v * GBN * GLD + row * GLD + col]) = ry[v][c];
         }
     };
 
@@ -382,12 +396,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             for (int u = 0; u < NX; ++u)
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
-                    fx[u][a] = *reinterpret_cast<const u32x4 *>(&sx[u][(wm + 32 * a + fr) * GLD + fk]);
+                    fx[u][a] = *reinterpret_cast<const u32x4 *>(&sx[u * BM * GLD + (wm + 32 * a + fr) * GLD + fk]);
 #pragma unroll
             for (int v = 0; v < NY; ++v)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
-                    fy[v][b] = *reinterpret_cast<const u32x4 *>(&sy[v][(wn + 32 * b + fr) * GLD + fk]);
+                    fy[v][b] = *reinterpret_cast<const u32x4 *>(&sy[v * GBN * GLD + (wn + 32 * b + fr) * GLD + fk]);
 #pragma unroll
             for (int pi = 0; pi < PR::n; ++pi)
 #pragma unroll
@@ -414,24 +428,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             }
 }
 
+int mgemm_wm = 2;  // waves along b per block (block tile 64*WM x 128); LC_MGEMM_WM overrides
+
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
                         int P, float *Out, int ldo, hipStream_t s) {
     if (P % GBK) return hipErrorInvalidValue;
-    const int grid = ((Bn + GBM - 1) / GBM) * ((Hn + GBN - 1) / GBN);
-#define LC_MG(T, MV)                                                                                        \
-    if (mode == MV) {                                                                                       \
-        hipLaunchKernelGGL((k_mgemm<T, MV>), dim3(grid), dim3(256), 0, s, (const T *)X, xps, (const T *)Y, yps, \
-                           Bn, Hn, P, Out, ldo);                                                            \
-        return hipGetLastError();                                                                           \
+    const int WM = mgemm_wm == 2 ? 2 : 4;
+    const int BM = 64 * WM;
+    const int grid = ((Bn + BM - 1) / BM) * ((Hn + GBN - 1) / GBN);
+    const int npx = mode == 1 ? 1 : (mode == 3 ? 2 : 3);
+    const size_t lds = (size_t)npx * (BM + GBN) * GLD * 2;
+#define LC_MG(T, MV, WMV)                                                                                      \
+    if (mode == MV && WM == WMV) {                                                                             \
+        if (lds > 65536) {                                                                                     \
+            hipError_t e = hipFuncSetAttribute((const void *)k_mgemm<T, MV, WMV>,                              \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);          \
+            if (e != hipSuccess) return e;                                                                     \
+        }                                                                                                      \
+        hipLaunchKernelGGL((k_mgemm<T, MV, WMV>), dim3(grid), dim3(128 * WMV), lds, s, (const T *)X, xps,    \
+                           (const T *)Y, yps, Bn, Hn, P, Out, ldo);                                            \
+        return hipGetLastError();                                                                              \
     }
     if (h16 == kBF16) {
-        LC_MG(__bf16, 1)
-        LC_MG(__bf16, 3)
-        LC_MG(__bf16, 6)
+        LC_MG(__bf16, 1, 2) LC_MG(__bf16, 3, 2) LC_MG(__bf16, 6, 2)
+        LC_MG(__bf16, 1, 4) LC_MG(__bf16, 3, 4) LC_MG(__bf16, 6, 4)
     } else {
-        LC_MG(_Float16, 1)
-        LC_MG(_Float16, 3)
-        LC_MG(_Float16, 6)
+        LC_MG(_Float16, 1, 2) LC_MG(_Float16, 3, 2) LC_MG(_Float16, 6, 2)
+        LC_MG(_Float16, 1, 4) LC_MG(_Float16, 3, 4) LC_MG(_Float16, 6, 4)
     }
 #undef LC_MG
     return hipErrorInvalidValue;

@@ -10,6 +10,9 @@ namespace lc {
 
 constexpr int kBF16 = 0, kF16 = 1;
 
+// waves along b per block of the MFMA product (2 or 4; block tile 64*WM x 128)
+extern int mgemm_wm;
+
 hipError_t launch_amat(int H, int P, int QA, const double *xc, const double *lam, const double2 *rowA,
                        const double2 *omt2, const double *wq, const double *s2, double *A, hipStream_t s);
 hipError_t launch_split_rows(int h16, const double *A, int H, int P, int ldk, int npc, void *Y,
