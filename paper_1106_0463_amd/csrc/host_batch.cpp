@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <sstream>
 #include <new>
@@ -45,6 +46,8 @@ struct QSet {
     double *w = nullptr;
     double2 *omt2 = nullptr;
 };
+constexpr int kParts = 4;  // pipeline parts of a captured batch execution
+
 struct QuadClass {
     int Q = 0, prec = 0;
     QuadCfg cfg{};
@@ -53,11 +56,23 @@ struct QuadClass {
     int ntiles = 0;
     int64_t rows = 0;
     std::vector<int> fns;
+    int tstart[kParts + 1] = {};  // tiles of part k: [tstart[k], tstart[k+1])
 };
 struct DstGroup {
     int threads = 0, Lmax = 0, n = 0;
     int32_t *list = nullptr;
+    int lstart[kParts + 1] = {};  // list entries of part k (list sorted by part, then length)
 };
+
+// tiles are in function order and parts are contiguous function ranges, so
+// the tiles of part k are one contiguous range
+void part_starts(const std::vector<BatchTile> &tiles, const std::vector<int> &part_of, int nparts, int *start) {
+    int k = 0;
+    start[0] = 0;
+    for (int t = 0; t < (int)tiles.size(); ++t)
+        while (k < nparts - 1 && part_of[tiles[t].fn] > k) start[++k] = t;
+    while (k < nparts) start[++k] = (int)tiles.size();
+}
 
 std::vector<BatchTile> make_tiles(const std::vector<FnDesc> &fn, const std::vector<int> &fns, int rpt) {
     std::vector<BatchTile> tiles;
@@ -79,6 +94,11 @@ struct BatchState {
     BigFn *dbig = nullptr;
     BigTile *ctiles = nullptr, *rtiles = nullptr, *ptiles = nullptr;
     int nct = 0, nrt = 0, npt = 0;
+    int cst[kParts + 1] = {}, rst[kParts + 1] = {}, pst[kParts + 1] = {};  // big tiles per part
+    std::vector<int> part_of;          // part of each function
+    int nparts = 1;
+    hipStream_t side = nullptr;        // second stream of the captured pipeline
+    hipEvent_t evq[kParts] = {}, evj = nullptr;
     double *x_arena = nullptr, *phi_arena = nullptr;
     double2 *zA = nullptr, *zB = nullptr;
     int64_t f_bytes = 0, x_elems = 0, c_elems = 0, phi_elems = 0, ws_bytes = 0;
@@ -111,28 +131,68 @@ hipError_t upload(BatchState *st, T **p, const std::vector<T> &v) {
 
 void free_state(BatchState *st) {
     if (!st) return;
+    for (auto &e : st->evq)
+        if (e) hipEventDestroy(e);
+    if (st->evj) hipEventDestroy(st->evj);
+    if (st->side) hipStreamDestroy(st->side);
     if (st->gexec) hipGraphExecDestroy(st->gexec);
     if (st->graph) hipGraphDestroy(st->graph);
     for (void *p : st->allocs) hipFree(p);
     delete st;
 }
 
+hipError_t launch_part_dst(BatchState *st, int k, double *c_arena, hipStream_t s) {
+    hipError_t e;
+    for (auto &g : st->groups) {
+        const int n = g.lstart[k + 1] - g.lstart[k];
+        e = launch_bdst(g.threads, g.Lmax, st->phi_arena, st->dfn, g.list + g.lstart[k], n, c_arena, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_bbig(st->phi_arena, st->dbig, st->ctiles + st->cst[k], st->cst[k + 1] - st->cst[k],
+                       st->rtiles + st->rst[k], st->rst[k + 1] - st->rst[k], st->ptiles + st->pst[k],
+                       st->pst[k + 1] - st->pst[k], c_arena, s);
+}
+
+hipError_t launch_part_quad(BatchState *st, int k, const void *f_arena, hipStream_t s) {
+    for (auto &qc : st->classes) {
+        const int n = qc.tstart[k + 1] - qc.tstart[k];
+        if (n <= 0) continue;
+        QuadCfg c = qc.cfg;
+        c.grid = std::max(1, std::min(c.grid, n));
+        hipError_t e = launch_bquad(c, qc.prec, f_arena, qc.w, qc.tiles + qc.tstart[k], n, st->dfn, st->phi_arena, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Eager order: all quadrature (timed as one region), then all DST work.
 hipError_t launch_all(lc_plan_s *p, BatchState *st, const void *f_arena, double *c_arena, hipStream_t s,
                       bool timed) {
     hipError_t e;
     int slot = -1;
     if (timed && (e = timing_begin(p, s, &slot)) != hipSuccess) return e;
-    for (auto &qc : st->classes) {
-        e = launch_bquad(qc.cfg, qc.prec, f_arena, qc.w, qc.tiles, qc.ntiles, st->dfn, st->phi_arena, s);
-        if (e != hipSuccess) return e;
-    }
+    for (int k = 0; k < st->nparts; ++k)
+        if ((e = launch_part_quad(st, k, f_arena, s)) != hipSuccess) return e;
     if (timed && (e = timing_end(p, s, slot)) != hipSuccess) return e;
-    for (auto &g : st->groups) {
-        e = launch_bdst(g.threads, g.Lmax, st->phi_arena, st->dfn, g.list, g.n, c_arena, s);
-        if (e != hipSuccess) return e;
+    for (int k = 0; k < st->nparts; ++k)
+        if ((e = launch_part_dst(st, k, c_arena, s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// Captured order: a two-stream pipeline.  The quadrature of part k runs on
+// the caller's stream; the DST of part k runs on the side stream once part
+// k's quadrature is done, so it overlaps the (HBM-bound) quadrature of part
+// k+1.  The side stream joins back before the graph ends.
+hipError_t launch_pipeline(BatchState *st, const void *f_arena, double *c_arena, hipStream_t s) {
+    hipError_t e;
+    for (int k = 0; k < st->nparts; ++k) {
+        if ((e = launch_part_quad(st, k, f_arena, s)) != hipSuccess) return e;
+        if ((e = hipEventRecord(st->evq[k], s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st->side, st->evq[k], 0)) != hipSuccess) return e;
+        if ((e = launch_part_dst(st, k, c_arena, st->side)) != hipSuccess) return e;
     }
-    return launch_bbig(st->phi_arena, st->dbig, st->ctiles, st->nct, st->rtiles, st->nrt, st->ptiles, st->npt,
-                       c_arena, s);
+    if ((e = hipEventRecord(st->evj, st->side)) != hipSuccess) return e;
+    return hipStreamWaitEvent(s, st->evj, 0);
 }
 
 }  // namespace
@@ -259,6 +319,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         if ((e = upload(st, &dt, tl)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: tiles");
         qc.tiles = dt;
         qc.ntiles = (int)tl.size();
+        part_starts(tl, st->part_of, st->nparts, qc.tstart);
         qc.cfg = c;
         qc.cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>(qc.ntiles, c.grid));
     }
@@ -331,6 +392,23 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
     st->x_elems = xoff;
     st->c_elems = coff;
     st->phi_elems = poff;
+    // pipeline parts: contiguous function ranges of about equal sample bytes
+    // (LC_BATCH_PARTS = 1..4; one part by default: measured fastest on the
+    // uneven-batch and mixed-stream workloads)
+    {
+        int want = 1;
+        if (const char *ev = getenv("LC_BATCH_PARTS")) want = std::max(1, std::min(kParts, atoi(ev)));
+        st->nparts = B >= 4 * want ? want : 1;
+    }
+    st->part_of.assign(B, 0);
+    if (st->nparts > 1) {
+        int64_t acc = 0;
+        for (int b = 0; b < B; ++b) {
+            const int64_t sz = st->fn[b].H * st->fn[b].Q * (st->fn[b].prec == LC_FP64 ? 8 : 4);
+            st->part_of[b] = (int)std::min<int64_t>(st->nparts - 1, (acc + sz / 2) * st->nparts / std::max<int64_t>(1, foff));
+            acc += sz;
+        }
+    }
 
     // ---- shared tables
     for (auto &d : st->fn) {
@@ -422,6 +500,7 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         qc.fns = kv.second;
         std::vector<BatchTile> tiles = make_tiles(st->fn, qc.fns, quad_rows_per_block(qc.cfg));
         qc.ntiles = (int)tiles.size();
+        part_starts(tiles, st->part_of, st->nparts, qc.tstart);
         qc.cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>(qc.ntiles, (int64_t)cu * 8));
         chk(upload(st, &qc.tiles, tiles));
         st->classes.push_back(qc);
@@ -471,6 +550,16 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
             for (int64_t n = 0; n < f.N; n += 1024) pt.push_back({id, (int32_t)n});
             big.push_back(f);
         }
+        auto starts = [&](const std::vector<BigTile> &v, int *out) {
+            int k = 0;
+            out[0] = 0;
+            for (int t = 0; t < (int)v.size(); ++t)
+                while (k < st->nparts - 1 && st->part_of[st->large[v[t].fn]] > k) out[++k] = t;
+            while (k < st->nparts) out[++k] = (int)v.size();
+        };
+        starts(ct, st->cst);
+        starts(rt, st->rst);
+        starts(pt, st->pst);
         chk(upload(st, &st->dbig, big));
         chk(upload(st, &st->ctiles, ct));
         chk(upload(st, &st->rtiles, rt));
@@ -483,9 +572,20 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         DstGroup g;
         g.threads = kv.first <= 512 ? 64 : (kv.first <= 2048 ? 256 : 1024);
         auto v = kv.second;
-        std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return st->fn[a].L > st->fn[b].L; });
-        g.Lmax = (int)st->fn[v[0]].L;
+        std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+            if (st->part_of[a] != st->part_of[b]) return st->part_of[a] < st->part_of[b];
+            return st->fn[a].L > st->fn[b].L;
+        });
+        g.Lmax = 0;
+        for (int b : v) g.Lmax = std::max<int>(g.Lmax, (int)st->fn[b].L);
         g.n = (int)v.size();
+        {
+            int k = 0;
+            g.lstart[0] = 0;
+            for (int i = 0; i < g.n; ++i)
+                while (k < st->nparts - 1 && st->part_of[v[i]] > k) g.lstart[++k] = i;
+            while (k < st->nparts) g.lstart[++k] = g.n;
+        }
         std::vector<int32_t> list(v.begin(), v.end());
         chk(upload(st, &g.list, list));
         chk(prepare_bdst(g.threads, g.Lmax));
@@ -494,6 +594,13 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
     if (e != hipSuccess) {
         free_state(st);
         return fail_status(LC_ERR_HIP, std::string("lc_plan_batch: setup failed: ") + hipGetErrorString(e));
+    }
+    chk(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking));
+    for (int k = 0; k < kParts; ++k) chk(hipEventCreateWithFlags(&st->evq[k], hipEventDisableTiming));
+    chk(hipEventCreateWithFlags(&st->evj, hipEventDisableTiming));
+    if (e != hipSuccess) {
+        free_state(st);
+        return fail_status(LC_ERR_HIP, std::string("lc_plan_batch: stream/event setup: ") + hipGetErrorString(e));
     }
     lc_plan_s *p = new (std::nothrow) lc_plan_s();
     if (!p) {
@@ -546,7 +653,7 @@ lc_status lc_execute_batch(lc_plan_t p, const void *f_arena, double *c_arena, hi
         }
         e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_batch: begin capture: ") + hipGetErrorString(e));
-        hipError_t el = launch_all(p, st, f_arena, c_arena, stream, false);
+        hipError_t el = launch_pipeline(st, f_arena, c_arena, stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(stream, &g);
         if (el != hipSuccess || e != hipSuccess) {
