@@ -12,7 +12,8 @@ twist, FFT and rescale over one resident batch of samples):
 
 Other workloads (--workload): single_small (N=64, M=256, Q=32), batch
 (4096 ragged random Legendre series, Q=48), gemm (Abel-as-GEMM, P=4096,
-B=16384), stream (65536-function Pareto mix).
+B=16384; --form direct: the direct Legendre-matrix product), stream
+(65536-function Pareto mix).
 
 Prints one JSON line.  ``roofline`` is for the dominant kernel, timed with
 HIP events that the library records around it on the execute stream;
@@ -332,7 +333,8 @@ def run_gemm(args):
     B, P, M, N, deg = 16384, 4096, 8192, 4096, 3000
     mode = args.mode
     coef = W.gemm_batch_coeffs(B, deg, seed=4)
-    g = lc.plan_gemm(P, M, N, mode)
+    direct = args.form == "direct"
+    g = (lc.plan_legendre_matrix if direct else lc.plan_gemm)(P, M, N, mode)
     F = series_grid(coef, g.nodes)
     C = torch.empty((B, N), dtype=torch.float64, device="cuda")
     step = lambda: g.execute(F, C)
@@ -343,8 +345,8 @@ def run_gemm(args):
     _sync()
     kms, cnt = g.kernel_ms()
     g.set_timing(False)
-    H = g.info["H"]
-    flops = 2.0 * B * H * P * NPROD[mode]
+    R = N if direct else g.info["H"]  # rows of the matrix operand
+    flops = 2.0 * B * R * P * NPROD[mode]
     achieved = flops / (kms * 1e-3) / 1e12
     # accuracy of this run on 256 sampled functions (true coefficients known)
     sel = np.random.default_rng(41).choice(B, 256, replace=False)
@@ -359,11 +361,14 @@ def run_gemm(args):
     line = {"metric": METRIC, "value": B * N / sec, "unit": "coefficients/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": {"fp64": "f64"}.get(mode, f"{mode[:4]} pieces, f32 accumulate, f64 DST"),
+            "dtype": {"fp64": "f64"}.get(mode, f"{mode[:4]} pieces, f32 accumulate, "
+                                               + ("f64 output" if direct else "f64 DST")),
             "data": "synthetic",
-            "config": {"workload": f"Abel-as-GEMM, P=4096 Chebyshev-Gauss samples, B=16384 random Legendre "
+            "config": {"workload": ("direct Legendre matrix" if direct else "Abel-as-GEMM")
+                                   + f", P=4096 Chebyshev-Gauss samples, B=16384 random Legendre "
                                    f"series of degree 3000, M=8192, N=4096, mode {mode}",
-                       "B": B, "P": P, "M": M, "N": N, "mode": mode, "E_a": E_a, "E_c": E_c},
+                       "B": B, "P": P, "M": M, "N": N, "mode": mode, "form": args.form,
+                       "E_a": E_a, "E_c": E_c},
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                          "frac": achieved / peak, "traffic": None,
                          "kernel": "k_mgemm (split-precision MFMA product)" if mode != "fp64" else "rocblas dgemm",
@@ -400,6 +405,8 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the default launch shapes instead of the autotuner's")
     ap.add_argument("--mode", default="bf16x3", help="gemm mode")
+    ap.add_argument("--form", default="abel", choices=["abel", "direct"],
+                    help="gemm workload: Abel product + batched FFT, or the direct Legendre matrix")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -74,7 +74,12 @@ typedef enum {
     LC_GEMM_FP16X1 = 4   /* one scaled fp16 piece each: one product                */
 } lc_gemm_mode;
 
-typedef enum { LC_PLAN_SINGLE = 0, LC_PLAN_BATCH = 1, LC_PLAN_GEMM = 2 } lc_plan_kind;
+typedef enum {
+    LC_PLAN_SINGLE = 0,
+    LC_PLAN_BATCH = 1,
+    LC_PLAN_GEMM = 2,            /* Abel product + batched twist/FFT/rescale     */
+    LC_PLAN_LEGENDRE_MATRIX = 3  /* one product with the full N x P matrix       */
+} lc_plan_kind;
 
 typedef struct lc_plan_s *lc_plan_t;
 
@@ -115,8 +120,8 @@ lc_status lc_plan_info(lc_plan_t plan, lc_plan_desc *desc);
  * lc_plan_destroy.  Single plans: x[H][Q] row-major FP64, row r holds
  * y_{r+1} = pi (r+1)/H; the caller writes f(x[r][q]) into f[r][q].
  * Batch plans: the node arena, function b at element offset x_off[b] (see
- * lc_plan_batch_offsets), laid out like a single plan.  GEMM plans: the P
- * Chebyshev-Gauss nodes x_p = cos((2p+1) pi / (2P)).
+ * lc_plan_batch_offsets), laid out like a single plan.  GEMM and
+ * Legendre-matrix plans: the P Chebyshev-Gauss nodes x_p = cos((2p+1) pi / (2P)).
  * rows / Q may be null.  Errors: LC_ERR_INVALID. */
 lc_status lc_plan_nodes(lc_plan_t plan, const double **x_dev, int64_t *rows, int32_t *Q);
 
@@ -162,6 +167,23 @@ lc_status lc_execute_batch(lc_plan_t plan, const void *f_arena, double *c_arena,
  * M/2 >= N, N >= 1.  Errors: LC_ERR_INVALID, LC_ERR_NOMEM, LC_ERR_HIP. */
 lc_status lc_plan_gemm(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_plan_t *out);
 
+/* Direct Legendre-matrix plan on the same fixed grid.  For a fixed grid the
+ * whole map from samples to coefficients (Abel step, twist, the FFT of
+ * eq. (2.4) and the (2n+1) rescale) is linear, i.e. one N x P matrix
+ *   Lmat = D A,
+ * with A the product-integration matrix above and D the map phi -> c of
+ * eq. (2.4) on the M-point grid.  Lmat is built once in FP64 on the device
+ * by applying the plan's FP64 twist/DST/rescale to the columns of A, so
+ * that it equals the Legendre coefficients of the Lagrange cardinal
+ * polynomials of the grid whenever the method is exact for them
+ * (M >= N + P).  Each execute is then a single product C = F^T Lmat^T,
+ * with no FFT; the split modes accumulate the piece products in FP32 on
+ * MFMA and write finished FP64 coefficients.  The plan is executed, sized
+ * and destroyed with the GEMM calls (lc_execute_gemm, lc_plan_gemm_reserve,
+ * lc_plan_destroy); lc_plan_info reports kind LC_PLAN_LEGENDRE_MATRIX.
+ * Arguments and errors as lc_plan_gemm. */
+lc_status lc_plan_legendre_matrix(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_plan_t *out);
+
 /* Executes a GEMM plan on B functions: F_dev device FP64 [P][B] (row p holds
  * f_b(x_p) for every b), C_dev device FP64 [B][N].  B <= the plan's
  * capacity (lc_plan_gemm_reserve, default 16384).  Asynchronous on stream.
@@ -173,8 +195,10 @@ lc_status lc_execute_gemm(lc_plan_t plan, const double *F_dev, int32_t B, double
  * Errors: LC_ERR_INVALID, LC_ERR_NOMEM. */
 lc_status lc_plan_gemm_reserve(lc_plan_t plan, int32_t B_max);
 
-/* Device pointer to the GEMM plan's FP64 product-integration matrix A,
- * [H+1][P] row-major (row 0, y = 0, is zero), valid until destroy.
+/* Device pointer to the GEMM plan's FP64 matrix, valid until destroy:
+ * the product-integration matrix A, [H+1][P] row-major (row 0, y = 0, is
+ * zero), for lc_plan_gemm plans; the transposed Legendre matrix Lmat^T,
+ * [P][N] row-major, for lc_plan_legendre_matrix plans.
  * Errors: LC_ERR_INVALID. */
 lc_status lc_plan_gemm_matrix(lc_plan_t plan, const double **A_dev);
 

@@ -20,7 +20,7 @@ import ctypes as C
 from ._lib import (GEMM_MODES, LC_FP32_QUAD, LC_FP64, PRECISIONS, LCError,  # noqa: F401
                    PlanDesc, check, load)
 
-__all__ = ["grid_size", "plan", "plan_batch", "plan_gemm", "Plan", "LCError"]
+__all__ = ["grid_size", "plan", "plan_batch", "plan_gemm", "plan_legendre_matrix", "Plan", "LCError"]
 
 
 def _torch():
@@ -147,4 +147,4 @@ def plan(N: int, M: int, Q: int, precision: str = "fp64") -> Plan:
 
 
 from .batch import BatchPlan, plan_batch  # noqa: E402,F401
-from .gemm import GemmPlan, plan_gemm  # noqa: E402,F401
+from .gemm import GemmPlan, plan_gemm, plan_legendre_matrix  # noqa: E402,F401

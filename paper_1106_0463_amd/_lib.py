@@ -38,6 +38,7 @@ SIGNATURES = [
     ("lc_plan_batch_offsets", C.c_int, [_vp, _pi64, _pi64, _pi64]),
     ("lc_execute_batch", C.c_int, [_vp, _vp, _vp, _vp]),
     ("lc_plan_gemm", C.c_int, [_i32, _i64, _i64, C.c_int, C.POINTER(_vp)]),
+    ("lc_plan_legendre_matrix", C.c_int, [_i32, _i64, _i64, C.c_int, C.POINTER(_vp)]),
     ("lc_execute_gemm", C.c_int, [_vp, _vp, _i32, _vp, _vp]),
     ("lc_plan_gemm_reserve", C.c_int, [_vp, _i32]),
     ("lc_plan_gemm_matrix", C.c_int, [_vp, C.POINTER(_vp)]),

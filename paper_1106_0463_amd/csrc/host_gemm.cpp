@@ -7,10 +7,17 @@
 // Precision modes: FP64 (rocBLAS DGEMM, the FP64 comparator) or split
 // 16-bit pieces with FP32 accumulation on MFMA (hand-written kernel fusing
 // the piece products); the DST and the (2n+1) rescale are FP64 in all modes.
+//
+// Direct Legendre-matrix plans fold the twist/DST/rescale into the matrix:
+// Lmat = D A (N x P), D the map phi -> c of eq. (2.4) on the M-grid, built
+// once in FP64 by running the batched FP64 DST over the columns of A.  An
+// execute is then the single product C = F^T Lmat^T with finished FP64
+// coefficients written by the product's epilogue.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <type_traits>
 #include <new>
@@ -29,7 +36,11 @@ hipError_t timing_end(lc_plan_s *p, hipStream_t s, int slot);
 namespace {
 
 struct GemmState {
-    int P = 0, ldk = 0, QA = 0, mode = 0;
+    int P = 0, Kp = 0, QA = 0, mode = 0;
+    int direct = 0;  // direct Legendre-matrix form
+    int64_t R = 0;   // rows of the Y operand: H (Abel form) or N (direct)
+    double *LT = nullptr;  // direct form: Lmat^T [P][N] FP64
+    int64_t Hpad = 0, Bpad = 0;  // operand rows padded to the MFMA block tile
     int h16 = kBF16, npc = 1, kmode = 1, scaled = 0;
     int64_t N = 0, M = 0, M_eff = 0, H = 0, L = 0;
     double *xc = nullptr, *lam = nullptr, *A = nullptr;
@@ -84,14 +95,15 @@ hipError_t reserve(GemmState *g, int B) {
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     if (g->mode == LC_GEMM_FP64) {
-        chk(galloc(g, &g->Out64, (size_t)B * g->H, true));
+        if (!g->direct) chk(galloc(g, &g->Out64, (size_t)B * g->H, true));
     } else {
+        // the split writes every padded row and k of the pieces it uses
         unsigned short *x = nullptr;
-        chk(galloc(g, &x, (size_t)g->npc * B * g->ldk, true));
+        g->Bpad = ((int64_t)B + kGemmBM - 1) / kGemmBM * kGemmBM;
+        chk(galloc(g, &x, (size_t)g->npc * g->Bpad * g->Kp, true));
         g->X = x;
-        if (e == hipSuccess && g->ldk != g->P) chk(hipMemset(x, 0, (size_t)g->npc * B * g->ldk * 2));
         chk(galloc(g, &g->colexp, (size_t)B, true));
-        chk(galloc(g, &g->Out32, (size_t)B * g->H, true));
+        if (!g->direct) chk(galloc(g, &g->Out32, (size_t)B * g->H, true));
     }
     if (e == hipSuccess) g->Bmax = B;
     return e;
@@ -106,6 +118,7 @@ void destroy_gemm(lc_plan_s *p) {
 
 void info_gemm(lc_plan_s *p, lc_plan_desc *d) {
     GemmState *g = (GemmState *)p->ext;
+    if (g->direct) d->kind = LC_PLAN_LEGENDRE_MATRIX;
     d->precision = g->mode;
     d->N = g->N;
     d->M = g->M;
@@ -130,20 +143,29 @@ lc_status nodes_gemm(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q) 
 
 using namespace lc;
 
-extern "C" {
+namespace {
 
-lc_status lc_plan_gemm(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_plan_t *out) {
-    if (!out) return fail_status(LC_ERR_INVALID, "lc_plan_gemm: out is null");
-    if (P < 2 || P > 16384) return fail_status(LC_ERR_INVALID, "lc_plan_gemm: P must be in [2, 16384]");
-    if (M < 2 || (M & 1)) return fail_status(LC_ERR_INVALID, "lc_plan_gemm: M must be even and >= 2");
-    if (N < 1 || N > M / 2) return fail_status(LC_ERR_INVALID, "lc_plan_gemm: need 1 <= N <= M/2");
-    if ((int)mode < LC_GEMM_FP64 || (int)mode > LC_GEMM_FP16X1)
-        return fail_status(LC_ERR_INVALID, "lc_plan_gemm: bad mode");
+lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, int direct, lc_plan_t *out,
+                           const char *fn) {
+    const std::string who = std::string(fn) + ": ";
+    if (!out) return fail_status(LC_ERR_INVALID, who + "out is null");
+    if (P < 2 || P > 16384) return fail_status(LC_ERR_INVALID, who + "P must be in [2, 16384]");
+    if (M < 2 || (M & 1)) return fail_status(LC_ERR_INVALID, who + "M must be even and >= 2");
+    if (N < 1 || N > M / 2) return fail_status(LC_ERR_INVALID, who + "need 1 <= N <= M/2");
+    if ((int)mode < LC_GEMM_FP64 || (int)mode > LC_GEMM_FP16X1) return fail_status(LC_ERR_INVALID, who + "bad mode");
     GemmState *g = new (std::nothrow) GemmState();
-    if (!g) return fail_status(LC_ERR_NOMEM, "lc_plan_gemm: host allocation failed");
-    if (const char *wm = getenv("LC_MGEMM_WM")) mgemm_wm = atoi(wm) == 2 ? 2 : 4;
+    if (!g) return fail_status(LC_ERR_NOMEM, who + "host allocation failed");
+    g->direct = direct;
+    if (const char *kc = getenv("LC_MGEMM_KCH")) mgemm_kch = atoi(kc) == 2 ? 2 : 4;
+    if (const char *st = getenv("LC_MGEMM_STAGES")) {
+        int ks = 0, ns = 0;
+        if (sscanf(st, "%d,%d", &ks, &ns) == 2) {
+            mgemm_ks = ks;
+            mgemm_ns = ns;
+        }
+    }
     g->P = P;
-    g->ldk = (P + 31) / 32 * 32;
+    g->Kp = (P + 31) / 32 * 32;
     g->QA = P / 2 + 8;
     g->mode = (int)mode;
     switch (mode) {
@@ -160,8 +182,9 @@ lc_status lc_plan_gemm(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_pl
     g->L = g->H / 2;
     if (g->L > kLdsFftMax) {
         free_gemm(g);
-        return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_gemm: M/4 beyond the LDS FFT length (8192)");
+        return fail_status(LC_ERR_UNSUPPORTED, who + "M/4 beyond the LDS FFT length (8192)");
     }
+    g->R = direct ? N : g->H;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     // Chebyshev-Gauss nodes and barycentric weights lam_p = (-1)^p sin((2p+1) pi / (2P))
@@ -196,15 +219,35 @@ lc_status lc_plan_gemm(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_pl
     up(&g->tw_fft, fft);
     chk(galloc(g, &g->A, (size_t)(g->H + 1) * P));
     if (e == hipSuccess) chk(launch_amat((int)g->H, P, g->QA, g->xc, g->lam, d_rowA, d_omt2, d_w, d_s2, g->A, 0));
+    if (e == hipSuccess && direct) {
+        // Lmat^T [P][N]: the FP64 twist/DST/rescale of every column of A
+        double *AT = nullptr;
+        chk(hipMalloc((void **)&AT, (size_t)P * g->H * sizeof(double)));
+        chk(galloc(g, &g->LT, (size_t)P * N));
+        if (e == hipSuccess) chk(launch_transpose_a(g->A, (int)g->H, P, AT, 0));
+        if (e == hipSuccess)
+            chk(launch_gdst(0, AT, (int)g->H, nullptr, nullptr, P, g->H, g->L, N, g->tw_pre, g->tw_pack, g->tw_fft,
+                            g->sched, g->LT, 0));
+        if (AT) {
+            hipError_t s2e = hipDeviceSynchronize();
+            if (e == hipSuccess) e = s2e;
+            hipFree(AT);
+        }
+    }
     if (e == hipSuccess && g->mode != LC_GEMM_FP64) {
         unsigned short *y = nullptr;
-        chk(galloc(g, &y, (size_t)g->npc * g->H * g->ldk));
+        g->Hpad = (g->R + 127) / 128 * 128;
+        chk(galloc(g, &y, (size_t)g->npc * g->Hpad * g->Kp));
         g->Y = y;
-        if (e == hipSuccess) chk(hipMemset(y, 0, (size_t)g->npc * g->H * g->ldk * 2));
-        chk(galloc(g, &g->rowexp, (size_t)g->H));
-        if (e == hipSuccess)
-            chk(launch_split_rows(g->h16, g->A, (int)g->H, P, g->ldk, g->npc, g->Y, (int64_t)g->H * g->ldk,
-                                  g->rowexp, g->scaled, 0));
+        chk(galloc(g, &g->rowexp, (size_t)g->R));
+        if (e == hipSuccess) {
+            if (direct)  // rows n of Lmat = columns of Lmat^T
+                chk(launch_split_rows(g->h16, g->LT, 0, 1, N, (int)N, P, g->Kp, (int)g->Hpad, g->npc, g->Y,
+                                      g->Hpad * g->Kp, g->rowexp, g->scaled, 0));
+            else  // rows 1..H of A
+                chk(launch_split_rows(g->h16, g->A, 1, P, 1, (int)g->H, P, g->Kp, (int)g->Hpad, g->npc, g->Y,
+                                      g->Hpad * g->Kp, g->rowexp, g->scaled, 0));
+        }
     }
     if (e == hipSuccess && g->mode == LC_GEMM_FP64) {
         if (rocblas_create_handle(&g->rb) != rocblas_status_success) e = hipErrorUnknown;
@@ -213,19 +256,30 @@ lc_status lc_plan_gemm(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_pl
     if (e == hipSuccess) chk(reserve(g, 16384));
     if (e != hipSuccess) {
         free_gemm(g);
-        return fail_status(e == hipErrorOutOfMemory ? LC_ERR_NOMEM : LC_ERR_HIP,
-                           std::string("lc_plan_gemm: ") + hipGetErrorString(e));
+        return fail_status(e == hipErrorOutOfMemory ? LC_ERR_NOMEM : LC_ERR_HIP, who + hipGetErrorString(e));
     }
     lc_plan_s *p = new (std::nothrow) lc_plan_s();
     if (!p) {
         free_gemm(g);
-        return fail_status(LC_ERR_NOMEM, "lc_plan_gemm: host allocation failed");
+        return fail_status(LC_ERR_NOMEM, who + "host allocation failed");
     }
     p->kind = LC_PLAN_GEMM;
     hipGetDevice(&p->device);
     p->ext = g;
     *out = p;
     return LC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lc_status lc_plan_gemm(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_plan_t *out) {
+    return plan_gemm_common(P, M, N, mode, 0, out, "lc_plan_gemm");
+}
+
+lc_status lc_plan_legendre_matrix(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, lc_plan_t *out) {
+    return plan_gemm_common(P, M, N, mode, 1, out, "lc_plan_legendre_matrix");
 }
 
 lc_status lc_plan_gemm_reserve(lc_plan_t p, int32_t B_max) {
@@ -242,7 +296,8 @@ lc_status lc_plan_gemm_reserve(lc_plan_t p, int32_t B_max) {
 
 lc_status lc_plan_gemm_matrix(lc_plan_t p, const double **A_dev) {
     if (!p || p->kind != LC_PLAN_GEMM || !A_dev) return fail_status(LC_ERR_INVALID, "lc_plan_gemm_matrix: bad argument");
-    *A_dev = ((GemmState *)p->ext)->A;
+    const GemmState *g = (const GemmState *)p->ext;
+    *A_dev = g->direct ? g->LT : g->A;
     return LC_OK;
 }
 
@@ -257,24 +312,34 @@ lc_status lc_execute_gemm(lc_plan_t p, const double *F_dev, int32_t B, double *C
         rocblas_set_stream(g->rb, stream);
         const double one = 1.0, zero = 0.0;
         if ((e = timing_begin(p, stream, &slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
-        // column-major: Out^T (H x B) = A[1:] (H x P) * F (P x B)
-        rocblas_status rs = rocblas_dgemm(g->rb, rocblas_operation_transpose, rocblas_operation_transpose, (int)g->H, B,
-                                          g->P, &one, g->A + g->P, g->P, F_dev, B, &zero, g->Out64, (int)g->H);
+        rocblas_status rs;
+        if (g->direct)  // column-major: C^T (N x B) = Lmat (N x P, stored as Lmat^T [P][N]) * F (P x B)
+            rs = rocblas_dgemm(g->rb, rocblas_operation_none, rocblas_operation_transpose, (int)g->N, B, g->P, &one,
+                               g->LT, (int)g->N, F_dev, B, &zero, C_dev, (int)g->N);
+        else  // column-major: Out^T (H x B) = A[1:] (H x P) * F (P x B)
+            rs = rocblas_dgemm(g->rb, rocblas_operation_transpose, rocblas_operation_transpose, (int)g->H, B, g->P,
+                               &one, g->A + g->P, g->P, F_dev, B, &zero, g->Out64, (int)g->H);
         if (rs != rocblas_status_success) return fail_status(LC_ERR_HIP, "lc_execute_gemm: rocblas_dgemm failed");
         if ((e = timing_end(p, stream, slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
+        if (g->direct) return LC_OK;
         e = launch_gdst(0, g->Out64, (int)g->H, nullptr, nullptr, B, g->H, g->L, g->N, g->tw_pre, g->tw_pack,
                         g->tw_fft, g->sched, C_dev, stream);
         if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: dst: ") + hipGetErrorString(e));
         return LC_OK;
     }
-    const int64_t xps = (int64_t)g->Bmax * g->ldk;
-    e = launch_split_cols(g->h16, F_dev, g->P, B, g->ldk, g->npc, g->X, xps, g->colexp, g->scaled, stream);
+    const int64_t xps = g->Bpad * g->Kp;
+    e = launch_split_cols(g->h16, F_dev, g->P, B, g->Kp, g->npc, g->X, xps, g->colexp, g->scaled, stream);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: split: ") + hipGetErrorString(e));
     if ((e = timing_begin(p, stream, &slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
-    e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, (int64_t)g->H * g->ldk, B, (int)g->H, g->ldk, g->Out32,
-                     (int)g->H, stream);
+    if (g->direct)
+        e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->N, g->Kp, nullptr, (int)g->N,
+                         C_dev, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, stream);
+    else
+        e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->H, g->Kp, g->Out32,
+                         (int)g->H, nullptr, nullptr, nullptr, stream);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: mfma: ") + hipGetErrorString(e));
     if ((e = timing_end(p, stream, slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
+    if (g->direct) return LC_OK;
     e = launch_gdst(1, g->Out32, (int)g->H, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, B, g->H,
                     g->L, g->N, g->tw_pre, g->tw_pack, g->tw_fft, g->sched, C_dev, stream);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: dst: ") + hipGetErrorString(e));

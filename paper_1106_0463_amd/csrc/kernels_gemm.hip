@@ -8,13 +8,15 @@
 // Kernels:
 //   k_amat        A in FP64, one workgroup per row j
 //   k_split_rows  A -> 16-bit pieces (bf16, or fp16 with a power-of-two row
-//                 scale), K-major [H][P]
-//   k_colmax / k_split_cols  F [P][B] FP64 -> pieces [B][P] (transposed)
+//                 scale, k_rowexp), in MFMA fragment order
+//   k_colmax / k_split_cols  F [P][B] FP64 -> pieces of F^T, fragment order
 //   k_mgemm       Out[b][j] = sum_{(u,v)} sum_p X_u[b][p] Y_v[j][p] on MFMA
 //                 (32x32x16, FP32 accumulation), fused over the piece
 //                 products of the precision mode
 //   k_gdst_lds    batched DST-III + rescale over the rows of Out
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "fft_lds.h"
 #include "lc_internal.h"
@@ -122,6 +124,19 @@ hipError_t launch_amat(int H, int P, int QA, const double *xc, const double *lam
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------- fragment order ---
+// Both 16-bit operands of the product are stored in the lane order of the
+// MFMA 32x32x16 operand fragment: element (row r, k) of a piece lives at
+//   ((r / 32) * K16 + k / 16) * 512 + ((r % 32) + 32 ((k / 8) % 2)) * 8 + k % 8
+// (halves; K16 = Kp / 16 with Kp = P rounded up to 32).  One fragment is then
+// 1 KiB in which lane l owns bytes [16 l, 16 l + 16): global loads, the
+// global->LDS copies and the LDS reads of the product are all 16 contiguous
+// bytes per lane, which no bank or channel pattern can split.  Rows are
+// padded to the block tile and k to Kp with zeros.
+__device__ __forceinline__ int64_t fo_offset(int64_t r, int k, int K16) {
+    return ((r >> 5) * K16 + (k >> 4)) * 512 + (((r & 31) + ((k >> 3) & 1) * 32) << 3) + (k & 7);
+}
+
 // --------------------------------------------------------------- splits ---
 // Piece extraction: v = sum of npc 16-bit pieces, each the nearest 16-bit
 // value of the remainder.  FP16 uses a power-of-two scale 2^-e per row (A)
@@ -141,43 +156,96 @@ template <> struct Round16<_Float16> {
     static __device__ __forceinline__ _Float16 from(float f) { return (_Float16)f; }  // IEEE RNE
 };
 
-template <typename H16>
-__device__ __forceinline__ void split_value(double v, int npc, H16 *out) {
-    double r = v;
-    for (int i = 0; i < npc; ++i) {
-        // the remainder r - piece is exact in FP64, so a piece that is not the
-        // nearest 16-bit value (double rounding through FP32) only shifts a
-        // few bits to the next piece
-        const H16 h = Round16<H16>::from((float)r);
-        out[i] = h;
-        r -= (double)(float)h;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Splits 8 consecutive-k values into npc pieces of 8 halves (16 bytes) each.
+template <typename H16, int NPC>
+__device__ __forceinline__ void split8(const double *v, u32x4 *out) {
+    H16 h[NPC][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        double r = v[e];
+#pragma unroll
+        for (int i = 0; i < NPC; ++i) {
+            // the remainder r - piece is exact in FP64, so a piece that is not
+            // the nearest 16-bit value (double rounding through FP32) only
+            // shifts a few bits to the next piece
+            const H16 p = Round16<H16>::from((float)r);
+            h[i][e] = p;
+            r -= (double)(float)p;
+        }
     }
+#pragma unroll
+    for (int i = 0; i < NPC; ++i) out[i] = __builtin_bit_cast(u32x4, h[i]);
 }
 
-// A rows 1..H -> pieces Y_i[j-1][p]; fp16: scale row by 2^-e_j (e_j from the
-// row's max |A|), exponent stored in rowexp[j-1].
-template <typename H16>
-__global__ __launch_bounds__(256) void k_split_rows(const double *__restrict__ A, int H, int P, int ldk, int npc,
-                                                    H16 *__restrict__ Y, int64_t piece_stride,
-                                                    int *__restrict__ rowexp, int scaled) {
+// The Y operand is an FP64 matrix with rows r = 0..H-1 and columns k = 0..P-1
+// read as S[(r + roff) rs + k cs]: the product-integration matrix A without
+// its zero row (roff = 1, rs = P, cs = 1), or the direct Legendre matrix
+// stored transposed (roff = 0, rs = 1, cs = N).
+struct Strided {
+    const double *p;
+    int64_t roff, rs, cs;
+    __device__ __forceinline__ double at(int64_t r, int64_t k) const { return p[(r + roff) * rs + k * cs]; }
+};
+
+// rowexp[r] = ilogb(max_k |S[r][k]|) + 1 (0 for a zero row): one block per row.
+__global__ __launch_bounds__(256) void k_rowexp(Strided S, int P, int *__restrict__ rowexp) {
     __shared__ double red[4];
-    const int j = blockIdx.x;  // output row (A row j + 1)
-    const double *a = A + (int64_t)(j + 1) * P;
+    const int r = blockIdx.x;
     double m = 0.0;
-    for (int p = threadIdx.x; p < P; p += 256) m = fmax(m, fabs(a[p]));
+    for (int k = threadIdx.x; k < P; k += 256) m = fmax(m, fabs(S.at(r, k)));
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
     m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    int ex = 0;
-    if (scaled && m > 0.0) ex = ilogb(m) + 1;  // |a| 2^-ex < 1
-    if (threadIdx.x == 0 && rowexp) rowexp[j] = ex;
-    const double sc = ldexp(1.0, -ex);
-    for (int p = threadIdx.x; p < P; p += 256) {
-        H16 pcs[3];
-        split_value<H16>(a[p] * sc, npc, pcs);
-        for (int i = 0; i < npc; ++i) Y[i * piece_stride + (int64_t)j * ldk + p] = pcs[i];
+    if (threadIdx.x == 0) rowexp[r] = m > 0.0 ? ilogb(m) + 1 : 0;
+}
+
+// S -> pieces Y_i in fragment order over Hpad rows; one thread per 8
+// consecutive k of one row; rows >= H and k >= P are zero.
+template <typename H16, int NPC>
+__global__ __launch_bounds__(256) void k_split_rows(Strided S, int H, int P, int K16, int64_t nfrag,
+                                                    H16 *__restrict__ Y, int64_t piece_stride,
+                                                    const int *__restrict__ rowexp) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t frag = t >> 6;
+    if (frag >= nfrag) return;
+    const int lane = (int)(t & 63);
+    const int64_t r = (frag / K16) * 32 + (lane & 31);
+    const int k = (int)(frag % K16) * 16 + (lane >> 5) * 8;
+    double v[8];
+    const double sc = (rowexp && r < H) ? ldexp(1.0, -rowexp[r]) : 1.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (r < H && k + e < P) ? S.at(r, k + e) * sc : 0.0;
+    u32x4 out[NPC];
+    split8<H16, NPC>(v, out);
+#pragma unroll
+    for (int i = 0; i < NPC; ++i)
+        *reinterpret_cast<u32x4 *>(Y + i * piece_stride + fo_offset(r, k, K16)) = out[i];
+}
+
+// AT[p][j] = A[j + 1][p] (the columns of A without its zero row, as rows):
+// 32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void k_transpose_a(const double *__restrict__ A, int H, int P,
+                                                     double *__restrict__ AT) {
+    __shared__ double tile[32][33];
+    const int j0 = blockIdx.y * 32, p0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int i = ty; i < 32; i += 8) {
+        const int j = j0 + i, p = p0 + tx;
+        tile[i][tx] = (j < H && p < P) ? A[(int64_t)(j + 1) * P + p] : 0.0;
     }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        const int p = p0 + i, j = j0 + tx;
+        if (p < P && j < H) AT[(int64_t)p * H + j] = tile[tx][i];
+    }
+}
+
+hipError_t launch_transpose_a(const double *A, int H, int P, double *AT, hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose_a, dim3((P + 31) / 32, (H + 31) / 32), dim3(256), 0, s, A, H, P, AT);
+    return hipGetLastError();
 }
 
 // per-function exponent colexp[b] = ilogb(max_p |F[p][b]|) + 1: a fill, then
@@ -193,48 +261,76 @@ __global__ __launch_bounds__(256) void k_colmax(const double *__restrict__ F, in
     const int b = blockIdx.x * 256 + threadIdx.x;
     const int p0 = blockIdx.y * 64;
     if (b >= B) return;
-    double m = 0.0;
     const int p1 = p0 + 64 < P ? p0 + 64 : P;
-    for (int p = p0; p < p1; ++p) m = fmax(m, fabs(F[(int64_t)p * B + b]));
-    if (m > 0.0) atomicMax(colexp + b, ilogb(m) + 1);
+    double m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int p = p0;
+    for (; p + 8 <= p1; p += 8) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) m[e] = fmax(m[e], fabs(__builtin_nontemporal_load(F + (int64_t)(p + e) * B + b)));
+    }
+    for (; p < p1; ++p) m[0] = fmax(m[0], fabs(F[(int64_t)p * B + b]));
+    double mm = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) mm = fmax(mm, m[e]);
+    if (mm > 0.0) atomicMax(colexp + b, ilogb(mm) + 1);
 }
 
-// F [P][B] -> pieces X_i[b][p] through a 64x64 LDS transpose tile.
-template <typename H16>
-__global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F, int P, int B, int ldk, int npc,
+// F [P][B] -> pieces X_i in fragment order over Bpad rows (function b is
+// row b); one thread per (b, 8 consecutive p).  Fragments are numbered with
+// the row block fastest, so that the waves resident together read long
+// contiguous stretches of the same rows of F.
+template <typename H16, int NPC>
+__global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F, int P, int B, int K16, int RB,
                                                     H16 *__restrict__ X, int64_t piece_stride,
                                                     const int *__restrict__ colexp) {
-    __shared__ double tile[64][65];
-    const int p0 = blockIdx.y * 64, b0 = blockIdx.x * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int i = ty; i < 64; i += 4) {
-        const int p = p0 + i, b = b0 + tx;
-        tile[i][tx] = (p < P && b < B) ? F[(int64_t)p * B + b] : 0.0;
-    }
-    __syncthreads();
-    for (int i = ty; i < 64; i += 4) {
-        const int b = b0 + i, p = p0 + tx;
-        if (b < B && p < P) {
-            const double sc = colexp ? ldexp(1.0, -max(colexp[b], -1000)) : 1.0;
-            H16 pcs[3];
-            split_value<H16>(tile[tx][i] * sc, npc, pcs);
-            for (int k = 0; k < npc; ++k) X[k * piece_stride + (int64_t)b * ldk + p] = pcs[k];
-        }
-    }
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t frag = t >> 6;
+    if (frag >= (int64_t)RB * K16) return;
+    const int lane = (int)(t & 63);
+    const int rb = (int)(frag % RB), k16 = (int)(frag / RB);
+    const int b = rb * 32 + (lane & 31);
+    const int k = k16 * 16 + (lane >> 5) * 8;
+    double v[8];
+    const double sc = (colexp && b < B) ? ldexp(1.0, -max(colexp[b], -1000)) : 1.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        v[e] = (b < B && k + e < P) ? __builtin_nontemporal_load(F + (int64_t)(k + e) * B + b) * sc : 0.0;
+    u32x4 out[NPC];
+    split8<H16, NPC>(v, out);
+#pragma unroll
+    for (int i = 0; i < NPC; ++i)
+        *reinterpret_cast<u32x4 *>(X + i * piece_stride + fo_offset(b, k, K16)) = out[i];
 }
 
-hipError_t launch_split_rows(int h16, const double *A, int H, int P, int ldk, int npc, void *Y,
-                             int64_t piece_stride, int *rowexp, int scaled, hipStream_t s) {
-    if (h16 == kBF16)
-        hipLaunchKernelGGL(k_split_rows<__bf16>, dim3(H), dim3(256), 0, s, A, H, P, ldk, npc, (__bf16 *)Y,
-                           piece_stride, rowexp, scaled);
-    else
-        hipLaunchKernelGGL(k_split_rows<_Float16>, dim3(H), dim3(256), 0, s, A, H, P, ldk, npc, (_Float16 *)Y,
-                           piece_stride, rowexp, scaled);
-    return hipGetLastError();
+hipError_t launch_split_rows(int h16, const double *S, int64_t roff, int64_t rs, int64_t cs, int H, int P, int Kp,
+                             int Hpad, int npc, void *Y, int64_t piece_stride, int *rowexp, int scaled,
+                             hipStream_t s) {
+    const Strided st{S, roff, rs, cs};
+    if (scaled) {
+        hipLaunchKernelGGL(k_rowexp, dim3(H), dim3(256), 0, s, st, P, rowexp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int K16 = Kp / 16;
+    const int64_t nfrag = (int64_t)(Hpad / 32) * K16;
+    const dim3 grid((unsigned)((nfrag * 64 + 255) / 256));
+    const int *re = scaled ? rowexp : nullptr;
+#define LC_SR(T, NP)                                                                                     \
+    if (npc == NP) {                                                                                     \
+        hipLaunchKernelGGL((k_split_rows<T, NP>), grid, dim3(256), 0, s, st, H, P, K16, nfrag, (T *)Y,  \
+                           piece_stride, re);                                                            \
+        return hipGetLastError();                                                                        \
+    }
+    if (h16 == kBF16) {
+        LC_SR(__bf16, 1) LC_SR(__bf16, 2) LC_SR(__bf16, 3)
+    } else {
+        LC_SR(_Float16, 1) LC_SR(_Float16, 2) LC_SR(_Float16, 3)
+    }
+#undef LC_SR
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_split_cols(int h16, const double *F, int P, int B, int ldk, int npc, void *X,
+hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int npc, void *X,
                              int64_t piece_stride, int *colexp, int scaled, hipStream_t s) {
     if (scaled) {
         hipLaunchKernelGGL(k_colexp_init, dim3((B + 255) / 256), dim3(256), 0, s, B, colexp);
@@ -244,27 +340,35 @@ hipError_t launch_split_cols(int h16, const double *F, int P, int B, int ldk, in
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    dim3 grid((B + 63) / 64, (P + 63) / 64);
-    if (h16 == kBF16)
-        hipLaunchKernelGGL(k_split_cols<__bf16>, grid, dim3(256), 0, s, F, P, B, ldk, npc, (__bf16 *)X,
-                           piece_stride, scaled ? colexp : nullptr);
-    else
-        hipLaunchKernelGGL(k_split_cols<_Float16>, grid, dim3(256), 0, s, F, P, B, ldk, npc, (_Float16 *)X,
-                           piece_stride, scaled ? colexp : nullptr);
-    return hipGetLastError();
+    const int K16 = Kp / 16;
+    const int RB = (B + kGemmBM - 1) / kGemmBM * (kGemmBM / 32);  // row blocks up to the padded B
+    const dim3 grid((unsigned)(((int64_t)RB * K16 * 64 + 255) / 256));
+    const int *ce = scaled ? colexp : nullptr;
+#define LC_SC(T, NP)                                                                                     \
+    if (npc == NP) {                                                                                     \
+        hipLaunchKernelGGL((k_split_cols<T, NP>), grid, dim3(256), 0, s, F, P, B, K16, RB, (T *)X,      \
+                           piece_stride, ce);                                                            \
+        return hipGetLastError();                                                                        \
+    }
+    if (h16 == kBF16) {
+        LC_SC(__bf16, 1) LC_SC(__bf16, 2) LC_SC(__bf16, 3)
+    } else {
+        LC_SC(_Float16, 1) LC_SC(_Float16, 2) LC_SC(_Float16, 3)
+    }
+#undef LC_SC
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------ MFMA GEMM ---
-// Block tile 128 (b) x 128 (j), 4 waves in 2x2, each wave 64x64 = 2x2
-// MFMA 32x32x16 tiles (16 FP32 accumulators each).  K advances 32 per LDS
-// stage; all pieces of both operands for the stage are staged in LDS (rows
-// padded to 40 halves = 80 B so that 16-byte fragment reads by 32
-// consecutive rows spread over the banks); the next stage is prefetched
-// into registers during the MFMAs.  Requires P % 32 == 0 (the host pads).
+// Block tile 128 (b) x 128 (j), 4 waves in 2 x 2, each wave 64 x 64 = 2 x 2
+// MFMA 32x32x16 tiles.  K advances KS per stage through a ring of NS LDS
+// stages filled by direct global->LDS copies (16 bytes per lane, one 1 KiB
+// fragment per wave instruction): the copy of stage kt + NS - 1 is issued
+// while stage kt is multiplied, and each wave waits only for the copies of
+// the stage it is about to read.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename H16> struct Mfma;
 template <> struct Mfma<__bf16> {
@@ -280,8 +384,6 @@ template <> struct Mfma<_Float16> {
     }
 };
 
-constexpr int GBM = 128, GBN = 128, GBK = 32, GLD = 40;  // LDS row: 40 halves
-
 // Piece products of each mode (u indexes X pieces, v indexes Y pieces):
 //   1: (0,0)                 one 16-bit product
 //   3: (0,0) (1,0) (0,1)     hi*hi + lo*hi + hi*lo
@@ -294,72 +396,75 @@ template <> struct Prods<6> {
     static constexpr int u[6] = {0, 1, 0, 2, 1, 0}, v[6] = {0, 0, 1, 0, 1, 2};
 };
 
-template <typename H16, int MODE, int WM>
-__global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mgemm(
-    const H16 *__restrict__ X, int64_t xps, const H16 *__restrict__ Y, int64_t yps, int Bn, int Hn, int P,
-    float *__restrict__ Out, int ldo) {
-    // block tile (64 WM) x 128: WM x 2 waves, each wave 64 x 64
+// s_waitcnt immediate that waits for at most n outstanding vector-memory
+// operations and leaves the other counters alone.
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+constexpr int kLgkmZero = 15 | (3 << 14) | (7 << 4);  // lgkmcnt(0) only
+
+// Workgroup barrier that orders the LDS accesses around it (compiler fence
+// plus s_barrier) without the full memory fence of __syncthreads, whose
+// vmcnt(0) would drain the copies in flight for later stages.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(kLgkmZero);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Epilogue: D64 = false writes the FP32 sums to Out[b][j]; D64 = true writes
+// FP64 C[b][j] = sum * 2^(rowexp[j] + colexp[b]) (exponent arrays may be
+// null), the finished coefficients of the direct Legendre-matrix form.
+template <typename H16, int MODE, int KS, int NS, bool D64, int KCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mgemm(
+    const H16 *__restrict__ X, int64_t xps, const H16 *__restrict__ Y, int64_t yps, int Bn, int Hn, int K16,
+    float *__restrict__ Out, int ldo, double *__restrict__ C64, const int *__restrict__ rowexp,
+    const int *__restrict__ colexp) {
     using PR = Prods<MODE>;
     constexpr int NX = PR::nx, NY = PR::ny;
-    constexpr int BM = 64 * WM, NT = 128 * WM;
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    H16 *sx = reinterpret_cast<H16 *>(smem);               // [NX][BM * GLD]
-    H16 *sy = sx + NX * BM * GLD;                            // [NY][GBN * GLD]
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    // tile coordinates, j fastest so that consecutive blocks share the X rows
-    const int ntn = (Hn + GBN - 1) / GBN;
-    const int bm0 = (blockIdx.x / ntn) * BM, bn0 = (blockIdx.x % ntn) * GBN;
+    constexpr int KF = KS / 16;                        // fragments along k per stage
+    constexpr int FX = NX * 4 * KF, FY = NY * 4 * KF;  // fragments per stage (4 row blocks of 32)
+    constexpr int FST = FX + FY;
+    static_assert(FST % 4 == 0, "stage fragments must split over 4 waves");
+    constexpr int DPW = FST / 4;  // copies per wave per stage
+    static_assert(DPW * (NS - 2) < 64, "vmcnt range");
+    extern __shared__ __attribute__((aligned(1024))) u32x4 ring[];  // [NS][FST][64]
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: the copies' LDS base
+    const int wm = (wave >> 1) * 2, wn = (wave & 1) * 2;  // row blocks of 32 owned by the wave
+    const int ntn = (Hn + 127) / 128;
+    const int rbx = (blockIdx.x / ntn) * 4, rby = (blockIdx.x % ntn) * 4;  // first row blocks of X and Y
 
-    // global -> register staging: a tile row is 32 halves = 4 chunks of 16 B
-    constexpr int CX = BM * 4 / NT, CY = GBN * 4 / NT;  // chunks per thread
-    u32x4 rx[NX][CX], ry[NY][CY];
-    auto gload = [&](int k0) {
+    // copy d of a stage (d = wave + 4 i): X fragments first (piece, row
+    // block, k fragment), then Y fragments
+    auto issue = [&](int kt) {
+        u32x4 *st = ring + (kt % NS) * FST * 64;
 #pragma unroll
-        for (int c = 0; c < CX; ++c) {
-            const int idx = tid + NT * c;
-            const int row = idx >> 2, col = (idx & 3) * 8;
-            const int gb = bm0 + row;
-#pragma unroll
-            for (int u = 0; u < NX; ++u)
-                rx[u][c] = gb < Bn ? *reinterpret_cast<const u32x4 *>(X + u * xps + (int64_t)gb * P + k0 + col)
-                                   : (u32x4)(0u);
-        }
-#pragma unroll
-        for (int c = 0; c < CY; ++c) {
-            const int idx = tid + NT * c;
-            const int row = idx >> 2, col = (idx & 3) * 8;
-            const int gj = bn0 + row;
-#pragma unroll
-            for (int v = 0; v < NY; ++v)
-                ry[v][c] = gj < Hn ? *reinterpret_cast<const u32x4 *>(Y + v * yps + (int64_t)gj * P + k0 + col)
-                                   : (u32x4)(0u);
-        }
-    };
-    auto sstore = [&]() {
-#pragma unroll
-        for (int c = 0; c < CX; ++c) {
-            const int idx = tid + NT * c;
-            const int row = idx >> 2, col = (idx & 3) * 8;
-#pragma unroll
-            for (int u = 0; u < NX; ++u) *reinterpret_cast<u32x4 *>(&sx[u * BM * GLD + row * GLD + col]) = rx[u][c];
-        }
-#pragma unroll
-        for (int c = 0; c < CY; ++c) {
-            const int idx = tid + NT * c;
-            const int row = idx >> 2, col = (idx & 3) * 8;
-#pragma unroll
-            for (int v = 0; v < NY; ++v) *reinterpret_cast<u32x4 *>(&sy[v * GBN * GLD + row * GLD + col]) = ry[v][c];
+        for (int i = 0; i < DPW; ++i) {
+            const int d = wave + 4 * i;
+            const H16 *src;
+            if (d < FX) {
+                const int u = d / (4 * KF), r = (d / KF) % 4, kf = d % KF;
+                src = X + u * xps + ((int64_t)(rbx + r) * K16 + kt * KF + kf) * 512;
+            } else {
+                const int e = d - FX;
+                const int v = e / (4 * KF), r = (e / KF) % 4, kf = e % KF;
+                src = Y + v * yps + ((int64_t)(rby + r) * K16 + kt * KF + kf) * 512;
+            }
+            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(src + lane * 8),
+                                             (__attribute__((address_space(3))) void *)(st + d * 64), 16, 0, 0);
         }
     };
 
-    // Two-level accumulation: the MFMA accumulator covers one K chunk of
-    // KCH stages and is then added into a second FP32 total and cleared, so
-    // that no FP32 chain runs over more than KCH*GBK/16 MFMA steps per
-    // product (long chains of same-sign partial sums lose accuracy).
-    constexpr int KCH = 4;
-    f32x16 acc[2][2], tot[2][2];
+    // Two-level accumulation: the MFMA accumulator covers KCH K-steps of 16
+    // and is then added into a second total and cleared, so that no FP32
+    // chain runs over more than KCH MFMA steps per product (each step
+    // rounds relative to the running partial sum).  The total is FP32 for
+    // the Abel product (whose output is FP32; the DST that follows averages
+    // the errors of phi) and FP64 with shorter chunks for the direct form,
+    // where nothing averages the accumulation error of a coefficient.
+    using TotT = typename std::conditional<D64, double, float>::type;
+    f32x16 acc[2][2];
+    TotT tot[2][2][16];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -367,41 +472,32 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 acc[a][b][v] = 0.f;
-                tot[a][b][v] = 0.f;
+                tot[a][b][v] = 0;
             }
 
-    const int nk = P / GBK;
-    gload(0);
+    const int nk = K16 / KF;  // stages
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s)
+        if (s < nk) issue(s);
+    int kstep = 0;
     for (int kt = 0; kt < nk; ++kt) {
-        if (kt % KCH == 0 && kt > 0) {
+        // the copies of stage kt are the oldest of this wave's outstanding ones
+        if (kt + NS - 2 < nk) __builtin_amdgcn_s_waitcnt(vmcnt_imm(DPW * (NS - 2)));
+        else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        lds_barrier();  // every wave's copies of stage kt have landed; stage kt - 1 is free
+        if (kt + NS - 1 < nk) issue(kt + NS - 1);
+        const u32x4 *st = ring + (kt % NS) * FST * 64;
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    tot[a][b] += acc[a][b];
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
-                }
-        }
-        __syncthreads();
-        sstore();
-        __syncthreads();
-        if (kt + 1 < nk) gload((kt + 1) * GBK);
-#pragma unroll
-        for (int ks = 0; ks < GBK; ks += 16) {
-            // fragments: lane holds row (lane % 32), k = ks + 8 (lane / 32) + 0..7
-            const int fr = lane & 31, fk = ks + 8 * (lane >> 5);
+        for (int kf = 0; kf < KF; ++kf) {
             u32x4 fx[NX][2], fy[NY][2];
 #pragma unroll
             for (int u = 0; u < NX; ++u)
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-                    fx[u][a] = *reinterpret_cast<const u32x4 *>(&sx[u * BM * GLD + (wm + 32 * a + fr) * GLD + fk]);
+                for (int a = 0; a < 2; ++a) fx[u][a] = st[((u * 4 + wm + a) * KF + kf) * 64 + lane];
 #pragma unroll
             for (int v = 0; v < NY; ++v)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    fy[v][b] = *reinterpret_cast<const u32x4 *>(&sy[v * GBN * GLD + (wn + 32 * b + fr) * GLD + fk]);
+                for (int b = 0; b < 2; ++b) fy[v][b] = st[(FX + (v * 4 + wn + b) * KF + kf) * 64 + lane];
 #pragma unroll
             for (int pi = 0; pi < PR::n; ++pi)
 #pragma unroll
@@ -409,12 +505,26 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
                     for (int b = 0; b < 2; ++b)
                         acc[a][b] = Mfma<H16>::run(fx[PR::u[pi]][a], fy[PR::v[pi]][b], acc[a][b]);
+            if (++kstep == KCH) {
+                kstep = 0;
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) {
+                            tot[a][b][v] += (TotT)acc[a][b][v];
+                            acc[a][b][v] = 0.f;
+                        }
+            }
         }
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) tot[a][b] += acc[a][b];
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) tot[a][b][v] += (TotT)acc[a][b][v];
     // D layout: lane l, register v -> row 8 (v/4) + 4 (l/32) + (v%4), col l%32
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -422,41 +532,64 @@ __global__ __launch_bounds__(128 * WM) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int row = bm0 + wm + 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int col = bn0 + wn + 32 * b + (lane & 31);
-                if (row < Bn && col < Hn) Out[(int64_t)row * ldo + col] = tot[a][b][v];
+                const int row = (rbx + wm + a) * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int col = (rby + wn + b) * 32 + (lane & 31);
+                if (row < Bn && col < Hn) {
+                    if constexpr (D64) {
+                        const int ex = (rowexp ? rowexp[col] : 0) + (colexp ? max(colexp[row], -1000) : 0);
+                        C64[(int64_t)row * ldo + col] = ldexp(tot[a][b][v], ex);
+                    } else {
+                        Out[(int64_t)row * ldo + col] = tot[a][b][v];
+                    }
+                }
             }
 }
 
-int mgemm_wm = 2;  // waves along b per block (block tile 64*WM x 128); LC_MGEMM_WM overrides
+// stage depth (k per stage, ring length) of each mode: LDS per block is
+// NS * (NX + NY) * 4 * KS/16 KiB, at most 80 KiB so that two blocks share a CU
+int mgemm_ks = 0, mgemm_ns = 0;  // 0: the per-mode default; LC_MGEMM_STAGES="KS,NS" overrides
+int mgemm_kch = 0;  // FP64-total chunk of the direct form (2 or 4; 0: default 4); LC_MGEMM_KCH overrides
 
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
-                        int P, float *Out, int ldo, hipStream_t s) {
-    if (P % GBK) return hipErrorInvalidValue;
-    const int WM = mgemm_wm == 2 ? 2 : 4;
-    const int BM = 64 * WM;
-    const int grid = ((Bn + BM - 1) / BM) * ((Hn + GBN - 1) / GBN);
+                        int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
+                        hipStream_t s) {
+    if (Kp % 32) return hipErrorInvalidValue;
+    const int K16 = Kp / 16;
+    int KS = mgemm_ks, NS = mgemm_ns;
+    if (!KS) {
+        KS = mode == 1 ? 32 : 16;
+        NS = mode == 6 ? 3 : 4;
+    }
+    const bool d64 = C64 != nullptr;
+    const int kch = d64 ? (mgemm_kch ? mgemm_kch : 4) : 8;
+    const int grid = ((Bn + kGemmBM - 1) / kGemmBM) * ((Hn + 127) / 128);
     const int npx = mode == 1 ? 1 : (mode == 3 ? 2 : 3);
-    const size_t lds = (size_t)npx * (BM + GBN) * GLD * 2;
-#define LC_MG(T, MV, WMV)                                                                                      \
-    if (mode == MV && WM == WMV) {                                                                             \
-        if (lds > 65536) {                                                                                     \
-            hipError_t e = hipFuncSetAttribute((const void *)k_mgemm<T, MV, WMV>,                              \
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);          \
-            if (e != hipSuccess) return e;                                                                     \
-        }                                                                                                      \
-        hipLaunchKernelGGL((k_mgemm<T, MV, WMV>), dim3(grid), dim3(128 * WMV), lds, s, (const T *)X, xps,    \
-                           (const T *)Y, yps, Bn, Hn, P, Out, ldo);                                            \
-        return hipGetLastError();                                                                              \
+    const size_t lds = (size_t)NS * 2 * npx * 4 * (KS / 16) * 1024;
+#define LC_MG1(T, MV, KSV, NSV, DV, KV)                                                                         \
+    if (mode == MV && KS == KSV && NS == NSV && d64 == DV && kch == KV) {                                       \
+        if (lds > 65536) {                                                                                      \
+            hipError_t e = hipFuncSetAttribute((const void *)k_mgemm<T, MV, KSV, NSV, DV, KV>,                  \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
+            if (e != hipSuccess) return e;                                                                      \
+        }                                                                                                       \
+        hipLaunchKernelGGL((k_mgemm<T, MV, KSV, NSV, DV, KV>), dim3(grid), dim3(256), lds, s, (const T *)X,    \
+                           xps, (const T *)Y, yps, Bn, Hn, K16, Out, ldo, C64, rowexp, colexp);                \
+        return hipGetLastError();                                                                               \
     }
+#define LC_MG(T, MV, KSV, NSV) \
+    LC_MG1(T, MV, KSV, NSV, false, 8) LC_MG1(T, MV, KSV, NSV, true, 2) LC_MG1(T, MV, KSV, NSV, true, 4)
+#define LC_MG_ALL(T)                                                                                            \
+    LC_MG(T, 1, 32, 2) LC_MG(T, 1, 32, 4) LC_MG(T, 1, 16, 4)                                                    \
+    LC_MG(T, 3, 32, 2) LC_MG(T, 3, 16, 2) LC_MG(T, 3, 16, 3) LC_MG(T, 3, 16, 4)                                 \
+    LC_MG(T, 6, 16, 2) LC_MG(T, 6, 16, 3)
     if (h16 == kBF16) {
-        LC_MG(__bf16, 1, 2) LC_MG(__bf16, 3, 2) LC_MG(__bf16, 6, 2)
-        LC_MG(__bf16, 1, 4) LC_MG(__bf16, 3, 4) LC_MG(__bf16, 6, 4)
+        LC_MG_ALL(__bf16)
     } else {
-        LC_MG(_Float16, 1, 2) LC_MG(_Float16, 3, 2) LC_MG(_Float16, 6, 2)
-        LC_MG(_Float16, 1, 4) LC_MG(_Float16, 3, 4) LC_MG(_Float16, 6, 4)
+        LC_MG_ALL(_Float16)
     }
+#undef LC_MG_ALL
 #undef LC_MG
+#undef LC_MG1
     return hipErrorInvalidValue;
 }
 

@@ -10,17 +10,29 @@ namespace lc {
 
 constexpr int kBF16 = 0, kF16 = 1;
 
-// waves along b per block of the MFMA product (2 or 4; block tile 64*WM x 128)
-extern int mgemm_wm;
+// rows of F^T per block tile of the MFMA product (also the padding unit of
+// the fragment-order operands)
+constexpr int kGemmBM = 128;
+
+// k per LDS stage and ring length of the MFMA product (0: per-mode default)
+extern int mgemm_ks, mgemm_ns;
+// K-steps of 16 per FP64 flush of the direct form's accumulators (2 or 4)
+extern int mgemm_kch;
 
 hipError_t launch_amat(int H, int P, int QA, const double *xc, const double *lam, const double2 *rowA,
                        const double2 *omt2, const double *wq, const double *s2, double *A, hipStream_t s);
-hipError_t launch_split_rows(int h16, const double *A, int H, int P, int ldk, int npc, void *Y,
-                             int64_t piece_stride, int *rowexp, int scaled, hipStream_t s);
-hipError_t launch_split_cols(int h16, const double *F, int P, int B, int ldk, int npc, void *X,
+// Y operand rows r < H, columns k < P read as S[(r + roff) rs + k cs]
+hipError_t launch_split_rows(int h16, const double *S, int64_t roff, int64_t rs, int64_t cs, int H, int P, int Kp,
+                             int Hpad, int npc, void *Y, int64_t piece_stride, int *rowexp, int scaled,
+                             hipStream_t s);
+hipError_t launch_transpose_a(const double *A, int H, int P, double *AT, hipStream_t s);
+hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int npc, void *X,
                              int64_t piece_stride, int *colexp, int scaled, hipStream_t s);
+// C64 == nullptr: FP32 sums into Out[Bn][ldo]; otherwise finished FP64
+// values into C64[Bn][ldo] scaled by 2^(rowexp[j] + colexp[b])
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
-                        int P, float *Out, int ldo, hipStream_t s);
+                        int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
+                        hipStream_t s);
 hipError_t launch_gdst(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,
                        int64_t H, int64_t L, int64_t N, const double2 *tw_pre, const double2 *tw_pack,
                        const double2 *tw_fft, const FftSched &sch, double *C, hipStream_t s);

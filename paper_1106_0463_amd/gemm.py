@@ -1,5 +1,5 @@
-"""Abel-as-GEMM plans: functions sampled on one fixed Chebyshev-Gauss grid
-(binding of lc_plan_gemm / lc_execute_gemm)."""
+"""Fixed-grid plans: functions sampled on one Chebyshev-Gauss grid
+(binding of lc_plan_gemm, lc_plan_legendre_matrix and lc_execute_gemm)."""
 from __future__ import annotations
 
 import ctypes as C
@@ -11,10 +11,13 @@ from ._lib import GEMM_MODES, check, load
 class GemmPlan(Plan):
     @property
     def matrix(self):
-        """FP64 product-integration matrix A, [H+1, P] (device view)."""
+        """FP64 matrix of the plan (device view): the product-integration
+        matrix A [H+1, P], or Lmat^T [P, N] for a Legendre-matrix plan."""
         ptr = C.c_void_p()
         check(self._lib.lc_plan_gemm_matrix(self._h, C.byref(ptr)), "lc_plan_gemm_matrix")
         info = self.info
+        if info["kind"] == LEGENDRE_MATRIX:
+            return _view(ptr.value, (info["Q"], info["N"]), self)
         return _view(ptr.value, (info["H"] + 1, info["Q"]), self)
 
     def reserve(self, B: int) -> None:
@@ -38,7 +41,19 @@ class GemmPlan(Plan):
         return out
 
 
+LEGENDRE_MATRIX = 3  # lc_plan_kind of lc_plan_legendre_matrix plans
+
+
 def plan_gemm(P: int, M: int, N: int, mode: str = "bf16x3") -> GemmPlan:
+    """Abel product phi = A F, then the batched twist/FFT/rescale."""
     h = C.c_void_p()
     check(load().lc_plan_gemm(int(P), int(M), int(N), GEMM_MODES[mode], C.byref(h)), "lc_plan_gemm")
+    return GemmPlan(h)
+
+
+def plan_legendre_matrix(P: int, M: int, N: int, mode: str = "bf16x3") -> GemmPlan:
+    """One product C = F^T Lmat^T with the FP64-built N x P Legendre matrix."""
+    h = C.c_void_p()
+    check(load().lc_plan_legendre_matrix(int(P), int(M), int(N), GEMM_MODES[mode], C.byref(h)),
+          "lc_plan_legendre_matrix")
     return GemmPlan(h)

@@ -118,3 +118,108 @@ def test_gemm_full_size_sampled(lc):
         g.destroy()
         del F, C
         torch.cuda.empty_cache()
+
+
+# ------------------------------------------------ direct Legendre matrix ---
+# Lmat = D A folds the twist/DST/rescale of eq. (2.4) into one N x P matrix.
+# Whenever the method is exact for degree < P (M >= N + P), Lmat holds the
+# Legendre coefficients of the Lagrange cardinal polynomials l_p of the
+# grid, so that Lmat V = I for V[p][m] = P_m(x_p), m < P.
+
+def _cardinal(P, p, x):
+    """l_p(x) of the Chebyshev-Gauss grid (barycentric form, long double)."""
+    k = np.arange(P)
+    th = np.pi * (2 * k.astype(np.longdouble) + 1) / (2 * P)
+    xk, lam = np.cos(th), (-1.0) ** k * np.sin(th)
+    d = x[:, None] - xk[None, :]
+    return (lam[p] / d[:, p]) / np.sum(lam[None, :] / d, axis=1)
+
+
+def test_legendre_matrix_basis_exact(lc):
+    banner("[gpu] legendre matrix fp64: Lmat V = I and oracle columns")
+    from oracle import definition as D
+    P, M, N = 256, 512, 256
+    g = lc.plan_legendre_matrix(P, M, N, "fp64")
+    assert g.info["kind"] == 3
+    LT = g.matrix.cpu().numpy()          # [P, N]
+    x = W.chebyshev_gauss_nodes(P)
+    V = npleg.legvander(x, P - 1)        # [P, P]
+    err = np.max(np.abs(LT.T @ V - np.eye(N, P)))
+    banner(f"    max |Lmat V - I| = {err:.2e}")
+    assert err < 1e-12
+    # columns against the definition (K-point Gauss rule, exact for degree
+    # P - 1 + N - 1 <= 2K - 1)
+    K = (P + N) // 2 + 8
+    xg, wg = D.gauss_legendre(K)
+    for p in (0, 1, 77, 128, 255):
+        ref = D.legendre_coeffs_from_samples(xg, wg, _cardinal(P, p, xg), N).astype(float)
+        assert np.max(np.abs(LT[p] - ref)) <= 1e-12 * np.max(np.abs(ref)) + 1e-14, p
+    g.destroy()
+
+
+def _run_direct(lc, mode, P, M, N, B, degree, seed=4):
+    import torch
+    from workloads.gpu import series_grid
+    coef = W.gemm_batch_coeffs(B, degree, seed=seed)
+    g = lc.plan_legendre_matrix(P, M, N, mode)
+    F = series_grid(coef, g.nodes)
+    C = g.execute(F)
+    torch.cuda.synchronize()
+    out = C.cpu().numpy()
+    g.destroy()
+    return out, coef
+
+
+def test_legendre_matrix_fp64_exact(lc):
+    banner("[gpu] legendre matrix fp64: exact coefficients, ragged sizes")
+    C, coef = _run_direct(lc, "fp64", 1000, 1600, 777, 77, 500, seed=9)
+    E_c, E_a = _errors(C, coef, 777)
+    banner(f"    E_c {E_c:.2e} E_a {E_a:.2e}")
+    assert E_c <= 1e-12
+
+
+# The direct form rounds each coefficient's own FP32 partial sums (no
+# transform averages them), so its accumulators are flushed into FP64 totals
+# every 4 K-steps of 16; its error is then relative to max|c| as well:
+# E_c bounds hold for the three- and six-product modes (the Abel form's E_c
+# is ~1e-4 at these sizes).
+@pytest.mark.parametrize("mode,bound_a,bound_c", [("bf16x6", 1e-7, 1e-6), ("fp16x3", 1e-7, 1e-6),
+                                                  ("bf16x3", 5e-7, 1e-4), ("fp16x1", 1e-3, 1.0)])
+def test_legendre_matrix_split_modes(lc, mode, bound_a, bound_c):
+    banner(f"[gpu] legendre matrix {mode}")
+    C, coef = _run_direct(lc, mode, 1024, 2048, 1024, 256, 700)
+    E_c, E_a = _errors(C, coef, 1024)
+    banner(f"    {mode}: E_c {E_c:.2e} E_a {E_a:.2e}")
+    assert E_a <= bound_a
+    assert E_c <= bound_c
+
+
+def test_legendre_matrix_ragged_split(lc):
+    banner("[gpu] legendre matrix ragged sizes, split vs fp64")
+    Cm, coef = _run_direct(lc, "fp16x3", 1000, 1600, 777, 77, 500, seed=9)
+    Cd, _ = _run_direct(lc, "fp64", 1000, 1600, 777, 77, 500, seed=9)
+    n = np.arange(777)
+    assert rel_err(Cm / (2 * n + 1), Cd / (2 * n + 1)) <= 1e-7
+
+
+def test_legendre_matrix_full_size_sampled(lc):
+    # P = 4096, M = 8192, N = 4096, B = 16384 series of degree 3000
+    import torch
+    from workloads.gpu import series_grid
+    banner("[gpu] legendre matrix full size B=16384")
+    B, P, M, N, deg = 16384, 4096, 8192, 4096, 3000
+    coef = W.gemm_batch_coeffs(B, deg, seed=4)
+    for mode, bound in (("fp16x3", 1e-7), ("bf16x6", 1e-7)):
+        g = lc.plan_legendre_matrix(P, M, N, mode)
+        F = series_grid(coef, g.nodes)
+        C = g.execute(F)
+        torch.cuda.synchronize()
+        sel = np.random.default_rng(41).choice(B, 256, replace=False)
+        Cs = C[torch.from_numpy(sel).cuda()].cpu().numpy()
+        E_c, E_a = _errors(Cs, coef[sel], N)
+        banner(f"    {mode}: E_c {E_c:.2e} E_a {E_a:.2e} (256 sampled functions)")
+        assert E_a <= bound
+        assert E_c <= 1e-6
+        g.destroy()
+        del F, C
+        torch.cuda.empty_cache()
