@@ -8,7 +8,9 @@ code with the HIP library and imports nothing from it.
   quadrature with the three-term recurrence (long double, O(N K)).
 * :mod:`oracle.method` -- the paper's discretized method step by step
   (Abel-type transform eqs. (2.5)/(2.14), trapezoid rule for eq. (2.4),
-  c_n = (2n+1) a_n), long double, with a plain O(M N) Fourier sum.
+  c_n = (2n+1) a_n), long double, with a plain O(M N) Fourier sum; also the
+  composite Abel rule (breakpoints, grading toward x = 1, per-row node
+  counts).
 * :mod:`oracle.closed_forms` -- closed-form coefficients and Abel transforms
   used to pin the two above.
 
@@ -23,6 +25,8 @@ from ._lib import build, load, threads  # noqa: F401
 from .definition import (gauss_legendre, legendre_coeffs,  # noqa: F401
                          legendre_coeffs_from_samples,
                          legendre_coeffs_piecewise, legendre_eval)
-from .method import (abel_fhat, abel_nodes, abel_phi, coeffs_from_fhat,  # noqa: F401
-                     fhat_from_phi, fourier_coeffs, fourier_coeffs_at,
-                     method_coeffs, method_coeffs_at, positive_half_samples, y_grid)
+from .method import (abel_fhat, abel_nodes, abel_phi, abel_phi_rule,  # noqa: F401
+                     abel_rule_cuts, abel_rule_node_count, abel_rule_row_q,
+                     coeffs_from_fhat, fhat_from_phi, fourier_coeffs, fourier_coeffs_at,
+                     method_coeffs, method_coeffs_at, method_coeffs_rule,
+                     positive_half_samples, y_grid)

@@ -171,3 +171,133 @@ def method_coeffs(f, N: int, M: int, Q: int, return_imag: bool = False,
     y = y_grid(M)
     fh = abel_fhat(f, y, Q, fp64_nodes)
     return coeffs_from_fhat(fh, N, return_imag)
+
+
+# ----------------------------------------------------------------------------
+# Composite Abel rule (breakpoints, grading toward x = 1, per-row node counts)
+#
+# With x = 1 - 2 s^2 (1 - t^2), s = sin(y/2), the Abel integral eq. (2.14) is
+#     phi(y) = 2 s * integral_0^1 f(1 - 2 s^2 (1 - t^2)) dt
+# (the substitution of the paper's numerical remarks, as in abel_phi).  A
+# composite rule cuts t in [0, 1] into panels:
+#   * a breakpoint b of f with cos y < b < 1 (a point where f or one of its
+#     derivatives jumps, e.g. x = 0 for |x|^{3/2}) becomes the cut
+#     t_b = sqrt(1 - r) with r = (1 - b) / (2 s^2), i.e. 1 - t_b = r / (1 + sqrt(1 - r));
+#   * grading toward t = 1 (x = 1), for f with a singularity just beyond
+#     x = 1, adds the cuts 1 - t = sigma^k, k = 1..K.
+# Cuts are handled by their distance e = 1 - t; cuts with e <= 1e-15 or
+# e >= 1 - 1e-15 are dropped, and a cut closer than 1e-12 max(e) to the
+# previous one (in decreasing e) is merged into it.
+# The first panel [0, t_1] uses the positive half of the 2q-point
+# Gauss-Legendre rule (the integrand is even in t there); every other panel
+# uses the q-point rule.  The node count q is fixed, or grows with the row
+# for f band-limited to degree ~D:
+#     q_j = min(q_max, 8 ceil((q + ceil(g)) / 8)),  g = D s^2/2 + 6.5 (D s^2/2)^{1/3},
+# (a law measured on cos(D x), whose transform needs about D s^2 / 2 nodes
+# per row, rather than a uniform D / 2).
+
+def abel_rule_row_q(s, rule: dict) -> int:
+    """Node count of a row with s = sin(y/2) under ``rule``."""
+    q = int(rule["q"])
+    D = float(rule.get("band", 0.0))
+    if D <= 0:
+        return q
+    g = LD(D) * LD(s) ** 2 / 2
+    g = g + LD(6.5) * np.cbrt(g)
+    qj = q + int(np.ceil(g))
+    qj = 8 * ((qj + 7) // 8)
+    return min(int(rule.get("q_max", qj)), qj)
+
+
+def abel_rule_cuts(s, rule: dict) -> list:
+    """Cut distances e = 1 - t in (0, 1), decreasing, for one row."""
+    s = LD(s)
+    c = 1 - 2 * s * s                                   # cos y
+    es = []
+    for b in rule.get("breaks", ()):
+        b = LD(b)
+        if c < b < 1:
+            r = (1 - b) / (2 * s * s)
+            es.append(r / (1 + np.sqrt(1 - r)))
+    sigma = float(rule.get("grade_ratio", 0.0))
+    for k in range(1, int(rule.get("grade_levels", 0)) + 1):
+        if sigma > 0:
+            es.append(LD(sigma) ** k)
+    es = sorted((e for e in es if LD(1e-15) < e < 1 - LD(1e-15)), reverse=True)
+    out = []
+    for e in es:
+        if out and out[-1] - e < LD(1e-12) * out[0]:
+            continue
+        out.append(e)
+    return out
+
+
+def _half_rule(q: int):
+    T, W = gauss_legendre(2 * q)
+    return T[:q], W[:q]                                  # positive half, decreasing
+
+
+def abel_phi_rule(f, y: np.ndarray, rule: dict, fp64_nodes: bool = False) -> np.ndarray:
+    """phi(y) of eq. (2.14) for y in (0, pi] by the composite rule above.
+    fp64_nodes=True rounds the nodes to FP64 before f is evaluated (the
+    samples an FP64 caller provides)."""
+    y = np.asarray(y, dtype=LD)
+    out = np.empty(y.shape, dtype=LD)
+    rules = {}
+    for i, yy in enumerate(y.ravel()):
+        s = np.sin(yy / 2)
+        if s == 0:
+            out.ravel()[i] = 0
+            continue
+        q = abel_rule_row_q(s, rule)
+        if q not in rules:
+            rules[q] = (_half_rule(q), gauss_legendre(q))
+        (T, W), (tau, om) = rules[q]
+        cuts = abel_rule_cuts(s, rule)
+        bounds = [LD(1)] + cuts + [LD(0)]                # e = 1 - t at panel ends
+        e_list, w_list = [], []
+        # first panel [0, t_1]: t = t_1 T, 1 - t = e_1 + t_1 (1 - T)
+        e1 = bounds[1]
+        t1 = 1 - e1
+        e_list.append(e1 + t1 * (1 - T))
+        w_list.append(t1 * W)
+        # panels [t_p, t_{p+1}]: 1 - t = e_{p+1} + h (1 - tau), h = (e_p - e_{p+1}) / 2
+        for p in range(1, len(bounds) - 1):
+            h = (bounds[p] - bounds[p + 1]) / 2
+            e_list.append(bounds[p + 1] + h * (1 - tau))
+            w_list.append(h * om)
+        e = np.concatenate(e_list)
+        w = np.concatenate(w_list)
+        x = 1 - 2 * s * s * (e * (2 - e))
+        if fp64_nodes:
+            x = x.astype(np.float64).astype(LD)
+        out.ravel()[i] = 2 * s * np.sum(w * np.asarray(f(x), dtype=LD))
+    return out
+
+
+def abel_rule_node_count(M: int, rule: dict) -> int:
+    """Number of Abel nodes of the composite rule over y = pi j / (M/2),
+    j = 1..M/2."""
+    H = int(M) // 2
+    n = 0
+    for j in range(1, H + 1):
+        s = np.sin(PI * j / (2 * H))
+        n += abel_rule_row_q(s, rule) * (1 + len(abel_rule_cuts(s, rule)))
+    return n
+
+
+def method_coeffs_rule(f, N: int, M: int, rule: dict, fp64_nodes: bool = False) -> np.ndarray:
+    """c_0..c_{N-1} by the method with the composite Abel rule: phi on the
+    positive half of the M-point grid, then eq. (2.5), the trapezoid form of
+    eq. (2.4) and c_n = (2n+1) a_n, as in :func:`method_coeffs`."""
+    y = y_grid(M)
+    H = int(M) // 2
+    j = np.arange(1, H + 1, dtype=LD)
+    yp = PI * j / H                                       # the distinct |y| > 0
+    phi_pos = abel_phi_rule(f, yp, rule, fp64_nodes)
+    # |y_k| = pi |k - H| / H on the grid y_k = -pi + 2 pi k / M
+    k = np.arange(int(M))
+    idx = np.abs(k - H)
+    phi_abs = np.where(idx == 0, LD(0), phi_pos[np.maximum(idx, 1) - 1])
+    fh = fhat_from_phi(phi_abs, y)
+    return coeffs_from_fhat(fh, N)

@@ -104,3 +104,24 @@ def load_table1(path: str) -> tuple[list[int], list[str]]:
             ns.append(int(a))
             vals.append(b)
     return ns, vals
+
+
+def phi_genfn(t: float, y) -> mp.mpf:
+    """phi(y) of eq. (2.14) for the generating function eq. (2.2),
+    (1 - 2xt + t^2)^{-1/2}: since its c_n = t^n and phi_{P_n} =
+    2 sin((n+1/2) y)/(2n+1), phi = sum_n t^n 2 sin((n+1/2) y)/(2n+1)
+    = Im[(2/sqrt(t)) artanh(sqrt(t) e^{iy/2})]."""
+    t, y = mp.mpf(t), mp.mpf(y)
+    z = mp.sqrt(t) * mp.exp(1j * y / 2)
+    return mp.im(2 / mp.sqrt(t) * mp.atanh(z))
+
+
+def phi_cos(omega: float, y) -> mp.mpf:
+    """phi(y) of eq. (2.14) for f = cos(omega x): with x = cos y + u^2/2,
+    phi = integral_0^{2 sin(y/2)} cos(omega (cos y + u^2/2)) du
+        = sqrt(pi/omega) [cos(omega cos y) C(z) - sin(omega cos y) S(z)],
+    z = 2 sin(y/2) sqrt(omega/pi), C and S the Fresnel integrals."""
+    w, y = mp.mpf(omega), mp.mpf(y)
+    z = 2 * mp.sin(y / 2) * mp.sqrt(w / mp.pi)
+    cy = mp.cos(y)
+    return mp.sqrt(mp.pi / w) * (mp.cos(w * cy) * mp.fresnelc(z) - mp.sin(w * cy) * mp.fresnels(z))
