@@ -192,9 +192,11 @@ def method_coeffs(f, N: int, M: int, Q: int, return_imag: bool = False,
 # Gauss-Legendre rule (the integrand is even in t there); every other panel
 # uses the q-point rule.  The node count q is fixed, or grows with the row
 # for f band-limited to degree ~D:
-#     q_j = min(q_max, 8 ceil((q + ceil(g)) / 8)),  g = D s^2/2 + 6.5 (D s^2/2)^{1/3},
+#     q_j = min(q_max, ladder(q + ceil(g))),  g = D s^2/2 + 6.5 (D s^2/2)^{1/3},
 # (a law measured on cos(D x), whose transform needs about D s^2 / 2 nodes
-# per row, rather than a uniform D / 2).
+# per row, rather than a uniform D / 2).  ladder(n) rounds up to a multiple
+# of 8 for n <= 128 and to a multiple of 2^(floor(log2 n) - 4) above (16
+# steps per octave), so that a plan needs about a hundred distinct rules.
 
 def abel_rule_row_q(s, rule: dict) -> int:
     """Node count of a row with s = sin(y/2) under ``rule``."""
@@ -204,9 +206,18 @@ def abel_rule_row_q(s, rule: dict) -> int:
         return q
     g = LD(D) * LD(s) ** 2 / 2
     g = g + LD(6.5) * np.cbrt(g)
-    qj = q + int(np.ceil(g))
-    qj = 8 * ((qj + 7) // 8)
+    qj = abel_rule_ladder(q + int(np.ceil(g)))
     return min(int(rule.get("q_max", qj)), qj)
+
+
+def abel_rule_ladder(n: int) -> int:
+    """Smallest ladder value >= n: multiples of 8 up to 128, then multiples
+    of 2^(floor(log2 n) - 4)."""
+    n = int(n)
+    if n <= 128:
+        return 8 * ((n + 7) // 8)
+    step = 1 << (n.bit_length() - 1 - 4)
+    return step * ((n + step - 1) // step)
 
 
 def abel_rule_cuts(s, rule: dict) -> list:

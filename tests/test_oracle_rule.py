@@ -30,6 +30,15 @@ def test_closed_forms_vs_mpmath_quadrature():
         assert abs(phi_cos(37, y) - ref) < mp.mpf(10) ** -20
 
 
+def test_ladder():
+    # multiples of 8 up to 128, then 16 steps per octave (at most 6.25% over)
+    assert [oracle.abel_rule_ladder(n) for n in (1, 8, 9, 128, 129, 136, 137, 255, 256, 257, 8193)] == \
+        [8, 8, 16, 128, 136, 136, 144, 256, 256, 272, 8704]
+    for n in range(1, 20000, 7):
+        v = oracle.abel_rule_ladder(n)
+        assert n <= v <= max(n + 7, int(n * 1.0625) + 1)
+
+
 def test_cuts_map_breakpoints_and_grading():
     rule = {"q": 8, "breaks": [-0.25, 0.0, 0.6], "grade_ratio": 0.2, "grade_levels": 3}
     for y in (0.7, 1.9, 3.1):
