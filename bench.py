@@ -5,10 +5,13 @@ twist, FFT and rescale over one resident batch of samples):
 
   single_large   f(x) = cos(16384 x) + (1 - 1.98 x + 0.9801)^{-1/2},
                  N = 65536, M = 262144, FP64.  The stated Q = 64 does not
-                 resolve cos(16384 x) (its coefficients come out O(1) wrong),
-                 so the timed run uses the resolving Q = 8384 (FP64 class:
-                 max |dc| <= 1e-12 max |c|); the Q = 64 point is reported
-                 beside it under "stated_q_point".
+                 resolve cos(16384 x) (its coefficients come out O(1) wrong).
+                 The timed run uses the composite Abel rule with per-row node
+                 counts for band 16384 (about D s_j^2 / 2 nodes in row j,
+                 FP64 class: max |dc| <= 1e-12 max |c|); the uniform rule at
+                 the resolving Q = 8384 is reported beside it under
+                 "uniform_rule_point" (--rule uniform swaps the two), and the
+                 Q = 64 point under "stated_q_point".
 
 Other workloads (--workload): single_small (N=64, M=256, Q=32), batch
 (4096 ragged random Legendre series, Q=48), gemm (Abel-as-GEMM, P=4096,
@@ -90,12 +93,12 @@ def cpu_baseline_single_large(budget_s: float = 20.0):
                       f"long-double Gauss-Legendre rule (rule construction included), {dt:.2f} s"}
 
 
-def bench_single(args, N, M, Q, f, name):
+def bench_single(args, N, M, Q, f, name, rule=None):
     import torch
 
     import paper_1106_0463_amd as lc
-    p = lc.plan(N, M, Q)
-    if args.autotune:
+    p = lc.plan_adaptive(N, M, **rule) if rule else lc.plan(N, M, Q)
+    if args.autotune and not rule:
         p.autotune()
     info = p.info
     x = p.nodes
@@ -113,10 +116,19 @@ def bench_single(args, N, M, Q, f, name):
     kms, cnt = p.kernel_ms()
     p.set_timing(False)
     H = info["H"]
-    alg_bytes = 8.0 * H * Q + 16.0 * H
+    # samples read (8 bytes each; the adaptive rule's per-panel padding to 4
+    # samples counts against the kernel) + phi written and re-read
+    alg_bytes = 8.0 * info["samples"] + 16.0 * H
     res = {"sec": sec, "kernel_ms": kms, "kernel_count": cnt, "alg_bytes": alg_bytes,
            "info": info, "coefs": out}
     return p, fx, res
+
+
+# Composite Abel rule of the large single function: node counts for f
+# band-limited to degree 16384 (cos(16384 x)), and six graded panels toward
+# x = 1 (ratio 0.2, at least 16 nodes each) for the generating-function part,
+# singular 5e-5 beyond x = 1
+BAND_RULE = dict(q=16, band=16384.0, q_max=8704, grade_ratio=0.2, grade_levels=6)
 
 
 def run_single_large(args):
@@ -126,7 +138,9 @@ def run_single_large(args):
     import workloads as W
     N, M = 65536, 262144
     wl = W.single_large(Q=args.q or Q_RESOLVING)
-    p, fx, r = bench_single(args, N, M, wl.Q, wl.f, wl.name)
+    band = args.rule == "band"
+    TKEY = "single_large_band" if band else "single_large"
+    p, fx, r = bench_single(args, N, M, wl.Q, wl.f, wl.name, rule=BAND_RULE if band else None)
     sec = r["sec"]
     kms = r["kernel_ms"]
     achieved = r["alg_bytes"] / (kms * 1e-3) / 1e9
@@ -144,19 +158,39 @@ def run_single_large(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "single large oscillatory function "
-                               "cos(16384x)+(1-1.98x+0.9801)^-1/2, FP64",
-                   "N": N, "M": M, "M_eff": r["info"]["M_eff"], "Q": wl.Q,
-                   "Q_stated": 64, "precision_class": "FP64 (<=1e-12 max|c|)"},
+                               "cos(16384x)+(1-1.98x+0.9801)^-1/2, FP64"
+                               + (", composite Abel rule (band 16384 node counts, 6 graded panels)" if band
+                                  else f", uniform Abel rule Q={wl.Q}"),
+                   "N": N, "M": M, "M_eff": r["info"]["M_eff"],
+                   "abel_rule": dict(BAND_RULE) if band else {"Q": wl.Q},
+                   "samples": r["info"]["samples"], "Q_stated": 64,
+                   "precision_class": "FP64 (<=1e-12 max|c|)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": TRAFFIC["single_large"][0] if wl.Q == Q_RESOLVING else None,
-                     "traffic_kernel": TRAFFIC["single_large"][1],
-                     "kernel": "k_quad_* (Abel quadrature reduction)",
+                     "traffic": TRAFFIC[TKEY][0] if (band or wl.Q == Q_RESOLVING) and TKEY in TRAFFIC else None,
+                     "kernel": "k_aquad (segmented Abel quadrature)" if band
+                               else "k_quad_* (Abel quadrature reduction)",
                      "kernel_ms": kms, "alg_bytes_per_launch": r["alg_bytes"]},
     }
+    TK = TRAFFIC.get(TKEY)
+    if TK:
+        line["roofline"]["traffic_kernel"] = TK[1]
     p.destroy()
     del fx
     torch.cuda.empty_cache()
+    # the other rule beside it: the uniform rule at the resolving Q (or the
+    # band rule when the uniform one is the main line)
+    if not args.skip_stated:
+        ro = None if band else BAND_RULE
+        po, fxo, rr = bench_single(args, N, M, Q_RESOLVING, wl.f, wl.name, rule=ro)
+        ao = rr["alg_bytes"] / (rr["kernel_ms"] * 1e-3) / 1e9
+        line["uniform_rule_point" if band else "band_rule_point"] = {
+            "abel_rule": {"Q": Q_RESOLVING} if band else dict(BAND_RULE), "samples": rr["info"]["samples"],
+            "value": N / rr["sec"], "ms_per_step": rr["sec"] * 1e3, "kernel_ms": rr["kernel_ms"],
+            "achieved_GBs": ao, "frac": ao / HBM_PEAK_GBS}
+        po.destroy()
+        del fxo
+        torch.cuda.empty_cache()
     # stated-Q point (bandwidth only: the stated Q does not resolve f)
     if not args.skip_stated:
         wl64 = W.single_large(Q=64)
@@ -397,7 +431,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_large",
                     choices=["single_large", "single_small", "batch", "gemm", "stream", "copy"])
-    ap.add_argument("--q", type=int, default=0, help="override Q (single_large)")
+    ap.add_argument("--q", type=int, default=0, help="override Q (single_large, uniform rule)")
+    ap.add_argument("--rule", default="band", choices=["band", "uniform"],
+                    help="single_large: composite Abel rule with per-row node counts, or the uniform rule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-stated", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])

@@ -78,8 +78,44 @@ typedef enum {
     LC_PLAN_SINGLE = 0,
     LC_PLAN_BATCH = 1,
     LC_PLAN_GEMM = 2,            /* Abel product + batched twist/FFT/rescale     */
-    LC_PLAN_LEGENDRE_MATRIX = 3  /* one product with the full N x P matrix       */
+    LC_PLAN_LEGENDRE_MATRIX = 3, /* one product with the full N x P matrix       */
+    LC_PLAN_ADAPTIVE = 4         /* single function, composite Abel rule         */
 } lc_plan_kind;
+
+/* Composite Abel rule of an adaptive plan (lc_plan_adaptive).  With
+ * x = 1 - 2 s^2 (1 - t^2), s = sin(y/2), eq. (2.14) reads
+ * phi(y) = 2 s integral_0^1 f dt; the rule cuts t in [0, 1] into panels:
+ *   - each breakpoint b with cos y < b < 1 (a point where f or a derivative
+ *     of f jumps, e.g. x = 0 for |x|^{3/2}) becomes the cut whose node is
+ *     x = b;
+ *   - grade_levels > 0 with 0 < grade_ratio < 1 adds the cuts
+ *     1 - t = grade_ratio^k, k = 1..grade_levels (panels shrinking toward
+ *     x = 1, for f singular just beyond x = 1);
+ * cuts closer than 1e-12 (relative, in 1 - t) merge, and cuts at t <= 1e-7
+ * (a breakpoint within ~1e-14 of cos y) are dropped.  The first panel uses
+ * the positive half of the 2q-point Gauss-Legendre rule (the integrand is
+ * even in t there), the others the q-point rule.  Node count of a panel
+ * [t_lo, t_hi]:
+ *   band == 0: q;
+ *   band  > 0: min(q_max, ladder(q + ceil(g))), g = G + 6.5 G^{1/3},
+ *              G = (band s^2 / 2) (t_hi^2 - t_lo^2),
+ *              for f band-limited to degree ~band: about band s^2 / 2 nodes
+ *              per row (instead of a uniform band / 2), shared among the
+ *              panels in proportion to the phase of cos(band x) they cover;
+ *              ladder() rounds up to a multiple of 8 up to 128 and to 16
+ *              steps per octave above.
+ * Limits: 1 <= q <= 65536; q (band = 0) or q_max (band > 0, q_max >= q)
+ * even whenever cuts are requested; nbreak <= 64, breaks in (-1, 1);
+ * grade_levels <= 64. */
+typedef struct {
+    int32_t q;             /* nodes per panel, or the base count when band > 0 */
+    int32_t q_max;         /* cap of the per-row count (band > 0)              */
+    double band;           /* 0, or the degree f is band-limited to            */
+    int32_t nbreak;        /* number of breakpoints                            */
+    const double *breaks;  /* host array of nbreak values (may be null if 0)   */
+    double grade_ratio;    /* 0, or the grading ratio in (0, 1)                */
+    int32_t grade_levels;  /* number of graded cuts                            */
+} lc_abel_rule;
 
 typedef struct lc_plan_s *lc_plan_t;
 
@@ -112,6 +148,18 @@ lc_status lc_grid_size(int64_t M, int64_t *M_eff);
  * workspace.  *out is written only on success.
  * Errors: LC_ERR_INVALID, LC_ERR_NOMEM, LC_ERR_HIP. */
 lc_status lc_plan(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t *out);
+
+/* Single-function plan with the composite Abel rule *rule (see
+ * lc_abel_rule) in place of the uniform Q-point rule; N, M and prec as in
+ * lc_plan.  The nodes are one flat FP64 array (lc_plan_nodes: rows = the
+ * number of samples, Q = 1): rows j = 1..M_eff/2 in order, a row's panels in
+ * order of increasing t, every panel padded to a multiple of 4 samples
+ * (padding repeats the panel's last node and has weight 0); nodes are the
+ * correctly rounded values of 1 - 2 s_j^2 (1 - t^2).  Executed with
+ * lc_execute on samples in that layout.
+ * Errors: LC_ERR_INVALID (bad rule or sizes), LC_ERR_NOMEM, LC_ERR_HIP,
+ * LC_ERR_UNSUPPORTED (too many samples). */
+lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *rule, lc_precision prec, lc_plan_t *out);
 
 /* Describes any plan.  Errors: LC_ERR_INVALID on null arguments. */
 lc_status lc_plan_info(lc_plan_t plan, lc_plan_desc *desc);

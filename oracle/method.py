@@ -186,25 +186,34 @@ def method_coeffs(f, N: int, M: int, Q: int, return_imag: bool = False,
 #   * grading toward t = 1 (x = 1), for f with a singularity just beyond
 #     x = 1, adds the cuts 1 - t = sigma^k, k = 1..K.
 # Cuts are handled by their distance e = 1 - t; cuts with e <= 1e-15 or
-# e >= 1 - 1e-15 are dropped, and a cut closer than 1e-12 max(e) to the
+# e >= 1 - 1e-7 (t <= 1e-7: a breakpoint within ~1e-14 of cos y, the row's
+# own end point) are dropped, and a cut closer than 1e-12 max(e) to the
 # previous one (in decreasing e) is merged into it.
 # The first panel [0, t_1] uses the positive half of the 2q-point
 # Gauss-Legendre rule (the integrand is even in t there); every other panel
-# uses the q-point rule.  The node count q is fixed, or grows with the row
-# for f band-limited to degree ~D:
-#     q_j = min(q_max, ladder(q + ceil(g))),  g = D s^2/2 + 6.5 (D s^2/2)^{1/3},
-# (a law measured on cos(D x), whose transform needs about D s^2 / 2 nodes
-# per row, rather than a uniform D / 2).  ladder(n) rounds up to a multiple
+# uses the q-point rule.  The node count of a panel [t_lo, t_hi] is q, or,
+# for f band-limited to degree ~D,
+#     q_p = min(q_max, ladder(q + ceil(g))),  g = G + 6.5 G^{1/3},
+#     G = (D s^2 / 2) (t_hi^2 - t_lo^2):
+# cos(D x) needs about D s^2 / 2 nodes for the whole row (a law measured on
+# its closed-form transform; a uniform rule needs D / 2 in every row), and
+# the phase of cos(D (1 - 2 s^2 (1 - t^2))) is spread over t in proportion
+# to t^2, so each panel gets its share.  ladder(n) rounds up to a multiple
 # of 8 for n <= 128 and to a multiple of 2^(floor(log2 n) - 4) above (16
 # steps per octave), so that a plan needs about a hundred distinct rules.
 
 def abel_rule_row_q(s, rule: dict) -> int:
-    """Node count of a row with s = sin(y/2) under ``rule``."""
+    """Node count of a whole row [0, 1] with s = sin(y/2) under ``rule``."""
+    return abel_rule_panel_q(s, LD(0), LD(1), rule)
+
+
+def abel_rule_panel_q(s, t_lo, t_hi, rule: dict) -> int:
+    """Node count of the panel [t_lo, t_hi] of a row with s = sin(y/2)."""
     q = int(rule["q"])
     D = float(rule.get("band", 0.0))
     if D <= 0:
         return q
-    g = LD(D) * LD(s) ** 2 / 2
+    g = LD(D) * LD(s) ** 2 / 2 * (LD(t_hi) ** 2 - LD(t_lo) ** 2)
     g = g + LD(6.5) * np.cbrt(g)
     qj = abel_rule_ladder(q + int(np.ceil(g)))
     return min(int(rule.get("q_max", qj)), qj)
@@ -234,7 +243,7 @@ def abel_rule_cuts(s, rule: dict) -> list:
     for k in range(1, int(rule.get("grade_levels", 0)) + 1):
         if sigma > 0:
             es.append(LD(sigma) ** k)
-    es = sorted((e for e in es if LD(1e-15) < e < 1 - LD(1e-15)), reverse=True)
+    es = sorted((e for e in es if LD(1e-15) < e < 1 - LD(1e-7)), reverse=True)
     out = []
     for e in es:
         if out and out[-1] - e < LD(1e-12) * out[0]:
@@ -260,20 +269,24 @@ def abel_phi_rule(f, y: np.ndarray, rule: dict, fp64_nodes: bool = False) -> np.
         if s == 0:
             out.ravel()[i] = 0
             continue
-        q = abel_rule_row_q(s, rule)
-        if q not in rules:
-            rules[q] = (_half_rule(q), gauss_legendre(q))
-        (T, W), (tau, om) = rules[q]
         cuts = abel_rule_cuts(s, rule)
         bounds = [LD(1)] + cuts + [LD(0)]                # e = 1 - t at panel ends
         e_list, w_list = [], []
         # first panel [0, t_1]: t = t_1 T, 1 - t = e_1 + t_1 (1 - T)
         e1 = bounds[1]
         t1 = 1 - e1
+        q = abel_rule_panel_q(s, LD(0), t1, rule)
+        if ("h", q) not in rules:
+            rules[("h", q)] = _half_rule(q)
+        T, W = rules[("h", q)]
         e_list.append(e1 + t1 * (1 - T))
         w_list.append(t1 * W)
         # panels [t_p, t_{p+1}]: 1 - t = e_{p+1} + h (1 - tau), h = (e_p - e_{p+1}) / 2
         for p in range(1, len(bounds) - 1):
+            q = abel_rule_panel_q(s, 1 - bounds[p], 1 - bounds[p + 1], rule)
+            if ("f", q) not in rules:
+                rules[("f", q)] = gauss_legendre(q)
+            tau, om = rules[("f", q)]
             h = (bounds[p] - bounds[p + 1]) / 2
             e_list.append(bounds[p + 1] + h * (1 - tau))
             w_list.append(h * om)
@@ -293,7 +306,10 @@ def abel_rule_node_count(M: int, rule: dict) -> int:
     n = 0
     for j in range(1, H + 1):
         s = np.sin(PI * j / (2 * H))
-        n += abel_rule_row_q(s, rule) * (1 + len(abel_rule_cuts(s, rule)))
+        bounds = [LD(1)] + abel_rule_cuts(s, rule) + [LD(0)]
+        for p in range(len(bounds) - 1):
+            t_lo = LD(0) if p == 0 else 1 - bounds[p]
+            n += abel_rule_panel_q(s, t_lo, 1 - bounds[p + 1], rule)
     return n
 
 

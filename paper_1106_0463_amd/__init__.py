@@ -20,7 +20,8 @@ import ctypes as C
 from ._lib import (GEMM_MODES, LC_FP32_QUAD, LC_FP64, PRECISIONS, LCError,  # noqa: F401
                    PlanDesc, check, load)
 
-__all__ = ["grid_size", "plan", "plan_batch", "plan_gemm", "plan_legendre_matrix", "Plan", "LCError"]
+__all__ = ["grid_size", "plan", "plan_adaptive", "plan_batch", "plan_gemm", "plan_legendre_matrix", "Plan",
+           "LCError"]
 
 
 def _torch():
@@ -143,6 +144,21 @@ def plan(N: int, M: int, Q: int, precision: str = "fp64") -> Plan:
     """Single-function plan: N coefficients, M-point y-grid, Q Abel nodes."""
     h = C.c_void_p()
     check(load().lc_plan(int(N), int(M), int(Q), PRECISIONS[precision], C.byref(h)), "lc_plan")
+    return Plan(h)
+
+
+def plan_adaptive(N: int, M: int, q: int, band: float = 0.0, q_max: int = 0, breaks=(),
+                  grade_ratio: float = 0.0, grade_levels: int = 0, precision: str = "fp64") -> Plan:
+    """Single-function plan with the composite Abel rule (lc_abel_rule):
+    breakpoints of f, geometric grading toward x = 1 and per-row node
+    counts for f band-limited to degree ``band``.  Nodes and samples are one
+    flat array (``Plan.nodes``)."""
+    from ._lib import AbelRule
+    br = (C.c_double * max(1, len(breaks)))(*[float(b) for b in breaks])
+    rule = AbelRule(int(q), int(q_max), float(band), len(breaks), br, float(grade_ratio), int(grade_levels))
+    h = C.c_void_p()
+    check(load().lc_plan_adaptive(int(N), int(M), C.byref(rule), PRECISIONS[precision], C.byref(h)),
+          "lc_plan_adaptive")
     return Plan(h)
 
 

@@ -25,12 +25,19 @@ class PlanDesc(C.Structure):
                 ("sample_bytes", C.c_int64), ("workspace_bytes", C.c_int64)]
 
 
+class AbelRule(C.Structure):
+    _fields_ = [("q", C.c_int32), ("q_max", C.c_int32), ("band", C.c_double), ("nbreak", C.c_int32),
+                ("breaks", C.POINTER(C.c_double)), ("grade_ratio", C.c_double),
+                ("grade_levels", C.c_int32)]
+
+
 # (name, restype, argtypes) for every symbol the header declares
 _vp, _i32, _i64 = C.c_void_p, C.c_int32, C.c_int64
 _pi64, _pi32 = C.POINTER(C.c_int64), C.POINTER(C.c_int32)
 SIGNATURES = [
     ("lc_grid_size", C.c_int, [_i64, _pi64]),
     ("lc_plan", C.c_int, [_i64, _i64, _i32, C.c_int, C.POINTER(_vp)]),
+    ("lc_plan_adaptive", C.c_int, [_i64, _i64, C.POINTER(AbelRule), C.c_int, C.POINTER(_vp)]),
     ("lc_plan_info", C.c_int, [_vp, C.POINTER(PlanDesc)]),
     ("lc_plan_nodes", C.c_int, [_vp, C.POINTER(_vp), _pi64, _pi32]),
     ("lc_execute", C.c_int, [_vp, _vp, _vp, _vp]),

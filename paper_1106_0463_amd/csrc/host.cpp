@@ -97,46 +97,59 @@ static void legendre_and_derivative(int n, long double x, long double &pn, long 
     dpn = (long double)n * (x * pk - pkm1) / (x * x - 1.0L);
 }
 
-static double2 dd_split(long double v) {
+double2 dd_split(long double v) {
     const double hi = (double)v;
     return make_double2(hi, (double)(v - (long double)hi));
 }
 
-void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w, std::vector<double2> &omt2) {
-    const int n = 2 * Q;
-    t.assign(Q, 0.0);
-    w.assign(Q, 0.0);
-    omt2.assign(Q, make_double2(0.0, 0.0));
+// Positive half (n/2 nodes, decreasing, n even) of the n-point rule in long
+// double: nodes x and weights w.
+void gauss_positive_half_ld(int n, std::vector<long double> &x, std::vector<long double> &w) {
+    const int h = n / 2;
+    x.assign(h, 0.0L);
+    w.assign(h, 0.0L);
     const long double PI = 3.141592653589793238462643383279502884L;
     auto work = [&](int i0, int i1) {
         for (int i = i0; i < i1; ++i) {
             const int k = i + 1;  // k-th largest root
             const long double nn = (long double)n;
-            long double x = (1.0L - 1.0L / (8.0L * nn * nn) + 1.0L / (8.0L * nn * nn * nn)) *
+            long double v = (1.0L - 1.0L / (8.0L * nn * nn) + 1.0L / (8.0L * nn * nn * nn)) *
                             cosl(PI * (4.0L * k - 1.0L) / (4.0L * nn + 2.0L));
             long double p, dp;
             for (int it = 0; it < 60; ++it) {
-                legendre_and_derivative(n, x, p, dp);
+                legendre_and_derivative(n, v, p, dp);
                 long double dx = p / dp;
-                x -= dx;
-                if (fabsl(dx) <= 4.0L * 1.0842e-19L * std::max(fabsl(x), 1e-3L)) break;
+                v -= dx;
+                if (fabsl(dx) <= 4.0L * 1.0842e-19L * std::max(fabsl(v), 1e-3L)) break;
             }
-            legendre_and_derivative(n, x, p, dp);
-            t[i] = (double)x;
-            w[i] = (double)(2.0L / ((1.0L - x * x) * dp * dp));
-            omt2[i] = dd_split((1.0L - x) * (1.0L + x));
+            legendre_and_derivative(n, v, p, dp);
+            x[i] = v;
+            w[i] = 2.0L / ((1.0L - v * v) * dp * dp);
         }
     };
-    const long long cost = (long long)Q * n;
+    const long long cost = (long long)h * n;
     int nth = 1;
     if (cost > 4000000LL) nth = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
     if (nth == 1) {
-        work(0, Q);
+        work(0, h);
     } else {
         std::vector<std::thread> th;
-        const int chunk = (Q + nth - 1) / nth;
-        for (int a = 0; a < Q; a += chunk) th.emplace_back(work, a, std::min(Q, a + chunk));
-        for (auto &x : th) x.join();
+        const int chunk = (h + nth - 1) / nth;
+        for (int a = 0; a < h; a += chunk) th.emplace_back(work, a, std::min(h, a + chunk));
+        for (auto &t : th) t.join();
+    }
+}
+
+void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w, std::vector<double2> &omt2) {
+    std::vector<long double> x, wl;
+    gauss_positive_half_ld(2 * Q, x, wl);
+    t.resize(Q);
+    w.resize(Q);
+    omt2.resize(Q);
+    for (int i = 0; i < Q; ++i) {
+        t[i] = (double)x[i];
+        w[i] = (double)wl[i];
+        omt2[i] = dd_split((1.0L - x[i]) * (1.0L + x[i]));
     }
 }
 
@@ -182,14 +195,18 @@ void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack, 
 
 // Row factors of the node formula: A_j = 2 sin^2(pi j / (2H)) as a
 // double-double pair, and 2 sin(pi j / (2H)) (the Abel Jacobian), j = 1..H.
-void row_factors(int64_t H, std::vector<double2> &A, std::vector<double> &s2) {
+long double row_half_sine(int64_t j, int64_t H) {
     const long double HALF_PI = 1.570796326794896619231321691639751442L;
+    return (2 * j <= H) ? sinl(HALF_PI * (long double)j / (long double)H)
+                        : cosl(HALF_PI * (long double)(H - j) / (long double)H);
+}
+
+void row_factors(int64_t H, std::vector<double2> &A, std::vector<double> &s2) {
     A.resize(H);
     s2.resize(H);
     for (int64_t r = 0; r < H; ++r) {
         const int64_t j = r + 1;                      // angle y/2 = (pi/2) j / H
-        const long double sj = (2 * j <= H) ? sinl(HALF_PI * (long double)j / (long double)H)
-                                            : cosl(HALF_PI * (long double)(H - j) / (long double)H);
+        const long double sj = row_half_sine(j, H);
         A[r] = dd_split(2.0L * sj * sj);
         s2[r] = (double)(2.0L * sj);
     }
@@ -425,6 +442,7 @@ lc_status lc_plan_nodes(lc_plan_t p, const double **x_dev, int64_t *rows, int32_
 
 // Shared helpers for timing (used by all plan kinds).
 namespace lc {
+lc_status execute_adaptive(lc_plan_s *p, const void *f, double *c, hipStream_t s);
 hipError_t timing_begin(lc_plan_s *p, hipStream_t s, int *slot) {
     *slot = -1;
     if (!p->timing) return hipSuccess;
@@ -451,9 +469,11 @@ extern "C" {
 
 lc_status lc_execute(lc_plan_t p, const void *f_dev, double *c_dev, hipStream_t stream) {
     if (!p) return fail(LC_ERR_INVALID, "lc_execute: plan is null");
-    if (p->kind != LC_PLAN_SINGLE) return fail(LC_ERR_INVALID, "lc_execute: not a single-function plan");
+    if (p->kind != LC_PLAN_SINGLE && p->kind != LC_PLAN_ADAPTIVE)
+        return fail(LC_ERR_INVALID, "lc_execute: not a single-function plan");
     if (!f_dev || !c_dev) return fail(LC_ERR_INVALID, "lc_execute: null f_dev or c_dev");
     if (((uintptr_t)f_dev) & 15) return fail(LC_ERR_INVALID, "lc_execute: f_dev must be 16-byte aligned");
+    if (p->kind == LC_PLAN_ADAPTIVE) return execute_adaptive(p, f_dev, c_dev, stream);
     const FnDesc &d = p->fn;
     int slot = -1;
     hipError_t e = timing_begin(p, stream, &slot);
@@ -505,10 +525,13 @@ namespace lc {
 // Implemented in host_batch.cpp / host_gemm.cpp.
 void destroy_batch(lc_plan_s *p);
 void destroy_gemm(lc_plan_s *p);
+void destroy_adaptive(lc_plan_s *p);
 void info_batch(lc_plan_s *p, lc_plan_desc *d);
 void info_gemm(lc_plan_s *p, lc_plan_desc *d);
+void info_adaptive(lc_plan_s *p, lc_plan_desc *d);
 lc_status nodes_batch(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
 lc_status nodes_gemm(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
+lc_status nodes_adaptive(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
 }  // namespace lc
 
 extern "C" {
@@ -529,6 +552,8 @@ lc_status lc_plan_info(lc_plan_t p, lc_plan_desc *d) {
         o.workspace_bytes = p->workspace_bytes;
     } else if (p->kind == LC_PLAN_BATCH) {
         info_batch(p, &o);
+    } else if (p->kind == LC_PLAN_ADAPTIVE) {
+        info_adaptive(p, &o);
     } else {
         info_gemm(p, &o);
     }
@@ -540,6 +565,7 @@ lc_status lc_plan_nodes(lc_plan_t p, const double **x_dev, int64_t *rows, int32_
     if (!p || !x_dev) return fail(LC_ERR_INVALID, "lc_plan_nodes: null argument");
     if (p->kind == LC_PLAN_BATCH) return nodes_batch(p, x_dev, rows, Q);
     if (p->kind == LC_PLAN_GEMM) return nodes_gemm(p, x_dev, rows, Q);
+    if (p->kind == LC_PLAN_ADAPTIVE) return nodes_adaptive(p, x_dev, rows, Q);
     *x_dev = p->x;
     if (rows) *rows = p->fn.H;
     if (Q) *Q = p->fn.Q;
@@ -551,6 +577,7 @@ lc_status lc_plan_destroy(lc_plan_t p) {
     hipDeviceSynchronize();
     if (p->kind == LC_PLAN_BATCH) destroy_batch(p);
     else if (p->kind == LC_PLAN_GEMM) destroy_gemm(p);
+    else if (p->kind == LC_PLAN_ADAPTIVE) destroy_adaptive(p);
     free_single(p);
     delete p;
     return LC_OK;

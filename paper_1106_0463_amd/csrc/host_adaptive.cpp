@@ -1,0 +1,387 @@
+// Adaptive single-function plans: the composite Abel rule of lc_abel_rule
+// (breakpoints, grading toward x = 1, per-row node counts) on the M-point
+// grid, then the twist / FFT / rescale of eq. (2.4) as in a single plan.
+//
+// Host planning follows the rule's specification in long double: per row
+// the cut distances e = 1 - t (breakpoint b: r / (1 + sqrt(1 - r)) with
+// r = (1 - b) / (2 s^2); grading: sigma^k), the panels between them, and for
+// every panel a segment {offset, node count, rule, scale, E, h} with
+// 1 - t_i = E + h d_i.  Distinct (q, kind) Gauss rules are built once
+// (long double Newton) into a padded weight table and a double-double node
+// table.  Rows are grouped by the lanes per row G that their shortest
+// panel fills, one reduction launch per group.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lc_internal.h"
+
+namespace lc {
+
+lc_status fail_status(lc_status s, const std::string &msg);
+hipError_t timing_begin(lc_plan_s *p, hipStream_t s, int *slot);
+hipError_t timing_end(lc_plan_s *p, hipStream_t s, int slot);
+
+namespace {
+
+constexpr int kNG = 5;  // lane groups G = 4, 8, 16, 32, 64
+
+struct AdaptiveState {
+    int64_t nnz = 0, nseg = 0;
+    int qmax = 0;
+    ASeg *segs = nullptr;
+    int32_t *rseg = nullptr;
+    double *wtab = nullptr;
+    double2 *dtab = nullptr;
+    int32_t *rows[kNG] = {};
+    int64_t nrows[kNG] = {};
+    int grid[kNG] = {};
+    std::vector<void *> allocs;
+};
+
+void free_adaptive(AdaptiveState *a) {
+    if (!a) return;
+    for (void *p : a->allocs) hipFree(p);
+    delete a;
+}
+
+template <typename T>
+hipError_t aalloc(AdaptiveState *a, T **p, size_t n, int64_t *ws) {
+    *p = nullptr;
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e == hipSuccess) {
+        a->allocs.push_back(*p);
+        *ws += (int64_t)(n * sizeof(T));
+    }
+    return e;
+}
+
+int ladder(long long n) {
+    if (n <= 128) return (int)(8 * ((n + 7) / 8));
+    int bl = 0;
+    for (long long v = n; v; v >>= 1) ++bl;
+    const long long step = 1LL << (bl - 1 - 4);
+    return (int)(step * ((n + step - 1) / step));
+}
+
+// node count of the panel [t_lo, t_hi] of a row with s = sin(y/2): the band
+// count D s^2 / 2 of a whole row, shared in proportion to t^2 (the phase of
+// cos(D (1 - 2 s^2 (1 - t^2))) over the panel), plus the pad
+int panel_q(long double s, long double t_lo, long double t_hi, const lc_abel_rule &r) {
+    if (!(r.band > 0)) return r.q;
+    long double g = (long double)r.band * s * s / 2 * (t_hi * t_hi - t_lo * t_lo);
+    g += 6.5L * cbrtl(g);
+    const long long n = (long long)r.q + (long long)ceill(g);
+    return (int)std::min<long long>(r.q_max, ladder(n));
+}
+
+// cut distances e = 1 - t in (0, 1), decreasing
+void row_cuts(long double s, const lc_abel_rule &r, std::vector<long double> &out) {
+    std::vector<long double> es;
+    const long double c = 1 - 2 * s * s;
+    for (int i = 0; i < r.nbreak; ++i) {
+        const long double b = r.breaks[i];
+        if (c < b && b < 1) {
+            const long double rr = (1 - b) / (2 * s * s);
+            es.push_back(rr / (1 + sqrtl(1 - rr)));
+        }
+    }
+    if (r.grade_ratio > 0)
+        for (int k = 1; k <= r.grade_levels; ++k) es.push_back(powl((long double)r.grade_ratio, (long double)k));
+    std::sort(es.begin(), es.end(), [](long double a, long double b) { return a > b; });
+    out.clear();
+    for (long double e : es) {
+        if (!(e > 1e-15L && e < 1 - 1e-7L)) continue;  // t <= 1e-7: a breakpoint at the row's end point
+        if (!out.empty() && out.back() - e < 1e-12L * out.front()) continue;
+        out.push_back(e);
+    }
+}
+
+lc_status check_rule(const lc_abel_rule *r) {
+    if (!r) return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: rule is null");
+    if (r->q < 1 || r->q > 65536) return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: q must be in [1, 65536]");
+    if (!(r->band >= 0) || !std::isfinite(r->band))
+        return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: band must be finite and >= 0");
+    if (r->band > 0 && (r->q_max < r->q || r->q_max > 65536))
+        return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: need q <= q_max <= 65536 when band > 0");
+    if (r->nbreak < 0 || r->nbreak > 64 || (r->nbreak > 0 && !r->breaks))
+        return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: nbreak must be in [0, 64] with a breaks array");
+    for (int i = 0; i < r->nbreak; ++i)
+        if (!(r->breaks[i] > -1.0 && r->breaks[i] < 1.0))
+            return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: breakpoints must lie in (-1, 1)");
+    if (!(r->grade_ratio >= 0 && r->grade_ratio < 1) || r->grade_levels < 0 || r->grade_levels > 64)
+        return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: grade_ratio in [0, 1), grade_levels in [0, 64]");
+    const bool cuts = r->nbreak > 0 || (r->grade_ratio > 0 && r->grade_levels > 0);
+    const int qcap = r->band > 0 ? r->q_max : r->q;
+    if (cuts && (qcap % 2))
+        return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: q (or q_max) must be even when the rule has cuts");
+    return LC_OK;
+}
+
+}  // namespace
+
+// The adaptive state owns every device buffer of the plan, including those
+// kept in the shared plan fields: detach them so the single-plan free skips
+// them.
+void detach_shared(lc_plan_s *p) {
+    p->x = nullptr;
+    p->rowA = nullptr;
+    p->s2 = nullptr;
+    p->tw_pre = nullptr;
+    p->tw_pack = nullptr;
+    p->tw_fft = nullptr;
+    p->phi = nullptr;
+    p->zA = nullptr;
+    p->zB = nullptr;
+}
+
+void destroy_adaptive(lc_plan_s *p) {
+    free_adaptive((AdaptiveState *)p->ext);
+    p->ext = nullptr;
+    detach_shared(p);
+}
+
+void info_adaptive(lc_plan_s *p, lc_plan_desc *d) {
+    const AdaptiveState *a = (const AdaptiveState *)p->ext;
+    d->precision = p->fn.prec;
+    d->N = p->fn.N;
+    d->M = p->fn.M;
+    d->M_eff = p->fn.M_eff;
+    d->H = p->fn.H;
+    d->Q = a->qmax;
+    d->samples = a->nnz;
+    d->sample_bytes = a->nnz * (p->fn.prec == LC_FP64 ? 8 : 4);
+    d->workspace_bytes = p->workspace_bytes;
+}
+
+lc_status nodes_adaptive(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q) {
+    *x = p->x;
+    if (rows) *rows = ((AdaptiveState *)p->ext)->nnz;
+    if (Q) *Q = 1;
+    return LC_OK;
+}
+
+lc_status execute_adaptive(lc_plan_s *p, const void *f, double *c, hipStream_t s) {
+    const AdaptiveState *a = (const AdaptiveState *)p->ext;
+    const FnDesc &d = p->fn;
+    int slot = -1;
+    hipError_t e = timing_begin(p, s, &slot);
+    if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute: timing event");
+    for (int gi = 0; gi < kNG; ++gi) {
+        e = launch_aquad(d.prec, 4 << gi, a->grid[gi], f, a->segs, a->rseg, a->rows[gi], a->nrows[gi], a->wtab,
+                         p->s2, p->phi, s);
+        if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute: quadrature: ") + hipGetErrorString(e));
+    }
+    e = timing_end(p, s, slot);
+    if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute: timing event");
+    e = launch_dst(p->dst, p->phi, d.H, d.L, d.N, p->tw_pre, p->tw_pack, p->tw_fft, p->zA, p->zB, c, s);
+    if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute: FFT: ") + hipGetErrorString(e));
+    return LC_OK;
+}
+
+}  // namespace lc
+
+using namespace lc;
+
+extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *rule, lc_precision prec,
+                                      lc_plan_t *out) {
+    if (!out) return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: out is null");
+    lc_status st = check_rule(rule);
+    if (st != LC_OK) return st;
+    if (N < 1 || M < 2 || (M & 1) || N > M / 2)
+        return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: need N >= 1, M even >= 2, N <= M/2");
+    if (prec != LC_FP64 && prec != LC_FP32_QUAD) return fail_status(LC_ERR_INVALID, "lc_plan_adaptive: bad precision");
+    int64_t M_eff = 0;
+    if ((st = lc_grid_size(M, &M_eff)) != LC_OK) return st;
+    const int64_t H = M_eff / 2, L = H / 2;
+    DstCfg dcfg = default_dst_cfg(L);
+    if (L > kLdsFftMax && dcfg.L1 == 0)
+        return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_adaptive: FFT length has no supported four-step split");
+    const lc_abel_rule r = *rule;
+    const int vec = prec == LC_FP64 ? 2 : 4;
+
+    // ---- rows -> panels -> segments (long double, the rule's specification)
+    std::map<std::pair<int, int>, int> rule_id;  // (q, full) -> index
+    std::vector<std::pair<int, int>> rules;
+    struct HSeg {
+        int32_t row, q, rid;
+        long double E, h, scale;
+    };
+    std::vector<HSeg> hs;
+    std::vector<int32_t> rseg(H + 1, 0);
+    std::vector<long double> cuts;
+    auto rid_of = [&](int q, int full) {
+        auto key = std::make_pair(q, full);
+        auto it = rule_id.find(key);
+        if (it != rule_id.end()) return it->second;
+        const int id = (int)rules.size();
+        rule_id[key] = id;
+        rules.push_back(key);
+        return id;
+    };
+    int qmax = 0;
+    for (int64_t rr = 0; rr < H; ++rr) {
+        rseg[rr] = (int32_t)hs.size();
+        const long double sj = row_half_sine(rr + 1, H);
+        row_cuts(sj, r, cuts);
+        const long double e1 = cuts.empty() ? 0.0L : cuts[0];
+        const int q1 = panel_q(sj, 0.0L, 1 - e1, r);
+        qmax = std::max(qmax, q1);
+        hs.push_back({(int32_t)rr, q1, rid_of(q1, 0), e1, 1 - e1, 1 - e1});  // first panel [0, t_1]
+        for (size_t k = 0; k < cuts.size(); ++k) {
+            // panel [1 - hi, 1 - lo] in t
+            const long double hi = cuts[k], lo = k + 1 < cuts.size() ? cuts[k + 1] : 0.0L;
+            const long double h = (hi - lo) / 2;
+            const int q = panel_q(sj, 1 - hi, 1 - lo, r);
+            qmax = std::max(qmax, q);
+            hs.push_back({(int32_t)rr, q, rid_of(q, 1), lo, h, h});
+        }
+        if (hs.size() > (size_t)INT32_MAX / 2)
+            return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_adaptive: too many panels");
+    }
+    rseg[H] = (int32_t)hs.size();
+
+    // ---- Gauss tables: weights padded with zeros, node offsets d = 1 - tau
+    std::vector<int64_t> woff(rules.size());
+    int64_t wlen = 0;
+    for (size_t i = 0; i < rules.size(); ++i) {
+        woff[i] = wlen;
+        wlen += (rules[i].first + 3) / 4 * 4;
+    }
+    std::vector<double> wt(wlen, 0.0);
+    std::vector<double2> dt(wlen, make_double2(0.0, 0.0));
+    for (size_t i = 0; i < rules.size(); ++i) {
+        const int q = rules[i].first;
+        std::vector<long double> x, w;
+        if (rules[i].second == 0) {  // positive half of the 2q-point rule, nodes decreasing
+            gauss_positive_half_ld(2 * q, x, w);
+            for (int k = 0; k < q; ++k) {
+                wt[woff[i] + k] = (double)w[k];
+                dt[woff[i] + k] = dd_split(1.0L - x[k]);
+            }
+        } else {  // the q-point rule (q even), nodes increasing
+            gauss_positive_half_ld(q, x, w);
+            const int h = q / 2;
+            for (int k = 0; k < h; ++k) {
+                wt[woff[i] + k] = (double)w[k];
+                dt[woff[i] + k] = dd_split(1.0L + x[k]);              // tau = -x_k
+                wt[woff[i] + q - 1 - k] = (double)w[k];
+                dt[woff[i] + q - 1 - k] = dd_split(1.0L - x[k]);      // tau = +x_k
+            }
+        }
+    }
+
+    // ---- device segments (sample offsets padded to 4)
+    std::vector<ASeg> segs(hs.size());
+    int64_t off = 0;
+    for (size_t k = 0; k < hs.size(); ++k) {
+        const HSeg &h = hs[k];
+        ASeg &a = segs[k];
+        a.off = off;
+        a.q = h.q;
+        a.qp = (h.q + 3) / 4 * 4;
+        a.woff = (int32_t)woff[h.rid];
+        a.scale = (double)h.scale;
+        a.row = h.row;
+        a.E = dd_split(h.E);
+        a.h = dd_split(h.h);
+        off += a.qp;
+    }
+    const int64_t nnz = off;
+    if ((double)nnz > 4.0e10) return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_adaptive: too many samples");
+
+    // ---- lane groups: G = the largest power of two <= the shortest panel's chunks (4..64)
+    std::vector<int32_t> grows[kNG];
+    for (int64_t rr = 0; rr < H; ++rr) {
+        int mc = 1 << 30;
+        for (int k = rseg[rr]; k < rseg[rr + 1]; ++k) mc = std::min(mc, segs[k].qp / vec);
+        int gi = 0;
+        while (gi + 1 < kNG && (4 << (gi + 1)) <= mc) ++gi;
+        grows[gi].push_back((int32_t)rr);
+    }
+
+    std::vector<double2> rowA, pre, pack, fft;
+    std::vector<double> s2h;
+    row_factors(H, rowA, s2h);
+    twiddles(H, pre, pack, fft);
+
+    lc_plan_s *p = new (std::nothrow) lc_plan_s();
+    AdaptiveState *a = new (std::nothrow) AdaptiveState();
+    if (!p || !a) {
+        delete p;
+        delete a;
+        return fail_status(LC_ERR_NOMEM, "lc_plan_adaptive: host allocation failed");
+    }
+    p->kind = LC_PLAN_ADAPTIVE;
+    hipGetDevice(&p->device);
+    p->ext = a;
+    p->fn.N = N;
+    p->fn.M = M;
+    p->fn.M_eff = M_eff;
+    p->fn.H = H;
+    p->fn.L = L;
+    p->fn.Q = 1;
+    p->fn.prec = (int)prec;
+    p->dst = dcfg;
+    a->nnz = nnz;
+    a->nseg = (int64_t)segs.size();
+    a->qmax = qmax;
+
+    int64_t ws = 0;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    auto up = [&](auto *dst, const auto &v) {
+        if (e == hipSuccess && !v.empty())
+            chk(hipMemcpy(dst, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice));
+    };
+    chk(aalloc(a, &p->x, (size_t)nnz, &ws));
+    chk(aalloc(a, &a->segs, segs.size(), &ws));
+    chk(aalloc(a, &a->rseg, rseg.size(), &ws));
+    chk(aalloc(a, &a->wtab, wt.size(), &ws));
+    chk(aalloc(a, &a->dtab, dt.size(), &ws));
+    chk(aalloc(a, &p->rowA, (size_t)H, &ws));
+    chk(aalloc(a, &p->s2, (size_t)H, &ws));
+    chk(aalloc(a, &p->tw_pre, (size_t)H, &ws));
+    chk(aalloc(a, &p->tw_pack, (size_t)L, &ws));
+    chk(aalloc(a, &p->tw_fft, (size_t)L, &ws));
+    chk(aalloc(a, &p->phi, (size_t)H, &ws));
+    if (L > kLdsFftMax) {
+        chk(aalloc(a, &p->zA, (size_t)L, &ws));
+        chk(aalloc(a, &p->zB, (size_t)L, &ws));
+    }
+    for (int gi = 0; gi < kNG; ++gi) {
+        chk(aalloc(a, &a->rows[gi], grows[gi].size(), &ws));
+        up(a->rows[gi], grows[gi]);
+        a->nrows[gi] = (int64_t)grows[gi].size();
+        const int64_t per_block = 4 * (64 / (4 << gi));
+        a->grid[gi] = (int)std::max<int64_t>(1, std::min<int64_t>((a->nrows[gi] + per_block - 1) / per_block,
+                                                                  (int64_t)device_cu_count() * 8));
+    }
+    up(a->segs, segs);
+    up(a->rseg, rseg);
+    up(a->wtab, wt);
+    up(a->dtab, dt);
+    up(p->rowA, rowA);
+    up(p->s2, s2h);
+    up(p->tw_pre, pre);
+    up(p->tw_pack, pack);
+    up(p->tw_fft, fft);
+    if (e == hipSuccess) chk(launch_anodes(a->segs, a->nseg, a->dtab, p->rowA, p->x, 0));
+    if (e == hipSuccess) chk(hipDeviceSynchronize());
+    if (e != hipSuccess) {
+        detach_shared(p);
+        free_adaptive(a);
+        delete p;
+        return fail_status(e == hipErrorOutOfMemory ? LC_ERR_NOMEM : LC_ERR_HIP,
+                           std::string("lc_plan_adaptive: ") + hipGetErrorString(e));
+    }
+    p->workspace_bytes = ws;
+    *out = p;
+    return LC_OK;
+}

@@ -5,6 +5,7 @@
 //     with the twist and the (2n+1) rescale; four-step form for long FFTs.
 #include <hip/hip_runtime.h>
 
+#include "dd_device.h"
 #include "fft_lds.h"
 #include "lc_internal.h"
 #include "quad_device.h"
@@ -41,17 +42,6 @@ __global__ __launch_bounds__(256) void k_nodes(int64_t H, int Q, const double2 *
 
 // The same construction for many functions at once (batch plans): block t
 // builds nodes [begin, end) of tiles[t].
-__device__ __forceinline__ double node_dd(double2 a, double2 b) {
-#pragma clang fp contract(off)
-    const double p = a.x * b.x;
-    double e = fma(a.x, b.x, -p);
-    e = fma(a.x, b.y, fma(a.y, b.x, e));
-    const double s = 1.0 - p;
-    const double bb = s - 1.0;
-    const double err = (1.0 - (s - bb)) + (-p - bb);
-    return s + (err - e);
-}
-
 __global__ __launch_bounds__(256) void k_bnodes(const NodeTile *__restrict__ tiles) {
     const NodeTile t = tiles[blockIdx.x];
     for (int64_t idx = t.begin + threadIdx.x; idx < t.end; idx += 256) {

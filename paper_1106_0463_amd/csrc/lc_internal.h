@@ -132,6 +132,26 @@ struct lc_plan_s {
 namespace lc {
 
 // --- launchers (kernels_single.hip) ---------------------------------------
+// One panel of one row of a composite Abel rule: q nodes (padded to qp, a
+// multiple of 4) at element offset off of the sample array, with
+// 1 - t = E + h d_i (d_i from the rule's node table at woff) and weights
+// scale * w_i (the rule's padded weight table at woff).
+struct ASeg {
+    int64_t off;
+    int32_t qp;
+    int32_t woff;
+    double scale;
+    int32_t q;
+    int32_t row;
+    double2 E;
+    double2 h;
+};
+
+hipError_t launch_anodes(const ASeg *segs, int64_t nseg, const double2 *dtab, const double2 *rowA, double *x,
+                         hipStream_t s);
+hipError_t launch_aquad(int prec, int G, int grid, const void *f, const ASeg *segs, const int32_t *rseg,
+                        const int32_t *rows, int64_t nrows, const double *wtab, const double *s2, double *phi,
+                        hipStream_t s);
 hipError_t launch_nodes(int64_t H, int Q, const double2 *A, const double2 *B, double *x,
                         hipStream_t s);
 hipError_t launch_bnodes(const NodeTile *tiles, int64_t ntiles, hipStream_t s);
@@ -167,6 +187,9 @@ FftSched make_sched(int L, const int *order = nullptr);
 void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w,
                      std::vector<double2> &omt2);
 void row_factors(int64_t H, std::vector<double2> &A, std::vector<double> &s2);
+void gauss_positive_half_ld(int n, std::vector<long double> &x, std::vector<long double> &w);
+long double row_half_sine(int64_t j, int64_t H);  // sin(pi j / (2H))
+double2 dd_split(long double v);
 void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack,
               std::vector<double2> &fft);
 QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu);

@@ -51,6 +51,14 @@ def cos_coeffs(omega: float, N: int) -> np.ndarray:
     return np.array(out, dtype=object)
 
 
+def cos_coeff(omega: float, n: int) -> mp.mpf:
+    """One coefficient of :func:`cos_coeffs`."""
+    if n % 2:
+        return mp.mpf(0)
+    w = mp.mpf(omega)
+    return (2 * n + 1) * (-1) ** (n // 2) * mp.sqrt(mp.pi / (2 * w)) * mp.besselj(n + mp.mpf(1) / 2, w)
+
+
 def abs_pow_coeffs(N: int, alpha: Fraction = Fraction(3, 2)) -> list:
     """Closed form printed before Table 1 (Section 2) for f = |x|^alpha,
     read as: 0 for odd n; 1/(alpha+1) for n = 0; otherwise

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -88,3 +89,19 @@ def test_null_arguments_rejected(lib):
 
 def test_autotune_rejects_null(lib):
     assert lib.lc_autotune(None, None) == 1
+
+
+@pytest.mark.parametrize("rule", [dict(q=0), dict(q=7, breaks=(0.0,)), dict(q=8, band=100.0, q_max=4),
+                                  dict(q=8, breaks=(1.5,)), dict(q=8, grade_ratio=1.0, grade_levels=2),
+                                  dict(q=8, band=-1.0), dict(q=8, breaks=tuple(np.linspace(-0.9, 0.9, 65)))])
+def test_adaptive_rule_rejected(rule):
+    # the rule is validated before any device work
+    import paper_1106_0463_amd as lc
+    with pytest.raises(lc.LCError) as ei:
+        lc.plan_adaptive(16, 64, **rule)
+    assert ei.value.status == 1
+
+
+def test_adaptive_null_rule(lib):
+    h = C.c_void_p()
+    assert lib.lc_plan_adaptive(16, 64, None, 0, C.byref(h)) == 1
