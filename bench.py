@@ -98,7 +98,7 @@ def bench_single(args, N, M, Q, f, name, rule=None):
 
     import paper_1106_0463_amd as lc
     p = lc.plan_adaptive(N, M, **rule) if rule else lc.plan(N, M, Q)
-    if args.autotune and not rule:
+    if args.autotune:
         p.autotune()
     info = p.info
     x = p.nodes

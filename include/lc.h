@@ -251,10 +251,12 @@ lc_status lc_plan_gemm_reserve(lc_plan_t plan, int32_t B_max);
 lc_status lc_plan_gemm_matrix(lc_plan_t plan, const double **A_dev);
 
 /* Times the plan's kernel variants (quadrature lanes per row and rows per
- * block, FFT radix schedule and threads) on the plan's own buffers and
+ * block, FFT radix schedule and threads; for adaptive plans the largest
+ * lane group of the segmented reduction) on the plan's own buffers and
  * keeps the fastest; results persist in the file named by LC_AUTOTUNE_CACHE
- * (if set), keyed by device architecture, H, Q and precision.  Synchronizes
- * stream.  Errors: LC_ERR_INVALID, LC_ERR_HIP, LC_ERR_NOMEM. */
+ * (if set), keyed by device architecture and the plan's shape.  GEMM plans
+ * have one launch shape: LC_OK.  Synchronizes stream.
+ * Errors: LC_ERR_INVALID, LC_ERR_HIP, LC_ERR_NOMEM. */
 lc_status lc_autotune(lc_plan_t plan, hipStream_t stream);
 
 /* Frees the plan and all of its device memory (synchronizes the device

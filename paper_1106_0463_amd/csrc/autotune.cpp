@@ -21,6 +21,7 @@ namespace lc {
 lc_status fail_status(lc_status s, const std::string &msg);
 lc_status tune_single(lc_plan_s *p, hipStream_t s);
 lc_status tune_batch(lc_plan_s *p, hipStream_t s);
+lc_status tune_adaptive(lc_plan_s *p, hipStream_t s);
 
 static std::mutex g_cache_mu;
 
@@ -167,5 +168,6 @@ extern "C" lc_status lc_autotune(lc_plan_t p, hipStream_t stream) {
     if (!p) return lc::fail_status(LC_ERR_INVALID, "lc_autotune: plan is null");
     if (p->kind == LC_PLAN_SINGLE) return lc::tune_single(p, stream);
     if (p->kind == LC_PLAN_BATCH) return lc::tune_batch(p, stream);
+    if (p->kind == LC_PLAN_ADAPTIVE) return lc::tune_adaptive(p, stream);
     return LC_OK;  // GEMM plans have a single launch shape
 }

@@ -8,12 +8,14 @@
 // every panel a segment {offset, node count, rule, scale, E, h} with
 // 1 - t_i = E + h d_i.  Distinct (q, kind) Gauss rules are built once
 // (long double Newton) into a padded weight table and a double-double node
-// table.  Rows are grouped by the lanes per row G that their shortest
-// panel fills, one reduction launch per group.
+// table.  Rows are grouped by the lanes per row G that their length fills,
+// one reduction launch per group, longest rows first.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <functional>
 #include <map>
 #include <new>
 #include <string>
@@ -24,6 +26,10 @@
 namespace lc {
 
 lc_status fail_status(lc_status s, const std::string &msg);
+std::string arch_name();
+bool cache_get(const std::string &key, std::string &val);
+void cache_put(const std::string &key, const std::string &val);
+double time_launch(const std::function<hipError_t(hipStream_t)> &f, hipStream_t s, int reps, hipError_t *err);
 hipError_t timing_begin(lc_plan_s *p, hipStream_t s, int *slot);
 hipError_t timing_end(lc_plan_s *p, hipStream_t s, int slot);
 
@@ -34,6 +40,8 @@ constexpr int kNG = 5;  // lane groups G = 4, 8, 16, 32, 64
 struct AdaptiveState {
     int64_t nnz = 0, nseg = 0;
     int qmax = 0;
+    int gcap = 2;                // largest lane group used (G = 4 << gcap)
+    std::vector<int64_t> rlen;   // chunks per row (host), for regrouping
     ASeg *segs = nullptr;
     int32_t *rseg = nullptr;
     double *wtab = nullptr;
@@ -101,6 +109,42 @@ void row_cuts(long double s, const lc_abel_rule &r, std::vector<long double> &ou
         if (!out.empty() && out.back() - e < 1e-12L * out.front()) continue;
         out.push_back(e);
     }
+}
+
+// Lane groups: G = the largest power of two <= a quarter of the row's chunks
+// (4 .. 4 << gcap; lanes past a short panel's end idle through it); within a
+// group the longest rows go first, so that a launch does not end on a few
+// long rows.
+void group_rows(const std::vector<int64_t> &rlen, int gcap, std::vector<int32_t> *grows) {
+    for (int gi = 0; gi < kNG; ++gi) grows[gi].clear();
+    for (size_t rr = 0; rr < rlen.size(); ++rr) {
+        int gi = 0;
+        while (gi + 1 <= gcap && (int64_t)(4 << (gi + 1)) * 4 <= rlen[rr]) ++gi;
+        grows[gi].push_back((int32_t)rr);
+    }
+    for (int gi = 0; gi < kNG; ++gi)
+        std::stable_sort(grows[gi].begin(), grows[gi].end(),
+                         [&](int32_t a, int32_t b) { return rlen[a] > rlen[b]; });
+}
+
+// uploads the row lists of grows into a's (preallocated, H entries in all)
+// group arrays and sets the launch grids
+hipError_t set_groups(AdaptiveState *a, const std::vector<int32_t> *grows) {
+    int64_t off = 0;
+    for (int gi = 0; gi < kNG; ++gi) {
+        a->rows[gi] = a->rows[0] + off;
+        a->nrows[gi] = (int64_t)grows[gi].size();
+        if (!grows[gi].empty()) {
+            hipError_t e = hipMemcpy(a->rows[gi], grows[gi].data(), grows[gi].size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice);
+            if (e != hipSuccess) return e;
+        }
+        off += a->nrows[gi];
+        const int64_t per_block = 4 * (64 / (4 << gi));
+        a->grid[gi] = (int)std::max<int64_t>(1, std::min<int64_t>((a->nrows[gi] + per_block - 1) / per_block,
+                                                                  (int64_t)device_cu_count() * 8));
+    }
+    return hipSuccess;
 }
 
 lc_status check_rule(const lc_abel_rule *r) {
@@ -182,6 +226,47 @@ lc_status execute_adaptive(lc_plan_s *p, const void *f, double *c, hipStream_t s
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute: timing event");
     e = launch_dst(p->dst, p->phi, d.H, d.L, d.N, p->tw_pre, p->tw_pack, p->tw_fft, p->zA, p->zB, c, s);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute: FFT: ") + hipGetErrorString(e));
+    return LC_OK;
+}
+
+// Autotuning: the largest lane group (G = 16, 32 or 64 lanes per row for the
+// long rows), timed on the plan's own node array standing in for samples.
+lc_status tune_adaptive(lc_plan_s *p, hipStream_t s) {
+    AdaptiveState *a = (AdaptiveState *)p->ext;
+    const std::string key = arch_name() + "|adaptive|" + std::to_string(p->fn.H) + "|" +
+                            std::to_string(a->nnz) + "|" + std::to_string(a->nseg) + "|" + std::to_string(p->fn.prec);
+    std::string cached;
+    std::vector<int32_t> grows[kNG];
+    int best = a->gcap;
+    if (cache_get(key, cached)) {
+        best = std::max(0, std::min(kNG - 1, atoi(cached.c_str())));
+    } else {
+        double best_ms = 1e30;
+        for (int gc = 1; gc < kNG; ++gc) {
+            group_rows(a->rlen, gc, grows);
+            hipError_t e = set_groups(a, grows);
+            if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: row groups");
+            const FnDesc &d = p->fn;
+            auto run = [&](hipStream_t st) {
+                for (int gi = 0; gi < kNG; ++gi) {
+                    hipError_t r = launch_aquad(d.prec, 4 << gi, a->grid[gi], p->x, a->segs, a->rseg, a->rows[gi],
+                                                a->nrows[gi], a->wtab, p->s2, p->phi, st);
+                    if (r != hipSuccess) return r;
+                }
+                return hipSuccess;
+            };
+            const double ms = time_launch(run, s, 5, &e);
+            if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: timing");
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = gc;
+            }
+        }
+        cache_put(key, std::to_string(best));
+    }
+    group_rows(a->rlen, best, grows);
+    if (set_groups(a, grows) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: row groups");
+    a->gcap = best;
     return LC_OK;
 }
 
@@ -296,15 +381,13 @@ extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *
     const int64_t nnz = off;
     if ((double)nnz > 4.0e10) return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_adaptive: too many samples");
 
-    // ---- lane groups: G = the largest power of two <= the shortest panel's chunks (4..64)
+    std::vector<int64_t> rlen(H, 0);
+    for (int64_t rr = 0; rr < H; ++rr)
+        for (int k = rseg[rr]; k < rseg[rr + 1]; ++k) rlen[rr] += segs[k].qp / vec;
     std::vector<int32_t> grows[kNG];
-    for (int64_t rr = 0; rr < H; ++rr) {
-        int mc = 1 << 30;
-        for (int k = rseg[rr]; k < rseg[rr + 1]; ++k) mc = std::min(mc, segs[k].qp / vec);
-        int gi = 0;
-        while (gi + 1 < kNG && (4 << (gi + 1)) <= mc) ++gi;
-        grows[gi].push_back((int32_t)rr);
-    }
+    int gcap = 2;  // G <= 16 lanes per row: measured best on the large band-limited rule
+    if (const char *ev = getenv("LC_AQUAD_GMAX")) gcap = std::max(0, std::min(kNG - 1, atoi(ev)));
+    group_rows(rlen, gcap, grows);
 
     std::vector<double2> rowA, pre, pack, fft;
     std::vector<double> s2h;
@@ -355,14 +438,10 @@ extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *
         chk(aalloc(a, &p->zA, (size_t)L, &ws));
         chk(aalloc(a, &p->zB, (size_t)L, &ws));
     }
-    for (int gi = 0; gi < kNG; ++gi) {
-        chk(aalloc(a, &a->rows[gi], grows[gi].size(), &ws));
-        up(a->rows[gi], grows[gi]);
-        a->nrows[gi] = (int64_t)grows[gi].size();
-        const int64_t per_block = 4 * (64 / (4 << gi));
-        a->grid[gi] = (int)std::max<int64_t>(1, std::min<int64_t>((a->nrows[gi] + per_block - 1) / per_block,
-                                                                  (int64_t)device_cu_count() * 8));
-    }
+    chk(aalloc(a, &a->rows[0], (size_t)H, &ws));  // all groups' row lists, back to back
+    if (e == hipSuccess) chk(set_groups(a, grows));
+    a->gcap = gcap;
+    a->rlen = std::move(rlen);
     up(a->segs, segs);
     up(a->rseg, rseg);
     up(a->wtab, wt);

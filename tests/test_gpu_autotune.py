@@ -74,3 +74,22 @@ def test_batch_autotune_keeps_results(lc):
         a1 = c1[c_off[b]:c_off[b + 1]].cpu().numpy()
         assert rel_err(a1, a0) <= 1e-12, b
     bp.destroy()
+
+
+def test_adaptive_autotune_keeps_results(lc, tmp_path):
+    import torch
+    banner("[gpu] autotune adaptive plan (lane groups)")
+    os.environ["LC_AUTOTUNE_CACHE"] = str(tmp_path / "cache_a.txt")
+    f = W.Sum(W.Cosine(900.0), W.GeneratingFunction(0.9))
+    rule = dict(q=16, band=900.0, q_max=2048, grade_ratio=0.2, grade_levels=3)
+    p = lc.plan_adaptive(1500, 6000, **rule)
+    fx = f.torch(p.nodes).contiguous()
+    c0 = p.execute(fx).clone()
+    p.autotune()
+    c1 = p.execute(fx).clone()
+    torch.cuda.synchronize()
+    assert rel_err(c1.cpu().numpy(), c0.cpu().numpy()) <= 5e-14
+    with open(os.environ["LC_AUTOTUNE_CACHE"]) as fh:
+        assert "adaptive" in fh.read()
+    p.destroy()
+    del os.environ["LC_AUTOTUNE_CACHE"]
