@@ -62,12 +62,22 @@ __device__ __forceinline__ double row_partial(const T *__restrict__ frow, const 
             acc1 = fma(w[(c + 3 * G) * VEC + e], dd_[e], acc1);
         }
     }
-    for (; c < NC; c += G) {
-        V a = ld_stream(p + c);
-        double da[VEC];
-        to_d(a, da);
+    // the lane's last (at most 3) chunks: all loads in flight before the
+    // first use, rather than one dependent round trip per chunk
+    if (c < NC) {
+        const bool h1 = c + G < NC, h2 = c + 2 * G < NC;
+        const V zero = V{};
+        const V a = ld_stream(p + c);
+        const V b = h1 ? ld_stream(p + c + G) : zero;
+        const V cc = h2 ? ld_stream(p + c + 2 * G) : zero;
+        double da[VEC], db[VEC], dc[VEC];
+        to_d(a, da); to_d(b, db); to_d(cc, dc);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc0 = fma(w[c * VEC + e], da[e], acc0);
+        for (int e = 0; e < VEC; ++e) {
+            acc0 = fma(w[c * VEC + e], da[e], acc0);
+            if (h1) acc1 = fma(w[(c + G) * VEC + e], db[e], acc1);
+            if (h2) acc0 = fma(w[(c + 2 * G) * VEC + e], dc[e], acc0);
+        }
     }
     return acc0 + acc1;
 }
