@@ -25,9 +25,10 @@ from ._lib import build, load, threads  # noqa: F401
 from .definition import (gauss_legendre, legendre_coeffs,  # noqa: F401
                          legendre_coeffs_from_samples,
                          legendre_coeffs_piecewise, legendre_eval)
-from .method import (abel_fhat, abel_nodes, abel_phi, abel_phi_rule,  # noqa: F401
+from .method import (abel_fhat, abel_node_set, abel_nodes, abel_phi, abel_phi_rule,  # noqa: F401
                      abel_rule_cuts, abel_rule_ladder, abel_rule_node_count, abel_rule_panel_q,
                      abel_rule_row_q,
                      coeffs_from_fhat, fhat_from_phi, fourier_coeffs, fourier_coeffs_at,
-                     method_coeffs, method_coeffs_at, method_coeffs_rule,
+                     method_coeffs, method_coeffs_2d, method_coeffs_at, method_coeffs_from_samples,
+                     method_coeffs_rule,
                      positive_half_samples, y_grid)

@@ -328,3 +328,65 @@ def method_coeffs_rule(f, N: int, M: int, rule: dict, fp64_nodes: bool = False) 
     phi_abs = np.where(idx == 0, LD(0), phi_pos[np.maximum(idx, 1) - 1])
     fh = fhat_from_phi(phi_abs, y)
     return coeffs_from_fhat(fh, N)
+
+
+# ----------------------------------------------------------------------------
+# Two-dimensional tensor-product transform (the extension named in the
+# paper's closing remarks):
+#     c_{nm} = (n + 1/2)(m + 1/2) integral integral f(x1, x2) P_n(x1) P_m(x2),
+# by the one-dimensional method along x1 for every sample point of x2, then
+# along x2 for every n.  Both axes use the same Abel nodes (the positive half
+# of the grid times the Gauss nodes), so the samples are f(X_a, X_b) on the
+# product of the 1-D node set with itself.
+
+def abel_node_set(M: int, Q: int) -> np.ndarray:
+    """The 1-D Abel nodes in the [M/2][Q] layout of positive_half_samples
+    (rows y = pi j / (M/2), j = 1..M/2; columns the positive Gauss nodes,
+    decreasing), long double."""
+    H = int(M) // 2
+    yg = np.abs(y_grid(M))
+    y = np.concatenate([yg[H + 1:], yg[:1]])
+    T, _ = gauss_legendre(2 * int(Q))
+    return abel_nodes(y, T[:int(Q)])
+
+
+def method_coeffs_from_samples(samples: np.ndarray, N: int, M: int, Q: int) -> np.ndarray:
+    """The method from given samples s[j-1][q] = f(x_{jq}) at the nodes of
+    :func:`abel_node_set` (the last axis may carry several functions:
+    s[j-1][q][k]): phi_j = 2 sin(y_j/2) (1/2) sum_q W_q s[j][q] (the folded
+    2Q-point rule of abel_phi), then eq. (2.5), the trapezoid form of
+    eq. (2.4) and c_n = (2n+1) a_n.  Returns [N] or [N][k]."""
+    s = np.asarray(samples, dtype=LD)
+    H = int(M) // 2
+    T, W = gauss_legendre(2 * int(Q))
+    # the full 2Q-point sum of an even integrand is twice the positive half
+    integral = LD(0.5) * 2 * np.tensordot(W[:int(Q)], s, axes=([0], [1]))   # [H] or [H][k]
+    j = np.arange(1, H + 1, dtype=LD)
+    yp = PI * j / H
+    phi_pos = (np.sqrt(2 * (1 - np.cos(yp))) * integral.T).T
+    y = y_grid(M)
+    k = np.arange(int(M))
+    idx = np.abs(k - H)
+    sel = np.maximum(idx, 1) - 1
+    phi_abs = phi_pos[sel]
+    phi_abs[idx == 0] = 0
+    if phi_abs.ndim == 1:
+        return coeffs_from_fhat(fhat_from_phi(phi_abs, y), N)
+    out = np.empty((int(N), phi_abs.shape[1]), dtype=LD)
+    for c in range(phi_abs.shape[1]):
+        out[:, c] = coeffs_from_fhat(fhat_from_phi(phi_abs[:, c], y), N)
+    return out
+
+
+def method_coeffs_2d(f2, N: int, M: int, Q: int, fp64_nodes: bool = True) -> np.ndarray:
+    """c[n1][n2] of f2(x1, x2) by the method along x1 (for every node of x2),
+    then along x2.  fp64_nodes rounds the nodes to FP64 before f2 is
+    evaluated (long double) there."""
+    X = abel_node_set(M, Q).reshape(-1)
+    if fp64_nodes:
+        X = X.astype(np.float64).astype(LD)
+    H, Qi = int(M) // 2, int(Q)
+    F = np.asarray(f2(X[:, None], X[None, :]), dtype=LD)          # F[a][b] = f(X_a, X_b)
+    c1 = method_coeffs_from_samples(F.reshape(H, Qi, -1), N, M, Q)   # [n1][b]
+    c2 = method_coeffs_from_samples(c1.T.reshape(H, Qi, -1), N, M, Q)  # [n2][n1]
+    return c2.T
