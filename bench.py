@@ -16,7 +16,8 @@ twist, FFT and rescale over one resident batch of samples):
 Other workloads (--workload): single_small (N=64, M=256, Q=32), batch
 (4096 ragged random Legendre series, Q=48), gemm (Abel-as-GEMM, P=4096,
 B=16384; --form direct: the direct Legendre-matrix product), stream
-(65536-function Pareto mix).
+(65536-function Pareto mix), tensor2d (2-D tensor-product transform, N=256
+per axis).
 
 Prints one JSON line.  ``roofline`` is for the dominant kernel, timed with
 HIP events that the library records around it on the execute stream;
@@ -411,6 +412,63 @@ def run_gemm(args):
     return line
 
 
+def run_tensor2d(args):
+    """Two-dimensional tensor-product plan: f(x1, x2) = exp(x1 x2) + x1^2
+    cos(3 x2), N = 256 per axis, M = 1024, Q = 32 (S = 16384 nodes per axis,
+    S^2 = 2.7e8 FP64 samples)."""
+    import numpy as np
+    import torch
+
+    import paper_1106_0463_amd as lc
+    N, M, Q = 256, 1024, 32
+    p = lc.plan_2d(N, M, Q)
+    info = p.info
+    X = p.nodes.reshape(-1)
+    F = (torch.exp(X[None, :] * X[:, None]) + X[None, :] ** 2 * torch.cos(3 * X[:, None])).contiguous()
+    del X
+    C = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    step = lambda: p.execute(F, C)
+    sec = time_steps(step, args.steps, args.warmup)
+    p.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    _sync()
+    kms, cnt = p.kernel_ms()
+    p.set_timing(False)
+    H, S = info["H"], info["H"] * info["Q"]
+    alg_bytes = 8.0 * S * S + 16.0 * S * H
+    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    line = {"metric": METRIC, "value": N * N / sec, "unit": "coefficients/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "2-D tensor-product transform of exp(x1 x2) + x1^2 cos(3 x2), "
+                                   "N=256 x 256, M=1024, Q=32 on both axes, FP64",
+                       "N": N, "M": M, "Q": Q, "S": S, "samples": S * S},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_quad_* over the S*H rows of the first pass",
+                         "kernel_ms": kms, "alg_bytes_per_launch": alg_bytes}}
+    p.destroy()
+    del F
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        K = N + 48
+        x, w = oracle.gauss_legendre(K)
+        xl = x.astype(np.longdouble)
+        Fk = np.exp(xl[:, None] * xl[None, :]) + xl[:, None] ** 2 * np.cos(3 * xl[None, :])
+        step1 = np.stack([oracle.legendre_coeffs_from_samples(x, w, Fk[:, k], N) for k in range(K)], axis=1)
+        for n in range(N):
+            oracle.legendre_coeffs_from_samples(x, w, step1[n, :], N)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": N * N / dt, "unit": "coefficients/s", "cores": oracle.threads(),
+                                "kind": "oracle",
+                                "sample": f"all {N}x{N} coefficients of the same f by eq. (2.3) along both "
+                                          f"axes with a {K}-point long-double Gauss-Legendre rule, {dt:.2f} s"}
+    return line
+
+
 def run_copy(args):
     """Plain device copy of 4 GiB (torch copy kernel): the reference point
     that scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -430,7 +488,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_large",
-                    choices=["single_large", "single_small", "batch", "gemm", "stream", "copy"])
+                    choices=["single_large", "single_small", "batch", "gemm", "stream", "tensor2d", "copy"])
     ap.add_argument("--q", type=int, default=0, help="override Q (single_large, uniform rule)")
     ap.add_argument("--rule", default="band", choices=["band", "uniform"],
                     help="single_large: composite Abel rule with per-row node counts, or the uniform rule")
@@ -463,6 +521,8 @@ def main():
         line = run_batch(args)
     elif args.workload == "stream":
         line = run_stream(args)
+    elif args.workload == "tensor2d":
+        line = run_tensor2d(args)
     else:
         line = run_gemm(args)
     print(json.dumps(line), flush=True)

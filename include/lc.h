@@ -79,7 +79,8 @@ typedef enum {
     LC_PLAN_BATCH = 1,
     LC_PLAN_GEMM = 2,            /* Abel product + batched twist/FFT/rescale     */
     LC_PLAN_LEGENDRE_MATRIX = 3, /* one product with the full N x P matrix       */
-    LC_PLAN_ADAPTIVE = 4         /* single function, composite Abel rule         */
+    LC_PLAN_ADAPTIVE = 4,        /* single function, composite Abel rule         */
+    LC_PLAN_2D = 5               /* two-dimensional tensor-product transform     */
 } lc_plan_kind;
 
 /* Composite Abel rule of an adaptive plan (lc_plan_adaptive).  With
@@ -160,6 +161,23 @@ lc_status lc_plan(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t 
  * Errors: LC_ERR_INVALID (bad rule or sizes), LC_ERR_NOMEM, LC_ERR_HIP,
  * LC_ERR_UNSUPPORTED (too many samples). */
 lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *rule, lc_precision prec, lc_plan_t *out);
+
+/* Two-dimensional tensor-product plan, the extension of the method to
+ * functions on the square:
+ *   c[n1][n2] = (n1 + 1/2)(n2 + 1/2) integral integral f(x1, x2) P_n1(x1) P_n2(x2),
+ * n1, n2 < N, by the one-dimensional method (eq. (2.4) with the Abel rule of
+ * a single plan (N, M, Q)) along x1 for every sample point of x2, then along
+ * x2 for every n1.  Both axes use the S = H Q nodes X of that single plan
+ * (lc_plan_nodes: x[H][Q], flattened as X_a, a = 0..S-1).  The caller
+ * samples F[b][a] = f(X_a, X_b) (S x S row-major, FP64 or FP32 per prec).
+ * Limits: those of lc_plan, M/4 <= 8192, S <= 2e6 and S^2 <= 4e10.
+ * Errors: as lc_plan; LC_ERR_UNSUPPORTED beyond the limits. */
+lc_status lc_plan_2d(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t *out);
+
+/* Executes a 2-D plan: F_dev the S x S samples (16-byte aligned), C_dev an
+ * N x N FP64 array (row n1, column n2).  Asynchronous on stream.
+ * Errors: LC_ERR_INVALID, LC_ERR_HIP. */
+lc_status lc_execute_2d(lc_plan_t plan, const void *F_dev, double *C_dev, hipStream_t stream);
 
 /* Describes any plan.  Errors: LC_ERR_INVALID on null arguments. */
 lc_status lc_plan_info(lc_plan_t plan, lc_plan_desc *desc);

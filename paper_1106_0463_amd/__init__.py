@@ -20,8 +20,8 @@ import ctypes as C
 from ._lib import (GEMM_MODES, LC_FP32_QUAD, LC_FP64, PRECISIONS, LCError,  # noqa: F401
                    PlanDesc, check, load)
 
-__all__ = ["grid_size", "plan", "plan_adaptive", "plan_batch", "plan_gemm", "plan_legendre_matrix", "Plan",
-           "LCError"]
+__all__ = ["grid_size", "plan", "plan_2d", "plan_adaptive", "plan_batch", "plan_gemm", "plan_legendre_matrix",
+           "Plan", "Plan2D", "LCError"]
 
 
 def _torch():
@@ -105,7 +105,7 @@ class Plan:
         check(self._lib.lc_plan_nodes(self._h, C.byref(ptr), C.byref(rows), C.byref(q)),
               "lc_plan_nodes")
         info = self.info
-        if info["kind"] == 0:
+        if info["kind"] in (0, 5):  # single and 2-D plans: [H, Q]
             return _view(ptr.value, (rows.value, q.value), self)
         return _view(ptr.value, (rows.value,), self)
 
@@ -160,6 +160,33 @@ def plan_adaptive(N: int, M: int, q: int, band: float = 0.0, q_max: int = 0, bre
     check(load().lc_plan_adaptive(int(N), int(M), C.byref(rule), PRECISIONS[precision], C.byref(h)),
           "lc_plan_adaptive")
     return Plan(h)
+
+
+class Plan2D(Plan):
+    """Two-dimensional tensor-product plan (lc_plan_2d): both axes use the
+    S = H Q nodes of ``nodes`` (flattened); samples F[b, a] = f(X_a, X_b)."""
+
+    def execute(self, F, out=None, stream=None):
+        """C[n1, n2] (float64 N x N) from the S x S samples F on the GPU."""
+        torch = _torch()
+        info = self.info
+        want = torch.float64 if info["precision"] == LC_FP64 else torch.float32
+        S = info["H"] * info["Q"]
+        if F.dtype != want or not F.is_cuda or not F.is_contiguous() or F.numel() != S * S:
+            raise ValueError(f"F must be a contiguous {want} CUDA tensor of {S} x {S} samples")
+        N = info["N"]
+        if out is None:
+            out = torch.empty((N, N), dtype=torch.float64, device=F.device)
+        check(self._lib.lc_execute_2d(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(out.data_ptr()),
+                                      _stream_handle(stream)), "lc_execute_2d")
+        return out
+
+
+def plan_2d(N: int, M: int, Q: int, precision: str = "fp64") -> Plan2D:
+    """Two-dimensional plan: N x N coefficients, the 1-D grid (M, Q) on both axes."""
+    h = C.c_void_p()
+    check(load().lc_plan_2d(int(N), int(M), int(Q), PRECISIONS[precision], C.byref(h)), "lc_plan_2d")
+    return Plan2D(h)
 
 
 from .batch import BatchPlan, plan_batch  # noqa: E402,F401

@@ -38,6 +38,8 @@ SIGNATURES = [
     ("lc_grid_size", C.c_int, [_i64, _pi64]),
     ("lc_plan", C.c_int, [_i64, _i64, _i32, C.c_int, C.POINTER(_vp)]),
     ("lc_plan_adaptive", C.c_int, [_i64, _i64, C.POINTER(AbelRule), C.c_int, C.POINTER(_vp)]),
+    ("lc_plan_2d", C.c_int, [_i64, _i64, _i32, C.c_int, C.POINTER(_vp)]),
+    ("lc_execute_2d", C.c_int, [_vp, _vp, _vp, _vp]),
     ("lc_plan_info", C.c_int, [_vp, C.POINTER(PlanDesc)]),
     ("lc_plan_nodes", C.c_int, [_vp, C.POINTER(_vp), _pi64, _pi32]),
     ("lc_execute", C.c_int, [_vp, _vp, _vp, _vp]),

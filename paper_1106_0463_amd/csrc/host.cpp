@@ -526,12 +526,15 @@ namespace lc {
 void destroy_batch(lc_plan_s *p);
 void destroy_gemm(lc_plan_s *p);
 void destroy_adaptive(lc_plan_s *p);
+void destroy_2d(lc_plan_s *p);
 void info_batch(lc_plan_s *p, lc_plan_desc *d);
 void info_gemm(lc_plan_s *p, lc_plan_desc *d);
 void info_adaptive(lc_plan_s *p, lc_plan_desc *d);
+void info_2d(lc_plan_s *p, lc_plan_desc *d);
 lc_status nodes_batch(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
 lc_status nodes_gemm(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
 lc_status nodes_adaptive(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
+lc_status nodes_2d(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
 }  // namespace lc
 
 extern "C" {
@@ -554,6 +557,8 @@ lc_status lc_plan_info(lc_plan_t p, lc_plan_desc *d) {
         info_batch(p, &o);
     } else if (p->kind == LC_PLAN_ADAPTIVE) {
         info_adaptive(p, &o);
+    } else if (p->kind == LC_PLAN_2D) {
+        info_2d(p, &o);
     } else {
         info_gemm(p, &o);
     }
@@ -566,6 +571,7 @@ lc_status lc_plan_nodes(lc_plan_t p, const double **x_dev, int64_t *rows, int32_
     if (p->kind == LC_PLAN_BATCH) return nodes_batch(p, x_dev, rows, Q);
     if (p->kind == LC_PLAN_GEMM) return nodes_gemm(p, x_dev, rows, Q);
     if (p->kind == LC_PLAN_ADAPTIVE) return nodes_adaptive(p, x_dev, rows, Q);
+    if (p->kind == LC_PLAN_2D) return nodes_2d(p, x_dev, rows, Q);
     *x_dev = p->x;
     if (rows) *rows = p->fn.H;
     if (Q) *Q = p->fn.Q;
@@ -578,6 +584,7 @@ lc_status lc_plan_destroy(lc_plan_t p) {
     if (p->kind == LC_PLAN_BATCH) destroy_batch(p);
     else if (p->kind == LC_PLAN_GEMM) destroy_gemm(p);
     else if (p->kind == LC_PLAN_ADAPTIVE) destroy_adaptive(p);
+    else if (p->kind == LC_PLAN_2D) destroy_2d(p);
     free_single(p);
     delete p;
     return LC_OK;

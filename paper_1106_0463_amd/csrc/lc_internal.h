@@ -152,6 +152,10 @@ hipError_t launch_anodes(const ASeg *segs, int64_t nseg, const double2 *dtab, co
 hipError_t launch_aquad(int prec, int G, int grid, const void *f, const ASeg *segs, const int32_t *rseg,
                         const int32_t *rows, int64_t nrows, const double *wtab, const double *s2, double *phi,
                         hipStream_t s);
+// dst[c][r] = src[r][c], R x C row-major FP64
+hipError_t launch_transpose64(const double *src, int64_t R, int64_t C, double *dst, hipStream_t s);
+// dst[r * n + i] = src[i], r < reps
+hipError_t launch_repeat(const double *src, int64_t n, int64_t reps, double *dst, hipStream_t s);
 hipError_t launch_nodes(int64_t H, int Q, const double2 *A, const double2 *B, double *x,
                         hipStream_t s);
 hipError_t launch_bnodes(const NodeTile *tiles, int64_t ntiles, hipStream_t s);

@@ -105,3 +105,15 @@ def test_adaptive_rule_rejected(rule):
 def test_adaptive_null_rule(lib):
     h = C.c_void_p()
     assert lib.lc_plan_adaptive(16, 64, None, 0, C.byref(h)) == 1
+
+
+@pytest.mark.parametrize("args", [(0, 64, 8), (40, 64, 8), (8, 63, 8), (8, 64, 0)])
+def test_plan_2d_rejects_invalid(args):
+    import paper_1106_0463_amd as lc
+    with pytest.raises(lc.LCError) as ei:
+        lc.plan_2d(*args)
+    assert ei.value.status == 1
+
+
+def test_execute_2d_rejects_null(lib):
+    assert lib.lc_execute_2d(None, None, None, None) == 1

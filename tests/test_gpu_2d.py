@@ -1,0 +1,83 @@
+"""GPU checks of two-dimensional tensor-product plans (the 1-D method along
+x1 for every node of x2, then along x2): element-wise parity with the
+oracle's 2-D transform on small and ragged sizes, closed-form separable
+products at a larger size, and FP32 samples."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from closed_forms import exp_coeffs
+from helpers import banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lc():
+    import torch
+    import paper_1106_0463_amd as lc
+    torch.cuda.set_device(0)
+    return lc
+
+
+def _f2_np(x1, x2):
+    return np.exp(x1 * x2) + x1 * x1 * np.cos(3 * x2)
+
+
+def _f2_torch(x1, x2):
+    import torch
+    return torch.exp(x1 * x2) + x1 * x1 * torch.cos(3 * x2)
+
+
+def _run(lc, N, M, Q, f2, precision="fp64"):
+    import torch
+    p = lc.plan_2d(N, M, Q, precision=precision)
+    X = p.nodes.reshape(-1)
+    F = f2(X[None, :], X[:, None]).contiguous()     # F[b][a] = f(X_a, X_b)
+    if precision == "fp32":
+        F = F.float().contiguous()
+    C = p.execute(F)
+    torch.cuda.synchronize()
+    out = C.cpu().numpy()
+    info = p.info
+    p.destroy()
+    return out, info
+
+
+@pytest.mark.parametrize("N,M,Q", [(16, 64, 8), (33, 200, 7), (5, 12, 3)])
+def test_2d_matches_oracle(lc, N, M, Q):
+    from helpers import expected_grid
+    banner(f"[gpu] 2-D plan vs oracle N={N} M={M} Q={Q}")
+    got, info = _run(lc, N, M, Q, _f2_torch)
+    Me = expected_grid(M)
+    ref = np.asarray(oracle.method_coeffs_2d(_f2_np, N, Me, Q), dtype=float)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    banner(f"    rel err {err:.2e} (S = {info['H'] * info['Q']})")
+    assert info["kind"] == 5 and info["samples"] == (info["H"] * info["Q"]) ** 2
+    assert err <= 1e-13
+
+
+def test_2d_separable_closed_forms(lc):
+    import torch
+    banner("[gpu] 2-D separable product vs closed forms N=128 M=512 Q=24")
+    N, M, Q, t = 128, 512, 24, 0.4
+    f2 = lambda x1, x2: torch.exp(0.9 * x1) * W.GeneratingFunction(t).torch(x2)
+    got, _ = _run(lc, N, M, Q, f2)
+    c1 = np.array([float(v) for v in exp_coeffs(0.9, N)])
+    ref = np.outer(c1, t ** np.arange(N))
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    banner(f"    rel err {err:.2e}")
+    assert err <= 1e-13
+
+
+def test_2d_fp32_samples(lc):
+    banner("[gpu] 2-D FP32 samples vs FP64")
+    N, M, Q = 64, 256, 16
+    c64, _ = _run(lc, N, M, Q, _f2_torch)
+    c32, _ = _run(lc, N, M, Q, _f2_torch, precision="fp32")
+    n = np.arange(N)
+    scale = np.outer(2 * n + 1, 2 * n + 1)
+    E_a = np.max(np.abs((c32 - c64) / scale)) / np.max(np.abs(c64 / scale))
+    banner(f"    E_a {E_a:.2e}")
+    assert E_a <= 1e-7
