@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <functional>
 #include <map>
@@ -41,6 +42,8 @@ struct AdaptiveState {
     int64_t nnz = 0, nseg = 0;
     int qmax = 0;
     int gcap = 2;                // largest lane group used (G = 4 << gcap)
+    int prec = LC_FP64;
+    int gmul = 2;                // grid = resident blocks * gmul / 2
     std::vector<int64_t> rlen;   // chunks per row (host), for regrouping
     ASeg *segs = nullptr;
     int32_t *rseg = nullptr;
@@ -128,7 +131,9 @@ void group_rows(const std::vector<int64_t> &rlen, int gcap, std::vector<int32_t>
 }
 
 // uploads the row lists of grows into a's (preallocated, H entries in all)
-// group arrays and sets the launch grids
+// group arrays and sets the launch grids: the blocks one round of the
+// device holds (occupancy) times gmul / 2, so that a grid-stride launch ends
+// without a partial round of blocks
 hipError_t set_groups(AdaptiveState *a, const std::vector<int32_t> *grows) {
     int64_t off = 0;
     for (int gi = 0; gi < kNG; ++gi) {
@@ -141,8 +146,9 @@ hipError_t set_groups(AdaptiveState *a, const std::vector<int32_t> *grows) {
         }
         off += a->nrows[gi];
         const int64_t per_block = 4 * (64 / (4 << gi));
+        const int64_t resident = (int64_t)device_cu_count() * aquad_blocks_per_cu(a->prec, 4 << gi);
         a->grid[gi] = (int)std::max<int64_t>(1, std::min<int64_t>((a->nrows[gi] + per_block - 1) / per_block,
-                                                                  (int64_t)device_cu_count() * 8));
+                                                                  std::max<int64_t>(1, resident * a->gmul / 2)));
     }
     return hipSuccess;
 }
@@ -239,10 +245,15 @@ lc_status tune_adaptive(lc_plan_s *p, hipStream_t s) {
     std::vector<int32_t> grows[kNG];
     int best = a->gcap;
     if (cache_get(key, cached)) {
-        best = std::max(0, std::min(kNG - 1, atoi(cached.c_str())));
+        int gc = best, mul = a->gmul;
+        if (sscanf(cached.c_str(), "%d %d", &gc, &mul) >= 1) best = std::max(0, std::min(kNG - 1, gc));
+        a->gmul = std::max(1, std::min(4, mul));
     } else {
         double best_ms = 1e30;
-        for (int gc = 1; gc < kNG; ++gc) {
+        int best_mul = a->gmul;
+        for (int cand = 0; cand < 3 * (kNG - 1); ++cand) {
+            const int gc = 1 + cand / 3, mul = 1 << (cand % 3);  // grid: 1/2, 1, 2 rounds of resident blocks
+            a->gmul = mul;
             group_rows(a->rlen, gc, grows);
             hipError_t e = set_groups(a, grows);
             if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: row groups");
@@ -260,9 +271,11 @@ lc_status tune_adaptive(lc_plan_s *p, hipStream_t s) {
             if (ms < best_ms) {
                 best_ms = ms;
                 best = gc;
+                best_mul = mul;
             }
         }
-        cache_put(key, std::to_string(best));
+        a->gmul = best_mul;
+        cache_put(key, std::to_string(best) + " " + std::to_string(best_mul));
     }
     group_rows(a->rlen, best, grows);
     if (set_groups(a, grows) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: row groups");
@@ -438,6 +451,7 @@ extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *
         chk(aalloc(a, &p->zA, (size_t)L, &ws));
         chk(aalloc(a, &p->zB, (size_t)L, &ws));
     }
+    a->prec = (int)prec;
     chk(aalloc(a, &a->rows[0], (size_t)H, &ws));  // all groups' row lists, back to back
     if (e == hipSuccess) chk(set_groups(a, grows));
     a->gcap = gcap;

@@ -62,12 +62,28 @@ __global__ __launch_bounds__(256) void k_aquad(const T *__restrict__ f, const AS
         double acc = 0.0;
         for (int k = rseg[r]; k < rseg[r + 1]; ++k) {
             const ASeg sg = segs[k];
-            const double part = row_partial<T, VEC, G>(f + sg.off, wtab + sg.woff, sg.qp / VEC, g);
+            // rule tables start at multiples of 4 doubles: 16-byte weight pairs
+            const double part = row_partial<T, VEC, G, true>(f + sg.off, wtab + sg.woff, sg.qp / VEC, g);
             acc = fma(sg.scale, part, acc);
         }
         acc = group_sum<G>(acc);
         if (g == 0) phi[r] = s2[r] * acc;
     }
+}
+
+// Blocks of k_aquad<T, G> resident on one CU at once (occupancy API).
+int aquad_blocks_per_cu(int prec, int G) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define LC_AO(T, GV)                                                                                   \
+    if (G == GV) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_aquad<T, GV>, 256, 0);
+    if (prec == LC_FP64) {
+        LC_AO(double, 4) LC_AO(double, 8) LC_AO(double, 16) LC_AO(double, 32) LC_AO(double, 64)
+    } else {
+        LC_AO(float, 4) LC_AO(float, 8) LC_AO(float, 16) LC_AO(float, 32) LC_AO(float, 64)
+    }
+#undef LC_AO
+    return (e == hipSuccess && n > 0) ? n : 4;
 }
 
 hipError_t launch_aquad(int prec, int G, int grid, const void *f, const ASeg *segs, const int32_t *rseg,

@@ -149,6 +149,7 @@ struct ASeg {
 
 hipError_t launch_anodes(const ASeg *segs, int64_t nseg, const double2 *dtab, const double2 *rowA, double *x,
                          hipStream_t s);
+int aquad_blocks_per_cu(int prec, int G);
 hipError_t launch_aquad(int prec, int G, int grid, const void *f, const ASeg *segs, const int32_t *rseg,
                         const int32_t *rows, int64_t nrows, const double *wtab, const double *s2, double *phi,
                         hipStream_t s);

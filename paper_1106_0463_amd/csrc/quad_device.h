@@ -42,7 +42,25 @@ __device__ __forceinline__ double group_sum(double acc) {
 // Generic variant for any Q: G lanes per row stride over the Q/VEC chunks
 // with bounds checks, 4 chunks in flight per lane; weights from global
 // memory (L1/L2 resident: every row reuses them).
-template <typename T, int VEC, int G>
+// Weights of one chunk: VEC doubles at w + c VEC.  WV = true reads them as
+// 16-byte pairs (w must then be 16-byte aligned).
+template <int VEC, bool WV>
+__device__ __forceinline__ void chunk_weights(const double *__restrict__ w, int c, double *o) {
+    if constexpr (WV && VEC % 2 == 0) {
+        const dv2 *q = reinterpret_cast<const dv2 *>(w + c * VEC);
+#pragma unroll
+        for (int e = 0; e < VEC / 2; ++e) {
+            const dv2 v = q[e];
+            o[2 * e] = v.x;
+            o[2 * e + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = w[c * VEC + e];
+    }
+}
+
+template <typename T, int VEC, int G, bool WV = false>
 __device__ __forceinline__ double row_partial(const T *__restrict__ frow, const double *__restrict__ w,
                                               int NC, int g) {
     using V = typename VecOf<T, VEC>::type;
@@ -54,12 +72,17 @@ __device__ __forceinline__ double row_partial(const T *__restrict__ frow, const 
           dd = ld_stream(p + c + 3 * G);
         double da[VEC], db[VEC], dc[VEC], dd_[VEC];
         to_d(a, da); to_d(b, db); to_d(cc, dc); to_d(dd, dd_);
+        double wa[VEC], wb[VEC], wc[VEC], wd[VEC];
+        chunk_weights<VEC, WV>(w, c, wa);
+        chunk_weights<VEC, WV>(w, c + G, wb);
+        chunk_weights<VEC, WV>(w, c + 2 * G, wc);
+        chunk_weights<VEC, WV>(w, c + 3 * G, wd);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            acc0 = fma(w[c * VEC + e], da[e], acc0);
-            acc1 = fma(w[(c + G) * VEC + e], db[e], acc1);
-            acc0 = fma(w[(c + 2 * G) * VEC + e], dc[e], acc0);
-            acc1 = fma(w[(c + 3 * G) * VEC + e], dd_[e], acc1);
+            acc0 = fma(wa[e], da[e], acc0);
+            acc1 = fma(wb[e], db[e], acc1);
+            acc0 = fma(wc[e], dc[e], acc0);
+            acc1 = fma(wd[e], dd_[e], acc1);
         }
     }
     // the lane's last (at most 3) chunks: all loads in flight before the
@@ -72,11 +95,15 @@ __device__ __forceinline__ double row_partial(const T *__restrict__ frow, const 
         const V cc = h2 ? ld_stream(p + c + 2 * G) : zero;
         double da[VEC], db[VEC], dc[VEC];
         to_d(a, da); to_d(b, db); to_d(cc, dc);
+        double wa[VEC], wb[VEC], wc[VEC];
+        chunk_weights<VEC, WV>(w, c, wa);
+        if (h1) chunk_weights<VEC, WV>(w, c + G, wb);
+        if (h2) chunk_weights<VEC, WV>(w, c + 2 * G, wc);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            acc0 = fma(w[c * VEC + e], da[e], acc0);
-            if (h1) acc1 = fma(w[(c + G) * VEC + e], db[e], acc1);
-            if (h2) acc0 = fma(w[(c + 2 * G) * VEC + e], dc[e], acc0);
+            acc0 = fma(wa[e], da[e], acc0);
+            if (h1) acc1 = fma(wb[e], db[e], acc1);
+            if (h2) acc0 = fma(wc[e], dc[e], acc0);
         }
     }
     return acc0 + acc1;
