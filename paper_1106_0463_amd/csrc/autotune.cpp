@@ -73,17 +73,22 @@ bool quad_from_str(const std::string &s, QuadCfg &c) {
     return true;
 }
 
-// Every supported quadrature launch shape for (precision, Q), with grids of
-// 4, 8 and 16 blocks per CU (capped by the useful number of blocks).
-std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu) {
+// Every supported quadrature launch shape for (precision, Q), each with
+// grids of one half, one and two rounds of the blocks the device holds at
+// once for that variant (occupancy API; a grid-stride launch whose grid is
+// not a whole number of rounds ends on a partial round), capped by the
+// useful number of blocks.
+std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu, bool batch) {
     std::vector<QuadCfg> out;
     auto add = [&](QuadCfg c) {
         if (!quad_cfg_supported(c, prec, Q)) return;
         const int64_t rpb = quad_rows_per_block(c);
         const int64_t useful = (rows + rpb - 1) / rpb;
-        for (int m : {4, 8, 16}) {
+        int occ = batch ? bquad_blocks_per_cu(c, prec) : quad_blocks_per_cu(c, prec);
+        if (occ < 1) occ = 8;
+        for (int half_rounds : {1, 2, 4}) {
             QuadCfg g = c;
-            g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(useful, (int64_t)cu * m));
+            g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(useful, (int64_t)cu * occ * half_rounds / 2));
             bool dup = false;
             for (auto &o : out) dup |= quad_to_str(o) == quad_to_str(g);
             if (!dup) out.push_back(g);

@@ -257,7 +257,12 @@ QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu) {
     }
     const int64_t rows_per_block = (int64_t)(c.block / 64) * (64 / c.G) * c.unroll;
     int64_t grid = (rows + rows_per_block - 1) / rows_per_block;
-    grid = std::min<int64_t>(grid, (int64_t)num_cu * 8);
+    // one round of resident blocks (occupancy of this variant)
+    c.Qv = Q;
+    c.grid = 1;
+    int occ = quad_blocks_per_cu(c, prec);
+    if (occ < 1) occ = 8;
+    grid = std::min<int64_t>(grid, (int64_t)num_cu * occ);
     c.grid = (int)std::max<int64_t>(1, grid);
     return c;
 }
@@ -269,9 +274,15 @@ DstCfg default_dst_cfg(int64_t L) {
         d.sched = make_sched((int)L);
         return d;
     }
-    // four-step split: L1 the largest divisor <= sqrt(L), both <= 2048
+    return four_step_cfg(L);
+}
+
+// Four-step split of an FFT of length L: L1 the largest divisor <= sqrt(L)
+// with both factors <= 2048 (L1 = 0 if there is none).
+DstCfg four_step_cfg(int64_t L) {
+    DstCfg d{};
     int64_t best = 0;
-    for (int64_t a = 1; a * a <= L; ++a)
+    for (int64_t a = 2; a * a <= L; ++a)
         if (L % a == 0 && a <= 2048 && L / a <= 2048) best = a;
     d.threads = 256;
     if (best == 0) return d;  // unsupported (checked by the planner)
@@ -660,7 +671,7 @@ lc_status tune_single(lc_plan_s *p, hipStream_t s) {
     const void *fsrc = p->x;  // same shape as the samples (FP64) or larger (FP32)
     double best = 1e30;
     QuadCfg bq = p->quad;
-    for (const QuadCfg &c : quad_candidates(d.prec, d.Q, d.H, device_cu_count())) {
+    for (const QuadCfg &c : quad_candidates(d.prec, d.Q, d.H, device_cu_count(), false)) {
         hipError_t er;
         const double t = time_launch([&](hipStream_t st) { return launch_quad(c, d.prec, fsrc, p->w, p->s2, d.H, d.Q, p->phi, st); }, s, 3, &er);
         if (er == hipSuccess && t < best) { best = t; bq = c; }

@@ -271,7 +271,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         for (auto &qc : st->classes) {
             double best = 1e30;
             QuadCfg bc = qc.cfg;
-            for (QuadCfg c : quad_candidates(qc.prec, qc.Q, qc.rows, cu)) {
+            for (QuadCfg c : quad_candidates(qc.prec, qc.Q, qc.rows, cu, true)) {
                 c.Qv = qc.Q;
                 std::vector<BatchTile> tl = make_tiles(st->fn, qc.fns, quad_rows_per_block(c));
                 BatchTile *dt = nullptr;
@@ -383,7 +383,7 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         coff += d.N;
         d.phi_off = poff;
         poff += d.H;
-        if (d.L > kLdsFftMax && default_dst_cfg(d.L).L1 == 0) {
+        if (d.L > kLdsFftMax && four_step_cfg(d.L).L1 == 0) {
             free_state(st);
             return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_batch: an FFT length has no four-step split");
         }
@@ -425,7 +425,7 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
             chk(upload(st, &h.tw_fft, fft));
             chk(upload(st, &h.rowA, rowA));
             chk(upload(st, &h.s2, s2));
-            h.dcfg = default_dst_cfg(d.L);
+            h.dcfg = four_step_cfg(d.L);
             st->hs[d.H] = h;
         }
         if (!st->qs.count(d.Q)) {
@@ -441,9 +441,16 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
     }
     chk(balloc(st, &st->x_arena, (size_t)st->x_elems));
     chk(balloc(st, &st->phi_arena, (size_t)st->phi_elems));
+    // functions whose FFT runs as the batched four-step (several workgroups
+    // per function) rather than in one workgroup's LDS: L > big_L
+    // (LC_BATCH_BIG_L overrides; a length without a split stays in LDS;
+    // moving lengths 1024..8192 to the four-step measured slower)
+    int64_t big_L = kLdsFftMax;
+    if (const char *ev = getenv("LC_BATCH_BIG_L")) big_L = std::max<int64_t>(64, atoll(ev));
+    auto is_big = [&](int64_t L) { return L > kLdsFftMax || (L > big_L && four_step_cfg(L).L1 != 0); };
     int64_t Lsum = 0;
     for (int b = 0; b < B; ++b)
-        if (st->fn[b].L > kLdsFftMax) Lsum += st->fn[b].L;
+        if (is_big(st->fn[b].L)) Lsum += st->fn[b].L;
     if (Lsum) {
         chk(balloc(st, &st->zA, (size_t)Lsum));
         chk(balloc(st, &st->zB, (size_t)Lsum));
@@ -501,7 +508,11 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         std::vector<BatchTile> tiles = make_tiles(st->fn, qc.fns, quad_rows_per_block(qc.cfg));
         qc.ntiles = (int)tiles.size();
         part_starts(tiles, st->part_of, st->nparts, qc.tstart);
-        qc.cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>(qc.ntiles, (int64_t)cu * 8));
+        {   // one round of resident blocks of this variant
+            int occ = bquad_blocks_per_cu(qc.cfg, qc.prec);
+            if (occ < 1) occ = 8;
+            qc.cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>(qc.ntiles, (int64_t)cu * occ));
+        }
         chk(upload(st, &qc.tiles, tiles));
         st->classes.push_back(qc);
     }
@@ -509,7 +520,7 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
     std::map<int, std::vector<int>> grp;
     for (int b = 0; b < B; ++b) {
         const int64_t L = st->fn[b].L;
-        if (L > kLdsFftMax) {
+        if (is_big(L)) {
             st->large.push_back(b);
             continue;
         }

@@ -95,9 +95,16 @@ __global__ __launch_bounds__(256) void k_bquad_gen(const unsigned char *__restri
     }
 }
 
+// When set, the dispatch below reports the resident blocks per CU of the
+// selected variant (occupancy API) into *g_bocc instead of launching it.
+static thread_local int *g_bocc = nullptr;
+
 template <typename T, int VEC, int G, int CPL, int U>
 static hipError_t bfit(const QuadCfg &c, const void *f, const double *w, const BatchTile *tiles, int ntiles,
                        const BatchFn *fns, double *phi, hipStream_t s) {
+    if (g_bocc)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_bocc, (const void *)k_bquad_fit<T, VEC, G, CPL, U>,
+                                                            c.block, 0);
     hipLaunchKernelGGL((k_bquad_fit<T, VEC, G, CPL, U>), dim3(c.grid), dim3(c.block), 0, s,
                        (const unsigned char *)f, w, tiles, ntiles, fns, phi);
     return hipGetLastError();
@@ -106,6 +113,8 @@ static hipError_t bfit(const QuadCfg &c, const void *f, const double *w, const B
 template <typename T, int VEC, int G>
 static hipError_t bgen(const QuadCfg &c, const void *f, const double *w, int Q, const BatchTile *tiles,
                        int ntiles, const BatchFn *fns, double *phi, hipStream_t s) {
+    if (g_bocc)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_bocc, (const void *)k_bquad_gen<T, VEC, G>, c.block, 0);
     hipLaunchKernelGGL((k_bquad_gen<T, VEC, G>), dim3(c.grid), dim3(c.block), 0, s,
                        (const unsigned char *)f, w, Q, tiles, ntiles, fns, phi);
     return hipGetLastError();
@@ -159,6 +168,15 @@ static hipError_t bdispatch(const QuadCfg &c, const void *f, const double *w, in
     return hipErrorInvalidValue;
 }
 #undef LC_BFIT_CASES
+
+int bquad_blocks_per_cu(const QuadCfg &cfg, int prec) {
+    int n = 0;
+    g_bocc = &n;
+    const hipError_t e = prec == LC_FP64 ? bdispatch<double>(cfg, nullptr, nullptr, cfg.Qv, nullptr, 1, nullptr, nullptr, 0)
+                                         : bdispatch<float>(cfg, nullptr, nullptr, cfg.Qv, nullptr, 1, nullptr, nullptr, 0);
+    g_bocc = nullptr;
+    return (e == hipSuccess && n > 0) ? n : 0;
+}
 
 hipError_t launch_bquad(const QuadCfg &cfg, int prec, const void *f_arena, const double *w, const BatchTile *tiles,
                         int ntiles, const BatchFn *fns, double *phi_arena, hipStream_t s) {

@@ -145,9 +145,16 @@ __global__ __launch_bounds__(256) void k_quad_gen(const T *__restrict__ f, const
     }
 }
 
+// When set, the dispatch below reports the resident blocks per CU of the
+// selected variant (occupancy API) into *g_occ instead of launching it.
+static thread_local int *g_occ = nullptr;
+
 template <typename T, int VEC, int G, int CPL, int U>
 static hipError_t go_fit(const QuadCfg &c, const void *f, const double *w, const double *s2, int64_t rows,
                          double *phi, hipStream_t s) {
+    if (g_occ)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_occ, (const void *)k_quad_fit<T, VEC, G, CPL, U>,
+                                                            c.block, 0);
     hipLaunchKernelGGL((k_quad_fit<T, VEC, G, CPL, U>), dim3(c.grid), dim3(c.block), 0, s,
                        (const T *)f, w, s2, rows, phi);
     return hipGetLastError();
@@ -156,6 +163,8 @@ static hipError_t go_fit(const QuadCfg &c, const void *f, const double *w, const
 template <typename T, int VEC, int G>
 static hipError_t go_gen(const QuadCfg &c, const void *f, const double *w, const double *s2, int64_t rows,
                          int Q, double *phi, hipStream_t s) {
+    if (g_occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_occ, (const void *)k_quad_gen<T, VEC, G>,
+                                                                    c.block, 0);
     hipLaunchKernelGGL((k_quad_gen<T, VEC, G>), dim3(c.grid), dim3(c.block), 0, s, (const T *)f, w, s2,
                        rows, Q, phi);
     return hipGetLastError();
@@ -210,6 +219,17 @@ static hipError_t dispatch_quad(const QuadCfg &c, const void *f, const double *w
     return hipErrorInvalidValue;
 }
 #undef LC_FIT_CASES
+
+int quad_blocks_per_cu(const QuadCfg &cfg, int prec) {
+    int n = 0;
+    g_occ = &n;
+    QuadCfg c = cfg;
+    c.grid = 1;
+    const hipError_t e = prec == LC_FP64 ? dispatch_quad<double>(c, nullptr, nullptr, nullptr, 0, c.Qv, nullptr, 0)
+                                         : dispatch_quad<float>(c, nullptr, nullptr, nullptr, 0, c.Qv, nullptr, 0);
+    g_occ = nullptr;
+    return (e == hipSuccess && n > 0) ? n : 0;
+}
 
 int quad_rows_per_block(const QuadCfg &c) { return (c.block / 64) * (64 / c.G) * (c.cpl > 0 ? c.unroll : 1); }
 

@@ -198,7 +198,12 @@ double2 dd_split(long double v);
 void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack,
               std::vector<double2> &fft);
 QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu);
+// resident blocks per CU of the quadrature variant cfg selects (single
+// plans / batch plans; cfg.Qv must hold Q); 0 if unknown
+int quad_blocks_per_cu(const QuadCfg &cfg, int prec);
+int bquad_blocks_per_cu(const QuadCfg &cfg, int prec);
 DstCfg default_dst_cfg(int64_t L);
+DstCfg four_step_cfg(int64_t L);
 int device_cu_count();
 
 // --- autotuner helpers (autotune.cpp) --------------------------------------
@@ -207,7 +212,7 @@ bool cache_get(const std::string &key, std::string &val);
 void cache_put(const std::string &key, const std::string &val);
 std::string quad_to_str(const QuadCfg &c);
 bool quad_from_str(const std::string &s, QuadCfg &c);
-std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu);
+std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu, bool batch);
 std::vector<FftSched> sched_candidates(int L);
 double time_launch(const std::function<hipError_t(hipStream_t)> &f, hipStream_t s, int reps, hipError_t *err);
 
