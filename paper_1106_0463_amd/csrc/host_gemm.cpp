@@ -156,7 +156,10 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
     GemmState *g = new (std::nothrow) GemmState();
     if (!g) return fail_status(LC_ERR_NOMEM, who + "host allocation failed");
     g->direct = direct;
-    if (const char *kc = getenv("LC_MGEMM_KCH")) mgemm_kch = atoi(kc) == 2 ? 2 : 4;
+    if (const char *kc = getenv("LC_MGEMM_KCH")) {
+        const int k = atoi(kc);
+        mgemm_kch = (k == 2 || k == 4 || k == 8) ? k : 0;
+    }
     if (const char *st = getenv("LC_MGEMM_STAGES")) {
         int ks = 0, ns = 0;
         if (sscanf(st, "%d,%d", &ks, &ns) == 2) {

@@ -548,7 +548,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // stage depth (k per stage, ring length) of each mode: LDS per block is
 // NS * (NX + NY) * 4 * KS/16 KiB, at most 80 KiB so that two blocks share a CU
 int mgemm_ks = 0, mgemm_ns = 0;  // 0: the per-mode default; LC_MGEMM_STAGES="KS,NS" overrides
-int mgemm_kch = 0;  // FP64-total chunk of the direct form (2 or 4; 0: default 4); LC_MGEMM_KCH overrides
+int mgemm_kch = 0;  // FP64-total chunk of the direct form (2, 4 or 8; 0: per mode); LC_MGEMM_KCH overrides
 
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
                         int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
@@ -561,7 +561,11 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
         NS = mode == 6 ? 3 : 4;
     }
     const bool d64 = C64 != nullptr;
-    const int kch = d64 ? (mgemm_kch ? mgemm_kch : 4) : 8;
+    // FP64 chunk length of the direct form: 4 K-steps for fp16x3 and bf16x6
+    // (at 8 their E_a reaches 1.0e-7 and 1.25e-7), 8 for bf16x3 and fp16x1,
+    // whose 16-bit representation limits them above that anyway
+    const bool long_chunks = mode == 1 || (mode == 3 && h16 == kBF16);
+    const int kch = d64 ? (mgemm_kch ? mgemm_kch : (long_chunks ? 8 : 4)) : 8;
     const int grid = ((Bn + kGemmBM - 1) / kGemmBM) * ((Hn + 127) / 128);
     const int npx = mode == 1 ? 1 : (mode == 3 ? 2 : 3);
     const size_t lds = (size_t)NS * 2 * npx * 4 * (KS / 16) * 1024;
@@ -576,8 +580,9 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
                            xps, (const T *)Y, yps, Bn, Hn, K16, Out, ldo, C64, rowexp, colexp);                \
         return hipGetLastError();                                                                               \
     }
-#define LC_MG(T, MV, KSV, NSV) \
-    LC_MG1(T, MV, KSV, NSV, false, 8) LC_MG1(T, MV, KSV, NSV, true, 2) LC_MG1(T, MV, KSV, NSV, true, 4)
+#define LC_MG(T, MV, KSV, NSV)                                                                                  \
+    LC_MG1(T, MV, KSV, NSV, false, 8) LC_MG1(T, MV, KSV, NSV, true, 2) LC_MG1(T, MV, KSV, NSV, true, 4)         \
+    LC_MG1(T, MV, KSV, NSV, true, 8)
 #define LC_MG_ALL(T)                                                                                            \
     LC_MG(T, 1, 32, 2) LC_MG(T, 1, 32, 4) LC_MG(T, 1, 16, 4)                                                    \
     LC_MG(T, 3, 32, 2) LC_MG(T, 3, 16, 2) LC_MG(T, 3, 16, 3) LC_MG(T, 3, 16, 4)                                 \

@@ -16,7 +16,8 @@ constexpr int kGemmBM = 128;
 
 // k per LDS stage and ring length of the MFMA product (0: per-mode default)
 extern int mgemm_ks, mgemm_ns;
-// K-steps of 16 per FP64 flush of the direct form's accumulators (2 or 4)
+// K-steps of 16 per FP64 flush of the direct form's accumulators (2, 4 or 8;
+// 0 = per mode)
 extern int mgemm_kch;
 
 hipError_t launch_amat(int H, int P, int QA, const double *xc, const double *lam, const double2 *rowA,

@@ -180,7 +180,8 @@ def test_legendre_matrix_fp64_exact(lc):
 
 # The direct form rounds each coefficient's own FP32 partial sums (no
 # transform averages them), so its accumulators are flushed into FP64 totals
-# every 4 K-steps of 16; its error is then relative to max|c| as well:
+# every 4 K-steps of 16 for fp16x3 and bf16x6 (every 8 for bf16x3 and fp16x1,
+# which their 16-bit representation limits anyway); its error is then relative to max|c| as well:
 # E_c bounds hold for the three- and six-product modes (the Abel form's E_c
 # is ~1e-4 at these sizes).
 @pytest.mark.parametrize("mode,bound_a,bound_c", [("bf16x6", 1e-7, 1e-6), ("fp16x3", 1e-7, 1e-6),
