@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel from the two rocprofv3 counter passes
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from the 4 GiB copy calibration),
 # with the kernel they were taken on
-TRAFFIC = {"single_large_band": (5.1068e9, "k_aquad<double, 16>"),
-           "batch_fp64": (7.8123e9, "k_bquad_fit<double, 2, 8, 3, 2>")}
+TRAFFIC = {"single_large_band": (5.1225e9, "k_aquad<double, 16>"),
+           "batch_fp64": (7.8647e9, "k_bquad_fit<double, 2, 8, 3, 1>")}
 METRIC = "Legendre coeffs/sec at 1 GPU (FP64 ≤1e-12 vs split-BF16 ≤1e-7 rel.)"
 Q_RESOLVING = 8384
 
