@@ -68,29 +68,27 @@ def time_steps(step, steps: int, warmup: int):
 
 
 def cpu_baseline_single_large(budget_s: float = 20.0):
-    """Time the definition oracle on a bounded sample of the large single
-    function: the first N_s coefficients with a K-point rule that resolves
-    f P_n (K = (N_s + 16600)/2 + 256)."""
-    import numpy as np
-
+    """Time the definition oracle on the large single function: the first
+    N_s coefficients with a K-point rule that resolves f P_n
+    (K = (N_s + 16600)/2 + 256), N_s doubling from 16384 up to the whole
+    N = 65536 while the time stays within the budget."""
     import oracle
     import workloads as W
     wl = W.single_large()
-    N_s = 16384
-    K = (N_s + 16600) // 2 + 256
-    t0 = time.perf_counter()
-    oracle.legendre_coeffs(wl.f, N_s, K)
-    dt = time.perf_counter() - t0
-    # grow the sample toward the budget (cost ~ N K)
-    if dt < budget_s / 8:
-        N_s = 32768
+    N_s, dt, K = 16384, 0.0, 0
+    while True:
         K = (N_s + 16600) // 2 + 256
         t0 = time.perf_counter()
         oracle.legendre_coeffs(wl.f, N_s, K)
         dt = time.perf_counter() - t0
+        # cost ~ N K: the next size takes about 3x as long
+        if N_s >= wl.N or dt * 3.5 > budget_s:
+            break
+        N_s *= 2
+    what = "all" if N_s >= wl.N else "the first"
     return {"value": N_s / dt, "unit": "coefficients/s", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"first {N_s} coefficients of the same f, eq. (2.3) by a {K}-point "
+            "sample": f"{what} {N_s} coefficients of the same f, eq. (2.3) by a {K}-point "
                       f"long-double Gauss-Legendre rule (rule construction included), {dt:.2f} s"}
 
 
