@@ -1,0 +1,120 @@
+"""Edge cases and determinism across plan kinds: repeated executes are
+bitwise identical; degenerate sizes (N = 1, the smallest grids, one Abel
+node, one function, P = 2) against the oracle or the method's exactness;
+an adaptive rule with many breakpoints against the oracle's rule."""
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+
+import oracle
+import workloads as W
+from helpers import banner, expected_grid, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lc():
+    import torch
+    import paper_1106_0463_amd as lc
+    torch.cuda.set_device(0)
+    return lc
+
+
+def _twice(fn):
+    import torch
+    a = fn().clone()
+    b = fn().clone()
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), b.cpu().numpy()
+
+
+def test_determinism_every_plan_kind(lc):
+    import torch
+    from workloads.gpu import series_grid
+    banner("[gpu] repeated executes are bitwise identical")
+    f = W.Sum(W.Exponential(0.7), W.GeneratingFunction(0.6))
+    p = lc.plan(300, 1200, 24)
+    fx = f.torch(p.nodes).contiguous()
+    a, b = _twice(lambda: p.execute(fx))
+    assert np.array_equal(a, b)
+    pa = lc.plan_adaptive(300, 1200, q=16, breaks=(0.3,), grade_ratio=0.2, grade_levels=3)
+    fa = f.torch(pa.nodes).contiguous()
+    a, b = _twice(lambda: pa.execute(fa))
+    assert np.array_equal(a, b)
+    p2 = lc.plan_2d(16, 64, 8)
+    X = p2.nodes.reshape(-1)
+    F2 = torch.exp(X[None, :] * X[:, None]).contiguous()
+    a, b = _twice(lambda: p2.execute(F2))
+    assert np.array_equal(a, b)
+    coef = W.gemm_batch_coeffs(40, 200, seed=11)
+    for mk in (lambda: lc.plan_gemm(256, 512, 200, "fp16x3"), lambda: lc.plan_legendre_matrix(256, 512, 200, "bf16x6")):
+        g = mk()
+        F = series_grid(coef, g.nodes)
+        a, b = _twice(lambda: g.execute(F))
+        assert np.array_equal(a, b)
+        g.destroy()
+    for q in (p, pa, p2):
+        q.destroy()
+
+
+@pytest.mark.parametrize("N,M,q", [(1, 4, 1), (1, 2, 3), (2, 8, 2)])
+def test_smallest_single_and_adaptive(lc, N, M, q):
+    banner(f"[gpu] smallest plans N={N} M={M} q={q}")
+    f = W.Exponential(0.5)
+    Me = expected_grid(M)
+    ref = np.array(oracle.method_coeffs(f, N, Me, q, fp64_nodes=True), dtype=float)
+    p = lc.plan(N, M, q)
+    c = p.execute(f.torch(p.nodes).contiguous()).cpu().numpy()
+    p.destroy()
+    pa = lc.plan_adaptive(N, M, q=q)
+    ca = pa.execute(f.torch(pa.nodes).contiguous()).cpu().numpy()
+    pa.destroy()
+    assert rel_err(c, ref) <= 1e-14
+    assert rel_err(ca, ref) <= 1e-14
+
+
+def test_many_breakpoints_against_oracle(lc):
+    banner("[gpu] adaptive rule with 64 breakpoints vs the oracle's rule")
+    brk = tuple(np.linspace(-0.95, 0.95, 64))
+    rule = dict(q=8, breaks=brk)
+    f = W.AbsPower(1.5)
+    N, M = 48, 256
+    p = lc.plan_adaptive(N, M, **rule)
+    c = p.execute(f.torch(p.nodes).contiguous()).cpu().numpy()
+    p.destroy()
+    ref = np.array(oracle.method_coeffs_rule(f, N, expected_grid(M), dict(rule), fp64_nodes=True), dtype=float)
+    assert rel_err(c, ref) <= 1e-13
+
+
+def test_2d_single_coefficient(lc):
+    import torch
+    banner("[gpu] 2-D plan with N = 1")
+    p = lc.plan_2d(1, 8, 4)
+    X = p.nodes.reshape(-1)
+    F = (2.0 + X[None, :] * X[:, None]).contiguous()
+    c = p.execute(F).cpu().numpy()
+    p.destroy()
+    # c_00 = (1/4) integral integral (2 + x1 x2) = 2
+    assert abs(c[0, 0] - 2.0) <= 1e-14
+
+
+@pytest.mark.parametrize("kind", ["gemm", "matrix"])
+def test_fixed_grid_tiny(lc, kind):
+    from workloads.gpu import series_grid
+    banner(f"[gpu] {kind}: P = 2, one function; P = 33 ragged")
+    mk = lc.plan_gemm if kind == "gemm" else lc.plan_legendre_matrix
+    # P = 2 nodes, degree 1, M = 4: exact
+    coef = np.array([[0.5, -1.25]])
+    g = mk(2, 4, 2, "fp64")
+    C = g.execute(series_grid(coef, g.nodes)).cpu().numpy()
+    g.destroy()
+    assert np.max(np.abs(C - coef)) <= 1e-14
+    coef = W.gemm_batch_coeffs(3, 20, seed=12)
+    g = mk(33, 128, 40, "fp16x3")
+    C = g.execute(series_grid(coef, g.nodes)).cpu().numpy()
+    g.destroy()
+    ref = np.zeros((3, 40))
+    ref[:, :21] = coef
+    n = np.arange(40)
+    assert rel_err(C / (2 * n + 1), ref / (2 * n + 1)) <= 1e-7
