@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel from the two rocprofv3 counter passes
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from the 4 GiB copy calibration),
 # with the kernel they were taken on
-TRAFFIC = {"single_large_band": (5.1225e9, "k_aquad<double, 16>"),
+TRAFFIC = {"single_large_band": (4.9569e9, "k_aflat<double>"),
            "batch_fp64": (7.8647e9, "k_bquad_fit<double, 2, 8, 3, 1>")}
 METRIC = "Legendre coeffs/sec at 1 GPU (FP64 ≤1e-12 vs split-BF16 ≤1e-7 rel.)"
 Q_RESOLVING = 8384
@@ -167,7 +167,7 @@ def run_single_large(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": TRAFFIC[TKEY][0] if (band or wl.Q == Q_RESOLVING) and TKEY in TRAFFIC else None,
-                     "kernel": "k_aquad (segmented Abel quadrature)" if band
+                     "kernel": "k_aflat (flattened composite-rule Abel quadrature)" if band
                                else "k_quad_* (Abel quadrature reduction)",
                      "kernel_ms": kms, "alg_bytes_per_launch": r["alg_bytes"]},
     }

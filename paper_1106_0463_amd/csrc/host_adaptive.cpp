@@ -9,7 +9,9 @@
 // 1 - t_i = E + h d_i.  Distinct (q, kind) Gauss rules are built once
 // (long double Newton) into a padded weight table and a double-double node
 // table.  Rows are grouped by the lanes per row G that their length fills,
-// one reduction launch per group, longest rows first.
+// one reduction launch per group, longest rows first.  Rows of at most
+// kAflatMaxSeg panels take the flattened reduction (one run of chunks per
+// row), rows with more panels the panel-by-panel one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,17 +43,25 @@ constexpr int kNG = 5;  // lane groups G = 4, 8, 16, 32, 64
 struct AdaptiveState {
     int64_t nnz = 0, nseg = 0;
     int qmax = 0;
-    int gcap = 2;                // largest lane group used (G = 4 << gcap)
+    int gcap = 3;                // largest lane group used (G = 4 << gcap)
     int prec = LC_FP64;
-    int gmul = 2;                // grid = resident blocks * gmul / 2
+    int gmul = 0;                // grid = resident blocks * gmul / 2 (0: one row per group)
     std::vector<int64_t> rlen;   // chunks per row (host), for regrouping
+    std::vector<ARow> rdesc;     // flattened-row descriptors by row (host)
     ASeg *segs = nullptr;
+    ATab *tab = nullptr;
     int32_t *rseg = nullptr;
     double *wtab = nullptr;
     double2 *dtab = nullptr;
+    // rows of more than kAflatMaxSeg panels: panel-by-panel reduction
     int32_t *rows[kNG] = {};
     int64_t nrows[kNG] = {};
     int grid[kNG] = {};
+    // the other rows: flattened reduction
+    ARow *frows[kNG] = {};
+    int64_t nfrows[kNG] = {};
+    int fgrid[kNG] = {};
+    AflatLaunch fl = {};
     std::vector<void *> allocs;
 };
 
@@ -131,26 +141,76 @@ void group_rows(const std::vector<int64_t> &rlen, int gcap, std::vector<int32_t>
 }
 
 // uploads the row lists of grows into a's (preallocated, H entries in all)
-// group arrays and sets the launch grids: the blocks one round of the
-// device holds (occupancy) times gmul / 2, so that a grid-stride launch ends
-// without a partial round of blocks
+// group arrays, rows of up to kAflatMaxSeg panels as flattened-row
+// descriptors and the others as row indices, and sets the launch grids: the
+// blocks one round of the device holds (occupancy) times gmul / 2, so that a
+// grid-stride launch ends without a partial round of blocks, or (gmul = 0)
+// one row per group, the blocks then taken longest rows first as CUs free
+// up.  A grid-stride launch gives group g the rows at positions g + k ngrp;
+// the longest-first list is laid out in serpentine order (every other round
+// reversed), so that no group collects the longest row of every round.
+template <typename T>
+void serpentine(std::vector<T> &v, int64_t ngrp) {
+    const int64_t n = (int64_t)v.size();
+    for (int64_t k0 = ngrp; k0 < n; k0 += 2 * ngrp) std::reverse(v.begin() + k0, v.begin() + std::min(n, k0 + ngrp));
+}
+
 hipError_t set_groups(AdaptiveState *a, const std::vector<int32_t> *grows) {
-    int64_t off = 0;
+    int64_t off = 0, foff = 0;
+    auto grid_of = [&](int64_t n, int gi, int per_cu) {
+        const int64_t per_block = 256 / (4 << gi);
+        const int64_t need = std::max<int64_t>(1, (n + per_block - 1) / per_block);
+        if (a->gmul == 0) return (int)std::min<int64_t>(need, INT32_MAX);
+        const int64_t resident = (int64_t)device_cu_count() * per_cu;
+        return (int)std::min<int64_t>(need, std::max<int64_t>(1, resident * a->gmul / 2));
+    };
     for (int gi = 0; gi < kNG; ++gi) {
+        std::vector<int32_t> slow;
+        std::vector<ARow> fast;
+        for (int32_t r : grows[gi]) {
+            if (a->rdesc[r].S <= kAflatMaxSeg) fast.push_back(a->rdesc[r]);
+            else slow.push_back(r);
+        }
         a->rows[gi] = a->rows[0] + off;
-        a->nrows[gi] = (int64_t)grows[gi].size();
-        if (!grows[gi].empty()) {
-            hipError_t e = hipMemcpy(a->rows[gi], grows[gi].data(), grows[gi].size() * sizeof(int32_t),
-                                     hipMemcpyHostToDevice);
+        a->nrows[gi] = (int64_t)slow.size();
+        a->frows[gi] = a->frows[0] + foff;
+        a->nfrows[gi] = (int64_t)fast.size();
+        a->grid[gi] = grid_of(a->nrows[gi], gi, aquad_blocks_per_cu(a->prec, 4 << gi));
+        a->fgrid[gi] = a->nfrows[gi] ? grid_of(a->nfrows[gi], gi, aflat_blocks_per_cu(a->prec)) : 0;
+        serpentine(slow, (int64_t)a->grid[gi] * (256 / (4 << gi)));
+        serpentine(fast, (int64_t)a->fgrid[gi] * (256 / (4 << gi)));
+        if (!slow.empty()) {
+            hipError_t e = hipMemcpy(a->rows[gi], slow.data(), slow.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return e;
+        }
+        if (!fast.empty()) {
+            hipError_t e = hipMemcpy(a->frows[gi], fast.data(), fast.size() * sizeof(ARow), hipMemcpyHostToDevice);
             if (e != hipSuccess) return e;
         }
         off += a->nrows[gi];
-        const int64_t per_block = 4 * (64 / (4 << gi));
-        const int64_t resident = (int64_t)device_cu_count() * aquad_blocks_per_cu(a->prec, 4 << gi);
-        a->grid[gi] = (int)std::max<int64_t>(1, std::min<int64_t>((a->nrows[gi] + per_block - 1) / per_block,
-                                                                  std::max<int64_t>(1, resident * a->gmul / 2)));
+        foff += a->nfrows[gi];
     }
+    // one flattened launch, the longest rows' blocks first
+    int b = 0;
+    for (int j = 0; j < kAflatLanes; ++j) {
+        const int gi = kNG - 1 - j;  // G = 64 >> j
+        a->fl.rows[j] = a->frows[gi];
+        a->fl.nrows[j] = a->nfrows[gi];
+        a->fl.b0[j] = b;
+        b += a->fgrid[gi];
+    }
+    a->fl.b0[kAflatLanes] = b;
     return hipSuccess;
+}
+
+// every reduction launch of the plan: flattened rows, then the others
+hipError_t launch_reductions(const AdaptiveState *a, int prec, const void *f, const double *s2, double *phi,
+                             hipStream_t s) {
+    hipError_t e = launch_aflat(prec, a->fl, f, a->tab, a->wtab, s2, phi, s);
+    for (int gi = 0; gi < kNG && e == hipSuccess; ++gi)
+        e = launch_aquad(prec, 4 << gi, a->grid[gi], f, a->segs, a->rseg, a->rows[gi], a->nrows[gi], a->wtab, s2,
+                         phi, s);
+    return e;
 }
 
 lc_status check_rule(const lc_abel_rule *r) {
@@ -223,11 +283,8 @@ lc_status execute_adaptive(lc_plan_s *p, const void *f, double *c, hipStream_t s
     int slot = -1;
     hipError_t e = timing_begin(p, s, &slot);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute: timing event");
-    for (int gi = 0; gi < kNG; ++gi) {
-        e = launch_aquad(d.prec, 4 << gi, a->grid[gi], f, a->segs, a->rseg, a->rows[gi], a->nrows[gi], a->wtab,
-                         p->s2, p->phi, s);
-        if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute: quadrature: ") + hipGetErrorString(e));
-    }
+    e = launch_reductions(a, d.prec, f, p->s2, p->phi, s);
+    if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute: quadrature: ") + hipGetErrorString(e));
     e = timing_end(p, s, slot);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute: timing event");
     e = launch_dst(p->dst, p->phi, d.H, d.L, d.N, p->tw_pre, p->tw_pack, p->tw_fft, p->zA, p->zB, c, s);
@@ -235,8 +292,9 @@ lc_status execute_adaptive(lc_plan_s *p, const void *f, double *c, hipStream_t s
     return LC_OK;
 }
 
-// Autotuning: the largest lane group (G = 16, 32 or 64 lanes per row for the
-// long rows), timed on the plan's own node array standing in for samples.
+// Autotuning: the largest lane group (G = 8 .. 64 lanes per row for the
+// long rows) and the grid (gmul 1, 2, 4 or one row per group), timed on the
+// plan's own node array standing in for samples.
 lc_status tune_adaptive(lc_plan_s *p, hipStream_t s) {
     AdaptiveState *a = (AdaptiveState *)p->ext;
     const std::string key = arch_name() + "|adaptive|" + std::to_string(p->fn.H) + "|" +
@@ -247,25 +305,18 @@ lc_status tune_adaptive(lc_plan_s *p, hipStream_t s) {
     if (cache_get(key, cached)) {
         int gc = best, mul = a->gmul;
         if (sscanf(cached.c_str(), "%d %d", &gc, &mul) >= 1) best = std::max(0, std::min(kNG - 1, gc));
-        a->gmul = std::max(1, std::min(4, mul));
+        a->gmul = std::max(0, std::min(4, mul));
     } else {
         double best_ms = 1e30;
         int best_mul = a->gmul;
-        for (int cand = 0; cand < 3 * (kNG - 1); ++cand) {
-            const int gc = 1 + cand / 3, mul = 1 << (cand % 3);  // grid: 1/2, 1, 2 rounds of resident blocks
+        for (int cand = 0; cand < 4 * (kNG - 1); ++cand) {
+            // grid: 1/2, 1, 2 rounds of resident blocks, or one row per group
+            const int gc = 1 + cand / 4, mul = cand % 4 == 3 ? 0 : 1 << (cand % 4);
             a->gmul = mul;
             group_rows(a->rlen, gc, grows);
             hipError_t e = set_groups(a, grows);
             if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: row groups");
-            const FnDesc &d = p->fn;
-            auto run = [&](hipStream_t st) {
-                for (int gi = 0; gi < kNG; ++gi) {
-                    hipError_t r = launch_aquad(d.prec, 4 << gi, a->grid[gi], p->x, a->segs, a->rseg, a->rows[gi],
-                                                a->nrows[gi], a->wtab, p->s2, p->phi, st);
-                    if (r != hipSuccess) return r;
-                }
-                return hipSuccess;
-            };
+            auto run = [&](hipStream_t st) { return launch_reductions(a, p->fn.prec, p->x, p->s2, p->phi, st); };
             const double ms = time_launch(run, s, 5, &e);
             if (e != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: timing");
             if (ms < best_ms) {
@@ -395,10 +446,21 @@ extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *
     if ((double)nnz > 4.0e10) return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_adaptive: too many samples");
 
     std::vector<int64_t> rlen(H, 0);
-    for (int64_t rr = 0; rr < H; ++rr)
-        for (int k = rseg[rr]; k < rseg[rr + 1]; ++k) rlen[rr] += segs[k].qp / vec;
+    std::vector<ATab> tab(segs.size());
+    std::vector<ARow> rdesc(H);
+    for (int64_t rr = 0; rr < H; ++rr) {
+        const int k0 = rseg[rr];
+        for (int k = k0; k < rseg[rr + 1]; ++k) {
+            const int64_t cst = (segs[k].off - segs[k0].off) / vec;
+            tab[k].cst = (int32_t)cst;
+            tab[k].wbase = (int32_t)(segs[k].woff / vec - cst);
+            tab[k].scale = segs[k].scale;
+            rlen[rr] += segs[k].qp / vec;
+        }
+        rdesc[rr] = ARow{segs[k0].off, (int32_t)rr, (int32_t)rlen[rr], k0, rseg[rr + 1] - k0, {0, 0}};
+    }
     std::vector<int32_t> grows[kNG];
-    int gcap = 2;  // G <= 16 lanes per row: measured best on the large band-limited rule
+    int gcap = 3;  // G <= 32 lanes per row, one row per group: measured best on the large band-limited rule
     if (const char *ev = getenv("LC_AQUAD_GMAX")) gcap = std::max(0, std::min(kNG - 1, atoi(ev)));
     group_rows(rlen, gcap, grows);
 
@@ -438,6 +500,7 @@ extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *
     };
     chk(aalloc(a, &p->x, (size_t)nnz, &ws));
     chk(aalloc(a, &a->segs, segs.size(), &ws));
+    chk(aalloc(a, &a->tab, tab.size(), &ws));
     chk(aalloc(a, &a->rseg, rseg.size(), &ws));
     chk(aalloc(a, &a->wtab, wt.size(), &ws));
     chk(aalloc(a, &a->dtab, dt.size(), &ws));
@@ -452,11 +515,14 @@ extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *
         chk(aalloc(a, &p->zB, (size_t)L, &ws));
     }
     a->prec = (int)prec;
-    chk(aalloc(a, &a->rows[0], (size_t)H, &ws));  // all groups' row lists, back to back
+    chk(aalloc(a, &a->rows[0], (size_t)H, &ws));   // all groups' row lists, back to back
+    chk(aalloc(a, &a->frows[0], (size_t)H, &ws));  // the same for flattened rows
+    a->rdesc = std::move(rdesc);
     if (e == hipSuccess) chk(set_groups(a, grows));
     a->gcap = gcap;
     a->rlen = std::move(rlen);
     up(a->segs, segs);
+    up(a->tab, tab);
     up(a->rseg, rseg);
     up(a->wtab, wt);
     up(a->dtab, dt);

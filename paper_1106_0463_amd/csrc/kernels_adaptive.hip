@@ -43,6 +43,137 @@ hipError_t launch_anodes(const ASeg *segs, int64_t nseg, const double2 *dtab, co
     return hipGetLastError();
 }
 
+// Orders the LDS accesses of one wave's lanes before and after it (a wave's
+// LDS operations execute in order; this keeps the compiler from moving them
+// across and waits for the writes).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Flattened reduction, G lanes per row: the panels of a row are contiguous
+// in f, so the group reads the row as one run of chunks in windows of 4 G
+// (one chunk per lane and step, four steps in flight), whatever the panel
+// boundaries.  The row's panel table sits in the group's LDS slot.  A window
+// inside one panel takes that panel's weights and scale; a window across
+// boundaries looks the panel up per chunk.  All lanes of a wave reach the
+// next row together (its groups reconverge after the window loop), so the
+// table of the next row is written after every read of the current one.
+//   phi[r] = s2[r] * sum_panels scale_k sum_i w_i f_i
+// Blocks blk = 0 .. nblk - 1 of this lane count take rows blk * 256/G + group,
+// striding by nblk * 256/G.
+template <typename T, int G>
+__device__ __forceinline__ void aflat_rows(const T *__restrict__ f, const ARow *__restrict__ rows, int64_t nrows,
+                                           int blk, int nblk, const ATab *__restrict__ tab,
+                                           const double *__restrict__ wtab, const double *__restrict__ s2,
+                                           double *__restrict__ phi, ATab *lds) {
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int W = 4 * G;
+    using V = typename VecOf<T, VEC>::type;
+    const int g = threadIdx.x & (G - 1);
+    const int gl = threadIdx.x / G;
+    ATab *st = lds + gl * kAflatMaxSeg;
+    const int64_t ngrp = (int64_t)nblk * (256 / G);
+    for (int64_t i = (int64_t)blk * (256 / G) + gl; i < nrows; i += ngrp) {
+        const ARow rd = rows[i];
+        for (int j = g; j < rd.S; j += G) st[j] = tab[rd.k0 + j];
+        wave_lds_sync();
+        const V *p = reinterpret_cast<const V *>(f + rd.rbeg);
+        const int nc = rd.nc, S = rd.S;
+        int k = 0;
+        int nxt = S > 1 ? st[1].cst : nc;
+        int wb = st[0].wbase;
+        double sc = st[0].scale;
+        double acc = 0.0;
+        for (int c0 = 0; c0 < nc; c0 += W) {
+            const int c = c0 + g;
+            V v[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v[m] = (c + m * G < nc) ? ld_stream(p + c + m * G) : V{};
+            if (c0 + W <= nxt) {
+                double d[4][VEC], w[4][VEC];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    to_d(v[m], d[m]);
+                    chunk_weights<VEC, true>(wtab, wb + c + m * G, w[m]);
+                }
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    a0 = fma(w[0][e], d[0][e], a0);
+                    a1 = fma(w[1][e], d[1][e], a1);
+                    a0 = fma(w[2][e], d[2][e], a0);
+                    a1 = fma(w[3][e], d[3][e], a1);
+                }
+                acc = fma(sc, a0 + a1, acc);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int cc = c + m * G;
+                    if (cc < nc) {
+                        int kk = k;
+                        while (kk + 1 < S && st[kk + 1].cst <= cc) ++kk;
+                        const ATab t = st[kk];
+                        double d[VEC], w[VEC];
+                        to_d(v[m], d);
+                        chunk_weights<VEC, true>(wtab, t.wbase + cc, w);
+                        double part = 0.0;
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) part = fma(w[e], d[e], part);
+                        acc = fma(t.scale, part, acc);
+                    }
+                }
+                while (k + 1 < S && st[k + 1].cst <= c0 + W) ++k;
+                wb = st[k].wbase;
+                sc = st[k].scale;
+                nxt = k + 1 < S ? st[k + 1].cst : nc;
+            }
+        }
+        acc = group_sum<G>(acc);
+        if (g == 0) phi[rd.r] = s2[rd.r] * acc;
+        wave_lds_sync();
+    }
+}
+
+// One launch for every lane count: blocks [b0[j], b0[j+1]) take the rows of
+// lane count 64 >> j (longest rows first in dispatch order); the LDS holds
+// the table slots of the largest number of groups per block (G = 4).
+template <typename T>
+__global__ __launch_bounds__(256) void k_aflat(const T *__restrict__ f, AflatLaunch L, const ATab *__restrict__ tab,
+                                               const double *__restrict__ wtab, const double *__restrict__ s2,
+                                               double *__restrict__ phi) {
+    __shared__ ATab lds[(256 / 4) * kAflatMaxSeg];
+    const int b = blockIdx.x;
+#define LC_AFR(J, GV)                                                                                  \
+    if (b < L.b0[J + 1]) {                                                                             \
+        aflat_rows<T, GV>(f, L.rows[J], L.nrows[J], b - L.b0[J], L.b0[J + 1] - L.b0[J], tab, wtab, s2, phi, lds); \
+        return;                                                                                        \
+    }
+    LC_AFR(0, 64) LC_AFR(1, 32) LC_AFR(2, 16) LC_AFR(3, 8) LC_AFR(4, 4)
+#undef LC_AFR
+}
+
+// Blocks of k_aflat<T> resident on one CU at once (occupancy API).
+int aflat_blocks_per_cu(int prec) {
+    int n = 0;
+    const hipError_t e = prec == LC_FP64
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_aflat<double>, 256, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_aflat<float>, 256, 0);
+    return (e == hipSuccess && n > 0) ? n : 4;
+}
+
+hipError_t launch_aflat(int prec, const AflatLaunch &L, const void *f, const ATab *tab, const double *wtab,
+                        const double *s2, double *phi, hipStream_t s) {
+    const int grid = L.b0[kAflatLanes];
+    if (grid < 1) return hipSuccess;
+    if (prec == LC_FP64)
+        hipLaunchKernelGGL(k_aflat<double>, dim3(grid), dim3(256), 0, s, (const double *)f, L, tab, wtab, s2, phi);
+    else
+        hipLaunchKernelGGL(k_aflat<float>, dim3(grid), dim3(256), 0, s, (const float *)f, L, tab, wtab, s2, phi);
+    return hipGetLastError();
+}
+
 // G lanes per row: a group walks the segments of its row, each reduced with
 // 16-byte loads of samples and of the (L2-resident) padded rule weights, and
 // the lane partials are combined with the fixed-order butterfly.

@@ -147,8 +147,40 @@ struct ASeg {
     double2 h;
 };
 
+// The same panel for the flattened row reduction: its first chunk (VEC
+// samples) counted from the row's start, the weight-table chunk that row
+// chunk 0 would map to (row chunk c of the panel takes weight chunk
+// wbase + c) and the scale.
+struct ATab {
+    int32_t cst;
+    int32_t wbase;
+    double scale;
+};
+// A row of the flattened reduction, in launch order: samples from element
+// rbeg, nc chunks, panels k0 .. k0 + S - 1 (S <= kAflatMaxSeg).
+struct ARow {
+    int64_t rbeg;
+    int32_t r;
+    int32_t nc;
+    int32_t k0;
+    int32_t S;
+    int32_t pad[2];
+};
+constexpr int kAflatMaxSeg = 16;
+// One launch of the flattened reduction over every lane count: entry j holds
+// the rows of G = 64 >> j lanes per row, taken by blocks [b0[j], b0[j + 1]).
+constexpr int kAflatLanes = 5;
+struct AflatLaunch {
+    const ARow *rows[kAflatLanes];
+    int64_t nrows[kAflatLanes];
+    int b0[kAflatLanes + 1];
+};
+
 hipError_t launch_anodes(const ASeg *segs, int64_t nseg, const double2 *dtab, const double2 *rowA, double *x,
                          hipStream_t s);
+int aflat_blocks_per_cu(int prec);
+hipError_t launch_aflat(int prec, const AflatLaunch &L, const void *f, const ATab *tab, const double *wtab,
+                        const double *s2, double *phi, hipStream_t s);
 int aquad_blocks_per_cu(int prec, int G);
 hipError_t launch_aquad(int prec, int G, int grid, const void *f, const ASeg *segs, const int32_t *rseg,
                         const int32_t *rows, int64_t nrows, const double *wtab, const double *s2, double *phi,

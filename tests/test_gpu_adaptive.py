@@ -7,7 +7,9 @@ sample f at their own correctly rounded FP64 nodes) and against the truth:
   paper's error level (its Error column: 2.7e-12 .. 1.6e-9);
 * the generating function eq. (2.2) at t = 0.999 with grading: c_n = t^n;
 * cos(omega x) with the band rule: the closed form of its coefficients;
-* a rule without cuts or band equals the uniform plan (same Gauss rule).
+* a rule without cuts or band equals the uniform plan (same Gauss rule);
+* rows of exactly 16 panels, and plans that mix rows of at most 16 panels
+  (one run of chunks per row) with rows of more (panel by panel).
 """
 import os
 from fractions import Fraction
@@ -170,3 +172,28 @@ def test_fp32_samples(lc):
     E_a = np.max(np.abs((c32 - c64) / (2 * n + 1))) / np.max(np.abs(c64 / (2 * n + 1)))
     banner(f"    E_a(fp32 vs fp64) {E_a:.2e}")
     assert E_a <= 1e-7
+
+
+def _panel_counts(M, rule):
+    H = M // 2
+    return [1 + len(oracle.abel_rule_cuts(np.sin(oracle.method.PI * j / (2 * H)), rule)) for j in range(1, H + 1)]
+
+
+@pytest.mark.parametrize("rule,mixed", [
+    (dict(q=8, grade_ratio=0.5, grade_levels=15), False),
+    (dict(q=8, breaks=(0.0, 0.3, -0.5, 0.7, 0.9), grade_ratio=0.5, grade_levels=12), True),
+])
+def test_many_panels(lc, rule, mixed):
+    N, M = 200, 1024
+    counts = _panel_counts(M, rule)
+    banner(f"[gpu] adaptive {min(counts)}..{max(counts)} panels per row, |x|^(3/2)")
+    if mixed:
+        assert min(counts) <= 16 < max(counts)
+    else:
+        assert min(counts) == max(counts) == 16
+    f = W.AbsPower(1.5)
+    got, info = _run(lc, f, N, M, rule)
+    ref = np.array(oracle.method_coeffs_rule(f, N, M, _orule(rule), fp64_nodes=True), dtype=float)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    banner(f"    vs oracle {err:.2e}")
+    assert err <= 1e-13
