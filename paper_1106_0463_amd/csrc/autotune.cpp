@@ -5,6 +5,7 @@
 // device architecture and the problem shape.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -77,7 +78,8 @@ bool quad_from_str(const std::string &s, QuadCfg &c) {
 // grids of one half, one and two rounds of the blocks the device holds at
 // once for that variant (occupancy API; a grid-stride launch whose grid is
 // not a whole number of rounds ends on a partial round), capped by the
-// useful number of blocks.
+// useful number of blocks, and with the useful number itself (one pass per
+// block: the blocks are handed out as CUs free up).
 std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu, bool batch) {
     std::vector<QuadCfg> out;
     auto add = [&](QuadCfg c) {
@@ -86,9 +88,10 @@ std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu, bool
         const int64_t useful = (rows + rpb - 1) / rpb;
         int occ = batch ? bquad_blocks_per_cu(c, prec) : quad_blocks_per_cu(c, prec);
         if (occ < 1) occ = 8;
-        for (int half_rounds : {1, 2, 4}) {
+        for (int half_rounds : {1, 2, 4, 0}) {
             QuadCfg g = c;
-            g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(useful, (int64_t)cu * occ * half_rounds / 2));
+            const int64_t want = half_rounds ? (int64_t)cu * occ * half_rounds / 2 : useful;
+            g.grid = (int)std::max<int64_t>(1, std::min<int64_t>({useful, want, (int64_t)INT32_MAX}));
             bool dup = false;
             for (auto &o : out) dup |= quad_to_str(o) == quad_to_str(g);
             if (!dup) out.push_back(g);

@@ -74,11 +74,18 @@ void part_starts(const std::vector<BatchTile> &tiles, const std::vector<int> &pa
     while (k < nparts) start[++k] = (int)tiles.size();
 }
 
-std::vector<BatchTile> make_tiles(const std::vector<FnDesc> &fn, const std::vector<int> &fns, int rpt) {
+// rpt rows per tile, addresses resolved: samples at f_off + r Q s bytes,
+// phi and s2 from row r of the function
+std::vector<BatchTile> make_tiles(const std::vector<FnDesc> &fn, const std::map<int64_t, HSet> &hs,
+                                  const std::vector<int> &fns, int rpt) {
     std::vector<BatchTile> tiles;
-    for (int b : fns)
-        for (int64_t r = 0; r < fn[b].H; r += rpt)
-            tiles.push_back({b, (int32_t)r, (int32_t)std::min<int64_t>(rpt, fn[b].H - r), 0});
+    for (int b : fns) {
+        const FnDesc &d = fn[b];
+        const int64_t esz = d.prec == LC_FP64 ? 8 : 4;
+        const double *s2 = hs.at(d.H).s2;
+        for (int64_t r = 0; r < d.H; r += rpt)
+            tiles.push_back({d.f_off + r * d.Q * esz, d.phi_off + r, s2 + r, (int32_t)std::min<int64_t>(rpt, d.H - r), b});
+    }
     return tiles;
 }
 
@@ -159,7 +166,7 @@ hipError_t launch_part_quad(BatchState *st, int k, const void *f_arena, hipStrea
         if (n <= 0) continue;
         QuadCfg c = qc.cfg;
         c.grid = std::max(1, std::min(c.grid, n));
-        hipError_t e = launch_bquad(c, qc.prec, f_arena, qc.w, qc.tiles + qc.tstart[k], n, st->dfn, st->phi_arena, s);
+        hipError_t e = launch_bquad(c, qc.prec, f_arena, qc.w, qc.tiles + qc.tstart[k], n, st->phi_arena, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -273,7 +280,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
             QuadCfg bc = qc.cfg;
             for (QuadCfg c : quad_candidates(qc.prec, qc.Q, qc.rows, cu, true)) {
                 c.Qv = qc.Q;
-                std::vector<BatchTile> tl = make_tiles(st->fn, qc.fns, quad_rows_per_block(c));
+                std::vector<BatchTile> tl = make_tiles(st->fn, st->hs, qc.fns, quad_rows_per_block(c));
                 BatchTile *dt = nullptr;
                 if ((e = hipMalloc((void **)&dt, tl.size() * sizeof(BatchTile))) != hipSuccess) break;
                 e = hipMemcpy(dt, tl.data(), tl.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
@@ -281,7 +288,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
                 if (e == hipSuccess) {
                     hipError_t er;
                     const int nt = (int)tl.size();
-                    const double t = time_launch([&](hipStream_t ss) { return launch_bquad(c, qc.prec, st->x_arena, qc.w, dt, nt, st->dfn, st->phi_arena, ss); }, s, 3, &er);
+                    const double t = time_launch([&](hipStream_t ss) { return launch_bquad(c, qc.prec, st->x_arena, qc.w, dt, nt, st->phi_arena, ss); }, s, 3, &er);
                     if (er == hipSuccess && t < best) { best = t; bc = c; }
                 }
                 hipFree(dt);
@@ -314,7 +321,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         QuadClass &qc = st->classes[i];
         QuadCfg c = qcfg[i];
         c.Qv = qc.Q;
-        std::vector<BatchTile> tl = make_tiles(st->fn, qc.fns, quad_rows_per_block(c));
+        std::vector<BatchTile> tl = make_tiles(st->fn, st->hs, qc.fns, quad_rows_per_block(c));
         BatchTile *dt = nullptr;
         if ((e = upload(st, &dt, tl)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_autotune: tiles");
         qc.tiles = dt;
@@ -505,7 +512,7 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         qc.cfg.Qv = qc.Q;
         qc.w = st->qs[qc.Q].w;
         qc.fns = kv.second;
-        std::vector<BatchTile> tiles = make_tiles(st->fn, qc.fns, quad_rows_per_block(qc.cfg));
+        std::vector<BatchTile> tiles = make_tiles(st->fn, st->hs, qc.fns, quad_rows_per_block(qc.cfg));
         qc.ntiles = (int)tiles.size();
         part_starts(tiles, st->part_of, st->nparts, qc.tstart);
         {   // one round of resident blocks of this variant

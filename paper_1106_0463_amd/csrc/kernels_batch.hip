@@ -1,7 +1,9 @@
 // Batched kernels: many functions of uneven size in one execution.
 //   * k_bquad_*: the Abel quadrature reduction over a table of row tiles
-//     (each tile a run of rows of one function); one launch per class of
-//     functions sharing (Q, sample precision), weights in registers.
+//     (each tile a run of rows of one function, its addresses resolved on
+//     the host); one launch per class of functions sharing (Q, sample
+//     precision), weights in registers.  A block reads the descriptor of its
+//     next tile while the samples of the current one are in flight.
 //   * k_bdst_lds: one workgroup per function, pack + LDS Stockham FFT +
 //     unpack/rescale (the twist and the one FFT of eq. (2.4)), functions
 //     listed longest first so the long ones start early.
@@ -17,7 +19,6 @@ template <typename T, int VEC, int G, int CPL, int U>
 __global__ __launch_bounds__(256) void k_bquad_fit(const unsigned char *__restrict__ f_arena,
                                                    const double *__restrict__ w,
                                                    const BatchTile *__restrict__ tiles, int ntiles,
-                                                   const BatchFn *__restrict__ fns,
                                                    double *__restrict__ phi_arena) {
     using V = typename VecOf<T, VEC>::type;
     constexpr int Q = G * CPL * VEC;
@@ -32,15 +33,16 @@ __global__ __launch_bounds__(256) void k_bquad_fit(const unsigned char *__restri
 #pragma unroll
         for (int e = 0; e < VEC; ++e) wr[c][e] = w[(g + c * G) * VEC + e];
 
+    BatchTile nx{};
+    if ((int)blockIdx.x < ntiles) nx = tiles[blockIdx.x];
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const BatchTile tl = tiles[t];
-        const BatchFn &fn = fns[tl.fn];
-        const T *f = reinterpret_cast<const T *>(f_arena + fn.f_off);
-        double *phi = phi_arena + fn.phi_off;
-        const double *s2 = fn.s2;
-        const int rend = tl.row0 + tl.nrows;
-        const int r0 = tl.row0 + wv * (RPW * U);
+        const BatchTile tl = nx;
+        const T *f = reinterpret_cast<const T *>(f_arena + tl.f_off);
+        double *phi = phi_arena + tl.phi_off;
+        const int rend = tl.nrows;
+        const int r0 = wv * (RPW * U);
         V val[U][CPL];
+        double s2v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int row = r0 + u * RPW + rg;
@@ -48,11 +50,17 @@ __global__ __launch_bounds__(256) void k_bquad_fit(const unsigned char *__restri
                 const V *p = reinterpret_cast<const V *>(f + (int64_t)row * Q) + g;
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) val[u][c] = ld_stream(p + c * G);
+                s2v[u] = ld_global(tl.s2 + row);
             } else {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) val[u][c] = (V)(T)0;
+                s2v[u] = 0.0;
             }
         }
+        // this tile's loads are in flight: read the next descriptor now (a
+        // scalar load issued earlier would be waited for with this tile's)
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + (int)gridDim.x < ntiles) nx = tiles[t + gridDim.x];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             double acc = 0.0;
@@ -65,7 +73,7 @@ __global__ __launch_bounds__(256) void k_bquad_fit(const unsigned char *__restri
             }
             acc = group_sum<G>(acc);
             const int row = r0 + u * RPW + rg;
-            if (g == 0 && row < rend) phi[row] = s2[row] * acc;
+            if (g == 0 && row < rend) phi[row] = s2v[u] * acc;
         }
     }
 }
@@ -74,7 +82,6 @@ template <typename T, int VEC, int G>
 __global__ __launch_bounds__(256) void k_bquad_gen(const unsigned char *__restrict__ f_arena,
                                                    const double *__restrict__ w, int Q,
                                                    const BatchTile *__restrict__ tiles, int ntiles,
-                                                   const BatchFn *__restrict__ fns,
                                                    double *__restrict__ phi_arena) {
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63;
@@ -82,16 +89,19 @@ __global__ __launch_bounds__(256) void k_bquad_gen(const unsigned char *__restri
     const int rg = lane / G;
     const int wv = threadIdx.x >> 6;
     const int NC = Q / VEC;
+    BatchTile nx{};
+    if ((int)blockIdx.x < ntiles) nx = tiles[blockIdx.x];
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const BatchTile tl = tiles[t];
-        const BatchFn &fn = fns[tl.fn];
-        const T *f = reinterpret_cast<const T *>(f_arena + fn.f_off);
-        const int rend = tl.row0 + tl.nrows;
-        const int row = tl.row0 + wv * RPW + rg;
+        const BatchTile tl = nx;
+        const T *f = reinterpret_cast<const T *>(f_arena + tl.f_off);
+        const int row = wv * RPW + rg;
+        const double s2v = row < tl.nrows ? ld_global(tl.s2 + row) : 0.0;
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + (int)gridDim.x < ntiles) nx = tiles[t + gridDim.x];
         double acc = 0.0;
-        if (row < rend) acc = row_partial<T, VEC, G>(f + (int64_t)row * Q, w, NC, g);
+        if (row < tl.nrows) acc = row_partial<T, VEC, G>(f + (int64_t)row * Q, w, NC, g);
         acc = group_sum<G>(acc);
-        if (g == 0 && row < rend) phi_arena[fn.phi_off + row] = fn.s2[row] * acc;
+        if (g == 0 && row < tl.nrows) phi_arena[tl.phi_off + row] = s2v * acc;
     }
 }
 
@@ -101,47 +111,47 @@ static thread_local int *g_bocc = nullptr;
 
 template <typename T, int VEC, int G, int CPL, int U>
 static hipError_t bfit(const QuadCfg &c, const void *f, const double *w, const BatchTile *tiles, int ntiles,
-                       const BatchFn *fns, double *phi, hipStream_t s) {
+                       double *phi, hipStream_t s) {
     if (g_bocc)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_bocc, (const void *)k_bquad_fit<T, VEC, G, CPL, U>,
                                                             c.block, 0);
     hipLaunchKernelGGL((k_bquad_fit<T, VEC, G, CPL, U>), dim3(c.grid), dim3(c.block), 0, s,
-                       (const unsigned char *)f, w, tiles, ntiles, fns, phi);
+                       (const unsigned char *)f, w, tiles, ntiles, phi);
     return hipGetLastError();
 }
 
 template <typename T, int VEC, int G>
 static hipError_t bgen(const QuadCfg &c, const void *f, const double *w, int Q, const BatchTile *tiles,
-                       int ntiles, const BatchFn *fns, double *phi, hipStream_t s) {
+                       int ntiles, double *phi, hipStream_t s) {
     if (g_bocc)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_bocc, (const void *)k_bquad_gen<T, VEC, G>, c.block, 0);
     hipLaunchKernelGGL((k_bquad_gen<T, VEC, G>), dim3(c.grid), dim3(c.block), 0, s,
-                       (const unsigned char *)f, w, Q, tiles, ntiles, fns, phi);
+                       (const unsigned char *)f, w, Q, tiles, ntiles, phi);
     return hipGetLastError();
 }
 
 #define LC_BFIT_CASES(TT, VV, GG)                                                                 \
     if (c.G == GG && c.vec == VV) {                                                               \
         switch (c.cpl * 16 + c.unroll) {                                                          \
-            case 1 * 16 + 1: return bfit<TT, VV, GG, 1, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 1 * 16 + 2: return bfit<TT, VV, GG, 1, 2>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 1 * 16 + 4: return bfit<TT, VV, GG, 1, 4>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 2 * 16 + 1: return bfit<TT, VV, GG, 2, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 2 * 16 + 2: return bfit<TT, VV, GG, 2, 2>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 2 * 16 + 4: return bfit<TT, VV, GG, 2, 4>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 3 * 16 + 1: return bfit<TT, VV, GG, 3, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 3 * 16 + 2: return bfit<TT, VV, GG, 3, 2>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 4 * 16 + 1: return bfit<TT, VV, GG, 4, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 4 * 16 + 2: return bfit<TT, VV, GG, 4, 2>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 6 * 16 + 1: return bfit<TT, VV, GG, 6, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
-            case 8 * 16 + 1: return bfit<TT, VV, GG, 8, 1>(c, f, w, tiles, ntiles, fns, phi, s); \
+            case 1 * 16 + 1: return bfit<TT, VV, GG, 1, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 1 * 16 + 2: return bfit<TT, VV, GG, 1, 2>(c, f, w, tiles, ntiles, phi, s); \
+            case 1 * 16 + 4: return bfit<TT, VV, GG, 1, 4>(c, f, w, tiles, ntiles, phi, s); \
+            case 2 * 16 + 1: return bfit<TT, VV, GG, 2, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 2 * 16 + 2: return bfit<TT, VV, GG, 2, 2>(c, f, w, tiles, ntiles, phi, s); \
+            case 2 * 16 + 4: return bfit<TT, VV, GG, 2, 4>(c, f, w, tiles, ntiles, phi, s); \
+            case 3 * 16 + 1: return bfit<TT, VV, GG, 3, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 3 * 16 + 2: return bfit<TT, VV, GG, 3, 2>(c, f, w, tiles, ntiles, phi, s); \
+            case 4 * 16 + 1: return bfit<TT, VV, GG, 4, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 4 * 16 + 2: return bfit<TT, VV, GG, 4, 2>(c, f, w, tiles, ntiles, phi, s); \
+            case 6 * 16 + 1: return bfit<TT, VV, GG, 6, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 8 * 16 + 1: return bfit<TT, VV, GG, 8, 1>(c, f, w, tiles, ntiles, phi, s); \
             default: break;                                                                       \
         }                                                                                         \
     }
 
 template <typename T>
 static hipError_t bdispatch(const QuadCfg &c, const void *f, const double *w, int Q, const BatchTile *tiles,
-                            int ntiles, const BatchFn *fns, double *phi, hipStream_t s) {
+                            int ntiles, double *phi, hipStream_t s) {
     if (c.cpl > 0) {
         if constexpr (sizeof(T) == 8) {
             LC_BFIT_CASES(T, 2, 4)
@@ -155,14 +165,14 @@ static hipError_t bdispatch(const QuadCfg &c, const void *f, const double *w, in
         return hipErrorInvalidValue;
     }
     switch (c.vec * 1000 + c.G) {
-        case 1004: return bgen<T, 1, 4>(c, f, w, Q, tiles, ntiles, fns, phi, s);
-        case 1008: return bgen<T, 1, 8>(c, f, w, Q, tiles, ntiles, fns, phi, s);
-        case 1016: return bgen<T, 1, 16>(c, f, w, Q, tiles, ntiles, fns, phi, s);
-        case 1032: return bgen<T, 1, 32>(c, f, w, Q, tiles, ntiles, fns, phi, s);
-        case 1064: return bgen<T, 1, 64>(c, f, w, Q, tiles, ntiles, fns, phi, s);
-        case 2016: return bgen<T, 2, 16>(c, f, w, Q, tiles, ntiles, fns, phi, s);
-        case 2032: return bgen<T, 2, 32>(c, f, w, Q, tiles, ntiles, fns, phi, s);
-        case 2064: return bgen<T, 2, 64>(c, f, w, Q, tiles, ntiles, fns, phi, s);
+        case 1004: return bgen<T, 1, 4>(c, f, w, Q, tiles, ntiles, phi, s);
+        case 1008: return bgen<T, 1, 8>(c, f, w, Q, tiles, ntiles, phi, s);
+        case 1016: return bgen<T, 1, 16>(c, f, w, Q, tiles, ntiles, phi, s);
+        case 1032: return bgen<T, 1, 32>(c, f, w, Q, tiles, ntiles, phi, s);
+        case 1064: return bgen<T, 1, 64>(c, f, w, Q, tiles, ntiles, phi, s);
+        case 2016: return bgen<T, 2, 16>(c, f, w, Q, tiles, ntiles, phi, s);
+        case 2032: return bgen<T, 2, 32>(c, f, w, Q, tiles, ntiles, phi, s);
+        case 2064: return bgen<T, 2, 64>(c, f, w, Q, tiles, ntiles, phi, s);
         default: break;
     }
     return hipErrorInvalidValue;
@@ -172,17 +182,17 @@ static hipError_t bdispatch(const QuadCfg &c, const void *f, const double *w, in
 int bquad_blocks_per_cu(const QuadCfg &cfg, int prec) {
     int n = 0;
     g_bocc = &n;
-    const hipError_t e = prec == LC_FP64 ? bdispatch<double>(cfg, nullptr, nullptr, cfg.Qv, nullptr, 1, nullptr, nullptr, 0)
-                                         : bdispatch<float>(cfg, nullptr, nullptr, cfg.Qv, nullptr, 1, nullptr, nullptr, 0);
+    const hipError_t e = prec == LC_FP64 ? bdispatch<double>(cfg, nullptr, nullptr, cfg.Qv, nullptr, 1, nullptr, 0)
+                                         : bdispatch<float>(cfg, nullptr, nullptr, cfg.Qv, nullptr, 1, nullptr, 0);
     g_bocc = nullptr;
     return (e == hipSuccess && n > 0) ? n : 0;
 }
 
 hipError_t launch_bquad(const QuadCfg &cfg, int prec, const void *f_arena, const double *w, const BatchTile *tiles,
-                        int ntiles, const BatchFn *fns, double *phi_arena, hipStream_t s) {
+                        int ntiles, double *phi_arena, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    if (prec == LC_FP64) return bdispatch<double>(cfg, f_arena, w, cfg.Qv, tiles, ntiles, fns, phi_arena, s);
-    return bdispatch<float>(cfg, f_arena, w, cfg.Qv, tiles, ntiles, fns, phi_arena, s);
+    if (prec == LC_FP64) return bdispatch<double>(cfg, f_arena, w, cfg.Qv, tiles, ntiles, phi_arena, s);
+    return bdispatch<float>(cfg, f_arena, w, cfg.Qv, tiles, ntiles, phi_arena, s);
 }
 
 // One workgroup per listed function.

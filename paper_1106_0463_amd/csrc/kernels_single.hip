@@ -95,6 +95,7 @@ __global__ __launch_bounds__(256) void k_quad_fit(const T *__restrict__ f, const
 
     for (int64_t r0 = wave * (RPW * U); r0 < rows; r0 += nwaves * (RPW * U)) {
         V val[U][CPL];
+        double s2v[U];  // read with the samples, not after the reduction
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = r0 + u * RPW + rg;
@@ -102,9 +103,11 @@ __global__ __launch_bounds__(256) void k_quad_fit(const T *__restrict__ f, const
                 const V *p = reinterpret_cast<const V *>(f + row * Q) + g;
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) val[u][c] = ld_stream(p + c * G);
+                s2v[u] = s2[row];
             } else {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) val[u][c] = (V)(T)0;
+                s2v[u] = 0.0;
             }
         }
 #pragma unroll
@@ -119,7 +122,7 @@ __global__ __launch_bounds__(256) void k_quad_fit(const T *__restrict__ f, const
             }
             acc = group_sum<G>(acc);
             const int64_t row = r0 + u * RPW + rg;
-            if (g == 0 && row < rows) phi[row] = s2[row] * acc;
+            if (g == 0 && row < rows) phi[row] = s2v[u] * acc;
         }
     }
 }
@@ -138,10 +141,11 @@ __global__ __launch_bounds__(256) void k_quad_gen(const T *__restrict__ f, const
     const int NC = Q / VEC;
     for (int64_t r0 = wave * RPW; r0 < rows; r0 += nwaves * RPW) {
         const int64_t row = r0 + rg;
+        const double s2v = row < rows ? s2[row] : 0.0;  // read before the row, not after it
         double acc = 0.0;
         if (row < rows) acc = row_partial<T, VEC, G>(f + row * Q, w, NC, g);
         acc = group_sum<G>(acc);
-        if (g == 0 && row < rows) phi[row] = s2[row] * acc;
+        if (g == 0 && row < rows) phi[row] = s2v * acc;
     }
 }
 

@@ -93,12 +93,15 @@ struct NodeTile {
 };
 
 // A run of rows of one function handled by one block of the batched
-// quadrature kernel.
+// quadrature kernel, resolved on the host: byte offset of its first row's
+// samples in the sample arena, element offset of its first phi, the s2 of
+// its first row, its row count, and the function (host bookkeeping).
 struct BatchTile {
-    int32_t fn;
-    int32_t row0;
+    int64_t f_off;
+    int64_t phi_off;
+    const double *s2;
     int32_t nrows;
-    int32_t pad;
+    int32_t fn;
 };
 
 }  // namespace lc
@@ -206,7 +209,7 @@ int quad_rows_per_block(const QuadCfg &cfg);
 
 // --- batched launchers (kernels_batch.hip) ---------------------------------
 hipError_t launch_bquad(const QuadCfg &cfg, int prec, const void *f_arena, const double *w,
-                        const BatchTile *tiles, int ntiles, const BatchFn *fns, double *phi_arena,
+                        const BatchTile *tiles, int ntiles, double *phi_arena,
                         hipStream_t s);
 hipError_t launch_bdst(int threads, int Lmax, const double *phi_arena, const BatchFn *fns,
                        const int32_t *list, int nlist, double *c_arena, hipStream_t s);

@@ -32,6 +32,12 @@ __device__ __forceinline__ V ld_stream(const V *p) {
     return __builtin_nontemporal_load(p);
 }
 
+// Load through a pointer known to address global memory (a pointer read out
+// of a descriptor is otherwise a flat access, counted with the LDS ones).
+__device__ __forceinline__ double ld_global(const double *p) {
+    return *(const __attribute__((address_space(1))) double *)p;
+}
+
 template <int G>
 __device__ __forceinline__ double group_sum(double acc) {
 #pragma unroll
