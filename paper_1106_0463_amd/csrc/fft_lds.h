@@ -77,7 +77,8 @@ template <> struct Dft<8> {
 // stored back to back in LDS (in place: every thread first loads all of its
 // butterflies, then the block synchronizes, then results are stored).
 // Ns is the product of the radices of the previous passes.  Twiddles
-// e^{2 pi i m / Lsub} are read from tw[m * tw_stride].
+// e^{2 pi i m / Lsub} are read from tw[m * tw_stride], requested with the
+// LDS loads so that their latency passes while the block synchronizes.
 // Requires nsub * Lsub <= EPT * T (checked by the host launchers).
 template <int R, int T, int EPT>
 __device__ __forceinline__ void stockham_pass(double2 *__restrict__ lds, int Lsub, int nsub, int Ns,
@@ -86,7 +87,10 @@ __device__ __forceinline__ void stockham_pass(double2 *__restrict__ lds, int Lsu
     const int nbs = Lsub / R;
     const int total = nsub * nbs;
     const int tid = threadIdx.x;
+    const int span = Ns * R;
+    const int twstep = Lsub / span;
     double2 v[MAXB][R];
+    double2 w[MAXB][R - 1];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * T;
@@ -96,11 +100,14 @@ __device__ __forceinline__ void stockham_pass(double2 *__restrict__ lds, int Lsu
             const double2 *x = lds + sub * Lsub;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = x[j + r * nbs];
+            if (Ns > 1) {
+                const int k = j % Ns;
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[i][r - 1] = tw[(int64_t)(k * r * twstep) * tw_stride];
+            }
         }
     }
     __syncthreads();
-    const int span = Ns * R;
-    const int twstep = Lsub / span;
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * T;
@@ -110,8 +117,7 @@ __device__ __forceinline__ void stockham_pass(double2 *__restrict__ lds, int Lsu
             const int k = j % Ns;
             if (Ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r)
-                    v[i][r] = cmul(v[i][r], tw[(int64_t)(k * r * twstep) * tw_stride]);
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[i][r - 1]);
             }
             Dft<R>::run(v[i]);
             double2 *y = lds + sub * Lsub;
@@ -148,20 +154,45 @@ __device__ void fft_lds(double2 *__restrict__ lds, int Lsub, int nsub, const Fft
 //   v_q = sum_{k<H} V_k e^{2 pi i q k / H}  as  v_{2p} = Re z_p, v_{2p+1} = Im z_p,
 // and the sine sums of eq. (2.4) follow in dst_post.  tw_pre[k] = e^{i pi k/(2H)}
 // (k < H), tw_pack[k] = e^{2 pi i k / H} (k < L).
+// Branch-free in k: V_0 = tw_pre[0] (phi_H - 0 i) with tw_pre[0] = 1 gives
+// exactly (phi_H, +0), and phi_k is read at index max(k, 1) so that k = 0
+// reads nothing outside phi.
 template <typename PhiAt>
 __device__ __forceinline__ double2 dst_pack(int64_t k, PhiAt phi, int64_t H, int64_t L,
                                             const double2 *__restrict__ tw_pre,
                                             const double2 *__restrict__ tw_pack) {
-    double2 vk;
-    if (k == 0) {
-        vk = make_double2(phi(H), 0.0);
-    } else {
-        vk = cmul(tw_pre[k], make_double2(phi(H - k), -phi(k)));
-    }
-    double2 vkl = cmul(tw_pre[k + L], make_double2(phi(L - k), -phi(L + k)));
-    double2 sum = cadd(vk, vkl);
-    double2 r = cmul(tw_pack[k], csub(vk, vkl));
+    const double pk = phi(k > 0 ? k : 1);
+    const double2 vk = cmul(tw_pre[k], make_double2(phi(H - k), k > 0 ? -pk : 0.0));
+    const double2 vkl = cmul(tw_pre[k + L], make_double2(phi(L - k), -phi(L + k)));
+    const double2 sum = cadd(vk, vkl);
+    const double2 r = cmul(tw_pack[k], csub(vk, vkl));
     return make_double2(sum.x - r.y, sum.y + r.x);
+}
+
+// Z_k of every k < L into lds[k], up to EPT values per thread (L <= EPT T),
+// four at a time: indices past L are clamped to L - 1 so that the four
+// values' loads are all issued before the first is used; only k < L is
+// stored.
+template <int T, int EPT, typename PhiAt>
+__device__ __forceinline__ void dst_pack_lds(double2 *__restrict__ lds, PhiAt phi, int64_t H, int L,
+                                             const double2 *__restrict__ tw_pre,
+                                             const double2 *__restrict__ tw_pack) {
+    constexpr int U = EPT < 4 ? EPT : 4;
+#pragma unroll
+    for (int i0 = 0; i0 < EPT; i0 += U) {
+        if (i0 * T >= L) break;
+        double2 z[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = (int)threadIdx.x + (i0 + u) * T;
+            z[u] = dst_pack(k < L ? k : L - 1, phi, H, L, tw_pre, tw_pack);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = (int)threadIdx.x + (i0 + u) * T;
+            if (k < L) lds[k] = z[u];
+        }
+    }
 }
 
 // DST-III unpack and rescale: c_n = (2n+1) a_n with

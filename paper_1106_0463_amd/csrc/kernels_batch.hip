@@ -210,7 +210,7 @@ __global__ __launch_bounds__(T) void k_bdst_lds(const double *__restrict__ phi_a
         const double *p;
         __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
     } ph{phi_arena + fn.phi_off};
-    for (int k = threadIdx.x; k < L; k += T) lds[k] = dst_pack(k, ph, H, L, fn.tw_pre, fn.tw_pack);
+    dst_pack_lds<T, 8>(lds, ph, H, L, fn.tw_pre, fn.tw_pack);
     __syncthreads();
     fft_lds<T, 8>(lds, L, 1, sch, fn.tw_fft, 1);
     double *c = c_arena + fn.c_off;

@@ -599,9 +599,10 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
 }
 
 // ------------------------------------------------- batched DST of rows ---
-// Function b reads phi_j = Out[b][j-1] * 2^(rowexp[j-1] + colexp[b]) (no
-// scaling when the exponent arrays are null).
-template <int T, typename PhiT>
+// Function b reads phi_j = Out[b][j-1] * 2^(rowexp[j-1] + colexp[b]); SC
+// (rowexp given) is a template argument, so that the reads of phi carry no
+// branch and the pack can issue them together.
+template <int T, typename PhiT, bool SC>
 __global__ __launch_bounds__(T) void k_gdst_lds(const PhiT *__restrict__ Out, int ldo, const int *__restrict__ rowexp,
                                                 const int *__restrict__ colexp, int64_t H, int L, int64_t N,
                                                 const double2 *__restrict__ tw_pre,
@@ -618,10 +619,11 @@ __global__ __launch_bounds__(T) void k_gdst_lds(const PhiT *__restrict__ Out, in
         int ce;
         __device__ __forceinline__ double operator()(int64_t m) const {
             const double v = (double)p[m - 1];
-            return re ? ldexp(v, re[m - 1] + ce) : v;
+            if constexpr (SC) return ldexp(v, re[m - 1] + ce);
+            return v;
         }
     } ph{row, rowexp, ce};
-    for (int k = threadIdx.x; k < L; k += T) lds[k] = dst_pack(k, ph, H, L, tw_pre, tw_pack);
+    dst_pack_lds<T, 8>(lds, ph, H, L, tw_pre, tw_pack);
     __syncthreads();
     fft_lds<T, 8>(lds, L, 1, sch, tw_fft, 1);
     double *c = C + (int64_t)b * N;
@@ -634,17 +636,18 @@ hipError_t launch_gdst(int phi_is_fp32, const void *Out, int ldo, const int *row
     const size_t lds = (size_t)L * sizeof(double2);
     int T = L <= 512 ? 64 : (L <= 2048 ? 256 : 1024);
     if (L > 8 * T) return hipErrorInvalidValue;
-#define LC_GD(TV, PT)                                                                                  \
-    if (T == TV) {                                                                                     \
+#define LC_GD1(TV, PT, SCV)                                                                            \
+    if (T == TV && (rowexp != nullptr) == SCV) {                                                       \
         if (lds > 65536) {                                                                             \
-            hipError_t e = hipFuncSetAttribute((const void *)k_gdst_lds<TV, PT>,                       \
+            hipError_t e = hipFuncSetAttribute((const void *)k_gdst_lds<TV, PT, SCV>,                  \
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
             if (e != hipSuccess) return e;                                                             \
         }                                                                                              \
-        hipLaunchKernelGGL((k_gdst_lds<TV, PT>), dim3(B), dim3(TV), lds, s, (const PT *)Out, ldo, rowexp, colexp, \
-                           H, (int)L, N, tw_pre, tw_pack, tw_fft, sch, C);                             \
+        hipLaunchKernelGGL((k_gdst_lds<TV, PT, SCV>), dim3(B), dim3(TV), lds, s, (const PT *)Out, ldo, rowexp, \
+                           colexp, H, (int)L, N, tw_pre, tw_pack, tw_fft, sch, C);                     \
         return hipGetLastError();                                                                      \
     }
+#define LC_GD(TV, PT) LC_GD1(TV, PT, true) LC_GD1(TV, PT, false)
     if (phi_is_fp32) {
         LC_GD(64, float)
         LC_GD(256, float)
@@ -655,6 +658,7 @@ hipError_t launch_gdst(int phi_is_fp32, const void *Out, int ldo, const int *row
         LC_GD(1024, double)
     }
 #undef LC_GD
+#undef LC_GD1
     return hipErrorInvalidValue;
 }
 

@@ -284,7 +284,7 @@ __global__ __launch_bounds__(T) void k_dst_lds(const double *__restrict__ phi, i
                                                double *__restrict__ c) {
     extern __shared__ double2 lds[];
     GlobalPhi ph{phi};
-    for (int k = threadIdx.x; k < L; k += T) lds[k] = dst_pack(k, ph, H, L, tw_pre, tw_pack);
+    dst_pack_lds<T, 8>(lds, ph, H, L, tw_pre, tw_pack);
     __syncthreads();
     fft_lds<T, 8>(lds, L, 1, sch, tw_fft, 1);
     for (int64_t n = threadIdx.x; n < N; n += T) c[n] = dst_post(n, lds, H);
