@@ -148,11 +148,26 @@ void free_state(BatchState *st) {
     delete st;
 }
 
-hipError_t launch_part_dst(BatchState *st, int k, double *c_arena, hipStream_t s) {
+// DST work of part k.  With a second stream s2 the DST groups (independent
+// functions) are spread over s and s2, largest estimated work first onto
+// the less loaded stream, so that one group's last round of workgroups
+// overlaps the others; the batched four-step passes stay on s.
+hipError_t launch_part_dst(BatchState *st, int k, double *c_arena, hipStream_t s, hipStream_t s2 = nullptr) {
     hipError_t e;
-    for (auto &g : st->groups) {
+    std::vector<int> order(st->groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    auto cost = [&](int i) {
+        const DstGroup &g = st->groups[i];
+        return (double)(g.lstart[k + 1] - g.lstart[k]) * g.Lmax;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    double load[2] = {0.0, 0.0};
+    for (int i : order) {
+        const DstGroup &g = st->groups[i];
         const int n = g.lstart[k + 1] - g.lstart[k];
-        e = launch_bdst(g.threads, g.Lmax, st->phi_arena, st->dfn, g.list + g.lstart[k], n, c_arena, s);
+        const int w = (s2 && load[1] < load[0]) ? 1 : 0;
+        load[w] += cost(i);
+        e = launch_bdst(g.threads, g.Lmax, st->phi_arena, st->dfn, g.list + g.lstart[k], n, c_arena, w ? s2 : s);
         if (e != hipSuccess) return e;
     }
     return launch_bbig(st->phi_arena, st->dbig, st->ctiles + st->cst[k], st->cst[k + 1] - st->cst[k],
@@ -189,14 +204,16 @@ hipError_t launch_all(lc_plan_s *p, BatchState *st, const void *f_arena, double 
 // Captured order: a two-stream pipeline.  The quadrature of part k runs on
 // the caller's stream; the DST of part k runs on the side stream once part
 // k's quadrature is done, so it overlaps the (HBM-bound) quadrature of part
-// k+1.  The side stream joins back before the graph ends.
+// k+1.  The last part's DST groups use both streams (the caller's has no
+// quadrature left).  The side stream joins back before the graph ends.
 hipError_t launch_pipeline(BatchState *st, const void *f_arena, double *c_arena, hipStream_t s) {
     hipError_t e;
     for (int k = 0; k < st->nparts; ++k) {
         if ((e = launch_part_quad(st, k, f_arena, s)) != hipSuccess) return e;
         if ((e = hipEventRecord(st->evq[k], s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(st->side, st->evq[k], 0)) != hipSuccess) return e;
-        if ((e = launch_part_dst(st, k, c_arena, st->side)) != hipSuccess) return e;
+        const bool last = k + 1 == st->nparts;
+        if ((e = launch_part_dst(st, k, c_arena, st->side, last ? s : nullptr)) != hipSuccess) return e;
     }
     if ((e = hipEventRecord(st->evj, st->side)) != hipSuccess) return e;
     return hipStreamWaitEvent(s, st->evj, 0);
