@@ -263,9 +263,21 @@ __global__ __launch_bounds__(256) void k_bbig_cols(const double *__restrict__ ph
         const double *p;
         __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
     } ph{phi_arena + fn.phi_off};
-    for (int e = threadIdx.x; e < CB * L1; e += 256) {
-        const int k1 = e / CB, cb = e - k1 * CB;
-        lds[cb * L1 + k1] = dst_pack((int64_t)L2 * k1 + k20 + cb, ph, fn.H, fn.L, fn.tw_pre, fn.tw_pack);
+    // four values per thread at a time, every load issued before the first use
+    for (int e0 = 0; e0 < CB * L1; e0 += 4 * 256) {
+        double2 z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = min(e0 + (int)threadIdx.x + u * 256, CB * L1 - 1);
+            const int k1 = e / CB, cb = e - k1 * CB;
+            z[u] = dst_pack((int64_t)L2 * k1 + k20 + cb, ph, fn.H, fn.L, fn.tw_pre, fn.tw_pack);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + (int)threadIdx.x + u * 256;
+            const int k1 = e / CB, cb = e - k1 * CB;
+            if (e < CB * L1) lds[cb * L1 + k1] = z[u];
+        }
     }
     __syncthreads();
     fft_lds<256, 8>(lds, L1, CB, s1, fn.tw_fft, L2);
@@ -282,7 +294,14 @@ __global__ __launch_bounds__(256) void k_bbig_rows(const BigFn *__restrict__ fns
     const BigFn &fn = fns[tl.fn];
     const int L1 = fn.L1, L2 = fn.L2, RB = fn.RB, p10 = tl.first;
     const FftSched s2 = fn.s2;
-    for (int e = threadIdx.x; e < RB * L2; e += 256) lds[e] = fn.zA[(int64_t)p10 * L2 + e];
+    for (int e0 = 0; e0 < RB * L2; e0 += 4 * 256) {  // four loads in flight per thread
+        double2 z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z[u] = fn.zA[(int64_t)p10 * L2 + min(e0 + (int)threadIdx.x + u * 256, RB * L2 - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + (int)threadIdx.x + u * 256 < RB * L2) lds[e0 + threadIdx.x + u * 256] = z[u];
+    }
     __syncthreads();
     fft_lds<256, 8>(lds, L2, RB, s2, fn.tw_fft, L1);
     for (int e = threadIdx.x; e < RB * L2; e += 256) {

@@ -302,9 +302,21 @@ __global__ __launch_bounds__(T) void k_fft_cols(const double *__restrict__ phi, 
     const int64_t L = (int64_t)L1 * L2;
     const int k20 = blockIdx.x * CB;
     GlobalPhi ph{phi};
-    for (int e = threadIdx.x; e < CB * L1; e += T) {
-        const int k1 = e / CB, cb = e - k1 * CB;
-        lds[cb * L1 + k1] = dst_pack((int64_t)L2 * k1 + k20 + cb, ph, H, L, tw_pre, tw_pack);
+    // four values per thread at a time, every load issued before the first use
+    for (int e0 = 0; e0 < CB * L1; e0 += 4 * T) {
+        double2 z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = min(e0 + (int)threadIdx.x + u * T, CB * L1 - 1);
+            const int k1 = e / CB, cb = e - k1 * CB;
+            z[u] = dst_pack((int64_t)L2 * k1 + k20 + cb, ph, H, L, tw_pre, tw_pack);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + (int)threadIdx.x + u * T;
+            const int k1 = e / CB, cb = e - k1 * CB;
+            if (e < CB * L1) lds[cb * L1 + k1] = z[u];
+        }
     }
     __syncthreads();
     fft_lds<T, 8>(lds, L1, CB, s1, tw_fft, L2);
@@ -321,7 +333,14 @@ __global__ __launch_bounds__(T) void k_fft_rows(const double2 *__restrict__ A, i
                                                 double2 *__restrict__ z) {
     extern __shared__ double2 lds[];
     const int p10 = blockIdx.x * RB;
-    for (int e = threadIdx.x; e < RB * L2; e += T) lds[e] = A[(int64_t)p10 * L2 + e];
+    for (int e0 = 0; e0 < RB * L2; e0 += 4 * T) {  // four loads in flight per thread
+        double2 z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z[u] = A[(int64_t)p10 * L2 + min(e0 + (int)threadIdx.x + u * T, RB * L2 - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + (int)threadIdx.x + u * T < RB * L2) lds[e0 + threadIdx.x + u * T] = z[u];
+    }
     __syncthreads();
     fft_lds<T, 8>(lds, L2, RB, s2, tw_fft, L1);
     for (int e = threadIdx.x; e < RB * L2; e += T) {
