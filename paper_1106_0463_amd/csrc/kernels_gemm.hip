@@ -133,6 +133,8 @@ hipError_t launch_amat(int H, int P, int QA, const double *xc, const double *lam
 // global->LDS copies and the LDS reads of the product are all 16 contiguous
 // bytes per lane, which no bank or channel pattern can split.  Rows are
 // padded to the block tile and k to Kp with zeros.
+constexpr int kSplitKW = 4;  // k fragments per wave in the column split
+
 __device__ __forceinline__ int64_t fo_offset(int64_t r, int k, int K16) {
     return ((r >> 5) * K16 + (k >> 4)) * 512 + (((r & 31) + ((k >> 3) & 1) * 32) << 3) + (k & 7);
 }
@@ -283,23 +285,29 @@ template <typename H16, int NPC>
 __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F, int P, int B, int K16, int RB,
                                                     H16 *__restrict__ X, int64_t piece_stride,
                                                     const int *__restrict__ colexp) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t frag = t >> 6;
-    if (frag >= (int64_t)RB * K16) return;
-    const int lane = (int)(t & 63);
-    const int rb = (int)(frag % RB), k16 = (int)(frag / RB);
+    // block (rb, kg): wave w writes the kSplitKW consecutive k fragments from
+    // (4 kg + w) kSplitKW on, so a block's fragments of one piece are one
+    // contiguous 4 kSplitKW KiB run; consecutive blocks take consecutive rb,
+    // so the reads sweep rows of F in order
+    const int rb = (int)(blockIdx.x % (unsigned)RB), kg = (int)(blockIdx.x / (unsigned)RB);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int b = rb * 32 + (lane & 31);
-    const int k = k16 * 16 + (lane >> 5) * 8;
-    double v[8];
     const double sc = (colexp && b < B) ? ldexp(1.0, -max(colexp[b], -1000)) : 1.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-        v[e] = (b < B && k + e < P) ? __builtin_nontemporal_load(F + (int64_t)(k + e) * B + b) * sc : 0.0;
-    u32x4 out[NPC];
-    split8<H16, NPC>(v, out);
+    for (int j = 0; j < kSplitKW; ++j) {
+        const int k16 = (kg * 4 + w) * kSplitKW + j;
+        if (k16 >= K16) break;
+        const int k = k16 * 16 + (lane >> 5) * 8;
+        double v[8];
 #pragma unroll
-    for (int i = 0; i < NPC; ++i)
-        *reinterpret_cast<u32x4 *>(X + i * piece_stride + fo_offset(b, k, K16)) = out[i];
+        for (int e = 0; e < 8; ++e)
+            v[e] = (b < B && k + e < P) ? __builtin_nontemporal_load(F + (int64_t)(k + e) * B + b) * sc : 0.0;
+        u32x4 out[NPC];
+        split8<H16, NPC>(v, out);
+#pragma unroll
+        for (int i = 0; i < NPC; ++i)
+            *reinterpret_cast<u32x4 *>(X + i * piece_stride + fo_offset(b, k, K16)) = out[i];
+    }
 }
 
 hipError_t launch_split_rows(int h16, const double *S, int64_t roff, int64_t rs, int64_t cs, int H, int P, int Kp,
@@ -342,7 +350,7 @@ hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int
     }
     const int K16 = Kp / 16;
     const int RB = (B + kGemmBM - 1) / kGemmBM * (kGemmBM / 32);  // row blocks up to the padded B
-    const dim3 grid((unsigned)(((int64_t)RB * K16 * 64 + 255) / 256));
+    const dim3 grid((unsigned)((int64_t)RB * ((K16 + 4 * kSplitKW - 1) / (4 * kSplitKW))));
     const int *ce = scaled ? colexp : nullptr;
 #define LC_SC(T, NP)                                                                                     \
     if (npc == NP) {                                                                                     \
