@@ -407,7 +407,32 @@ def run_gemm(args):
                          "kernel": "k_mgemm (split-precision MFMA product)" if mode != "fp64" else "rocblas dgemm",
                          "kernel_ms": kms, "flops_per_launch": flops}}
     g.destroy()
+    if mode != "fp64":
+        line["library_gemm_point"] = library_gemm_point(B, P, R, torch.bfloat16 if mode.startswith("bf16")
+                                                        else torch.float16, peak, args.steps)
     return line
+
+
+def library_gemm_point(B, K, R, dtype, peak, steps):
+    """One plain product of the same shape through torch.matmul (the vendor
+    GEMM library), as context for the fraction of the fused split-precision
+    kernel: [B, K] x [K, R] in the 16-bit piece type."""
+    import torch
+    a = torch.randn(B, K, device="cuda", dtype=dtype)
+    b = torch.randn(K, R, device="cuda", dtype=dtype)
+    for _ in range(3):
+        torch.matmul(a, b)
+    _sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        torch.matmul(a, b)
+    e1.record()
+    _sync()
+    ms = e0.elapsed_time(e1) / steps
+    tf = 2.0 * B * K * R / (ms * 1e-3) / 1e12
+    return {"op": f"torch.matmul [{B},{K}] x [{K},{R}] {str(dtype).replace('torch.', '')}",
+            "ms": ms, "achieved_TFLOPs": tf, "frac": tf / peak}
 
 
 def run_tensor2d(args):
