@@ -92,6 +92,25 @@ def cpu_baseline_single_large(budget_s: float = 20.0):
                       f"long-double Gauss-Legendre rule (rule construction included), {dt:.2f} s"}
 
 
+def read_ceiling_gbs(nbytes: int = 4 << 30, reps: int = 10) -> float:
+    """Read bandwidth of torch.sum over nbytes of float64 (GB/s, HIP events)."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        x.sum()
+    _sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        x.sum()
+    e1.record()
+    _sync()
+    ms = e0.elapsed_time(e1) / reps
+    del x
+    torch.cuda.empty_cache()
+    return nbytes / (ms * 1e-3) / 1e9
+
+
 def bench_single(args, N, M, Q, f, name, rule=None):
     import torch
 
@@ -177,6 +196,11 @@ def run_single_large(args):
     p.destroy()
     del fx
     torch.cuda.empty_cache()
+    # a measured read ceiling beside the nominal peak: one plain read-only
+    # stream of the vendor library over 4 GiB
+    rc = read_ceiling_gbs()
+    line["roofline"]["measured_read_ceiling"] = {"op": "torch.sum over 4 GiB of float64", "GBs": rc,
+                                                 "frac_of_measured": achieved / rc}
     # the other rule beside it: the uniform rule at the resolving Q (or the
     # band rule when the uniform one is the main line)
     if not args.skip_stated:
