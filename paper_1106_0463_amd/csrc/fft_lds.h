@@ -73,38 +73,56 @@ template <> struct Dft<8> {
     }
 };
 
+// q = a / d and rem = a % d for 0 <= a < 2^20, d >= 1, from an FP32
+// reciprocal rd = 1/d: the estimate a rd is off by less than one, so one
+// correction step makes both exact (a few instructions instead of a full
+// integer division).
+__device__ __forceinline__ int fdivmod(int a, int d, float rd, int &rem) {
+    int q = (int)((float)a * rd);
+    int r = a - q * d;
+    if (r >= d) { ++q; r -= d; }
+    if (r < 0) { --q; r += d; }
+    rem = r;
+    return q;
+}
+
 // One radix-R Stockham pass over nsub independent transforms of length Lsub
 // stored back to back in LDS (in place: every thread first loads all of its
 // butterflies, then the block synchronizes, then results are stored).
 // Ns is the product of the radices of the previous passes.  Twiddles
 // e^{2 pi i m / Lsub} are read from tw[m * tw_stride], requested with the
 // LDS loads so that their latency passes while the block synchronizes.
-// Requires nsub * Lsub <= EPT * T (checked by the host launchers).
-template <int R, int T, int EPT>
+// ONE: nsub == 1.  Requires nsub * Lsub <= EPT * T (checked by the host
+// launchers) and Lsub * tw_stride < 2^31.
+template <int R, int T, int EPT, bool ONE>
 __device__ __forceinline__ void stockham_pass(double2 *__restrict__ lds, int Lsub, int nsub, int Ns,
-                                              const double2 *__restrict__ tw, int64_t tw_stride) {
+                                              const double2 *__restrict__ tw, int tw_stride) {
     constexpr int MAXB = (EPT + R - 1) / R;
     const int nbs = Lsub / R;
-    const int total = nsub * nbs;
+    const int total = ONE ? nbs : nsub * nbs;
     const int tid = threadIdx.x;
     const int span = Ns * R;
     const int twstep = Lsub / span;
+    const float rnbs = 1.0f / (float)nbs, rns = 1.0f / (float)Ns;
     double2 v[MAXB][R];
     double2 w[MAXB][R - 1];
+    int base[MAXB];  // output index of the butterfly's first value
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * T;
         if (b < total) {
-            const int sub = b / nbs;
-            const int j = b - sub * nbs;
+            int sub = 0, j = b;
+            if constexpr (!ONE) sub = fdivmod(b, nbs, rnbs, j);
             const double2 *x = lds + sub * Lsub;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = x[j + r * nbs];
+            int k;
+            const int q = fdivmod(j, Ns, rns, k);
             if (Ns > 1) {
-                const int k = j % Ns;
 #pragma unroll
-                for (int r = 1; r < R; ++r) w[i][r - 1] = tw[(int64_t)(k * r * twstep) * tw_stride];
+                for (int r = 1; r < R; ++r) w[i][r - 1] = tw[k * r * twstep * tw_stride];
             }
+            base[i] = sub * Lsub + q * span + k;
         }
     }
     __syncthreads();
@@ -112,21 +130,32 @@ __device__ __forceinline__ void stockham_pass(double2 *__restrict__ lds, int Lsu
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * T;
         if (b < total) {
-            const int sub = b / nbs;
-            const int j = b - sub * nbs;
-            const int k = j % Ns;
             if (Ns > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[i][r - 1]);
             }
             Dft<R>::run(v[i]);
-            double2 *y = lds + sub * Lsub;
-            const int base = (j / Ns) * span + k;
 #pragma unroll
-            for (int s = 0; s < R; ++s) y[base + s * Ns] = v[i][s];
+            for (int s = 0; s < R; ++s) lds[base[i] + s * Ns] = v[i][s];
         }
     }
     __syncthreads();
+}
+
+template <int T, int EPT, bool ONE>
+__device__ __forceinline__ void fft_passes(double2 *__restrict__ lds, int Lsub, int nsub, const FftSched &sch,
+                                           const double2 *__restrict__ tw, int tw_stride) {
+    int Ns = 1;
+    for (int p = 0; p < sch.npass; ++p) {
+        const int R = sch.radix[p];
+        switch (R) {
+            case 8: stockham_pass<8, T, EPT, ONE>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
+            case 4: stockham_pass<4, T, EPT, ONE>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
+            case 3: stockham_pass<3, T, EPT, ONE>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
+            default: stockham_pass<2, T, EPT, ONE>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
+        }
+        Ns *= R;
+    }
 }
 
 // Unnormalized positive-exponent FFT of nsub transforms of length Lsub in LDS:
@@ -134,17 +163,8 @@ __device__ __forceinline__ void stockham_pass(double2 *__restrict__ lds, int Lsu
 template <int T, int EPT>
 __device__ void fft_lds(double2 *__restrict__ lds, int Lsub, int nsub, const FftSched &sch,
                         const double2 *__restrict__ tw, int64_t tw_stride) {
-    int Ns = 1;
-    for (int p = 0; p < sch.npass; ++p) {
-        const int R = sch.radix[p];
-        switch (R) {
-            case 8: stockham_pass<8, T, EPT>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
-            case 4: stockham_pass<4, T, EPT>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
-            case 3: stockham_pass<3, T, EPT>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
-            default: stockham_pass<2, T, EPT>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
-        }
-        Ns *= R;
-    }
+    if (nsub == 1) fft_passes<T, EPT, true>(lds, Lsub, 1, sch, tw, (int)tw_stride);
+    else fft_passes<T, EPT, false>(lds, Lsub, nsub, sch, tw, (int)tw_stride);
 }
 
 // DST-III pack.  With phi_m = phi[m-1] for m = 1..H (H = 2L) and
