@@ -462,6 +462,8 @@ extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *
     std::vector<int32_t> grows[kNG];
     int gcap = 3;  // G <= 32 lanes per row, one row per group: measured best on the large band-limited rule
     if (const char *ev = getenv("LC_AQUAD_GMAX")) gcap = std::max(0, std::min(kNG - 1, atoi(ev)));
+    int gmul = 0;  // one row per group: measured best
+    if (const char *ev = getenv("LC_AQUAD_GMUL")) gmul = std::max(0, std::min(4, atoi(ev)));
     group_rows(rlen, gcap, grows);
 
     std::vector<double2> rowA, pre, pack, fft;
@@ -515,6 +517,7 @@ extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *
         chk(aalloc(a, &p->zB, (size_t)L, &ws));
     }
     a->prec = (int)prec;
+    a->gmul = gmul;
     chk(aalloc(a, &a->rows[0], (size_t)H, &ws));   // all groups' row lists, back to back
     chk(aalloc(a, &a->frows[0], (size_t)H, &ws));  // the same for flattened rows
     a->rdesc = std::move(rdesc);

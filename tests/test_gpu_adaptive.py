@@ -197,3 +197,24 @@ def test_many_panels(lc, rule, mixed):
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     banner(f"    vs oracle {err:.2e}")
     assert err <= 1e-13
+
+
+@pytest.mark.parametrize("gmax", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("gmul", [0, 1])
+def test_launch_shapes(lc, monkeypatch, gmax, gmul):
+    # every lane count of the reductions, with one row per lane group and
+    # with a grid stride (a group then walks several rows and reuses its
+    # panel-table slot), on rows of mixed lengths (about 200 to 1000 samples:
+    # each cap up to 64 lanes is used) and 13 to 18 panels (both the flattened
+    # and the panel-by-panel reduction)
+    monkeypatch.setenv("LC_AQUAD_GMAX", str(gmax))
+    monkeypatch.setenv("LC_AQUAD_GMUL", str(gmul))
+    banner(f"[gpu] adaptive launch shape: lane cap {4 << gmax}, grid {'one row per group' if gmul == 0 else 'stride'}")
+    N, M = 300, 2048
+    rule = dict(q=8, band=1024.0, q_max=1024, breaks=(0.0, 0.3, -0.5, 0.7, 0.9), grade_ratio=0.5, grade_levels=12)
+    f = W.AbsPower(1.5)
+    got, info = _run(lc, f, N, M, rule)
+    ref = np.array(oracle.method_coeffs_rule(f, N, M, _orule(rule), fp64_nodes=True), dtype=float)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    banner(f"    vs oracle {err:.2e}")
+    assert err <= 1e-13
