@@ -1,0 +1,126 @@
+"""GPU checks of every launch shape of the uniform Abel reductions.
+
+The autotuner times all supported shapes of the single and batched
+quadrature reductions but only the chosen one reaches a caller.  Here each
+shape is forced through the autotuner's cache file (its last entry for a
+plan wins) and executed: exact-fit variants (weights in registers, rows
+unrolled) and generic variants (any Q), each with a one-block grid (one
+block strides over every row), a few blocks and more blocks than rows.
+Every result must equal the default shape's up to summation order, and the
+single FP64 plan also matches the method oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import banner, expected_grid, rel_err
+
+pytestmark = pytest.mark.gpu
+Q = 48
+GRIDS = (1, 5, 1 << 20)
+FIT_KEYS = {17, 18, 20, 33, 34, 36, 49, 50, 65, 66, 97, 129}  # 16 cpl + unroll of the built variants
+
+
+@pytest.fixture(scope="module")
+def lc():
+    import torch
+    import paper_1106_0463_amd as lc
+    torch.cuda.set_device(0)
+    return lc
+
+
+def shapes(prec: str, q: int):
+    """(vec, G, cpl, unroll) of every reduction the library accepts for q."""
+    out = []
+    vfit = 2 if prec == "fp64" else 4
+    for G in (4, 8, 16):
+        for cpl in (1, 2, 3, 4, 6, 8):
+            for u in (1, 2, 4):
+                if G * cpl * vfit == q and cpl * 16 + u in FIT_KEYS:
+                    out.append((vfit, G, cpl, u))
+    for vec in (1, 2):
+        for G in (4, 8, 16, 32, 64):
+            if q % vec == 0 and (vec == 1 or G >= 16):
+                out.append((vec, G, 0, 1))
+    return out
+
+
+def _last_entry(path, kind):
+    lines = [ln.rstrip("\n") for ln in open(path) if f"|{kind}|" in ln]
+    assert lines, f"no {kind} entry in the cache"
+    key, val = lines[-1].split("\t")
+    return key, val.split()
+
+
+def _force(path, key, tokens):
+    with open(path, "a") as fh:
+        fh.write(key + "\t" + " ".join(str(t) for t in tokens) + "\n")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_single_shapes(lc, tmp_path, monkeypatch, prec):
+    import torch
+    cache = str(tmp_path / "tune.txt")
+    monkeypatch.setenv("LC_AUTOTUNE_CACHE", cache)
+    N, M = 300, 2400  # 460 KB of FP64 samples: past the fused single-workgroup path
+    f = W.Exponential(-2.5)
+    p = lc.plan(N, M, Q, precision=prec)
+    fx = f.torch(p.nodes).contiguous()
+    if prec == "fp32":
+        fx = fx.float().contiguous()
+    ref = p.execute(fx).cpu().numpy()
+    p.autotune()
+    key, tok = _last_entry(cache, "single")
+    assert tok[0] == "quad" and tok[7] == "dst" and tok[-2] == "fused"
+    tok[-1] = "0"  # the reduction kernel, not the fused small path
+    if prec == "fp64":
+        Me = expected_grid(M)
+        want = np.array(oracle.method_coeffs(f, N, Me, Q), dtype=float)
+        assert rel_err(ref, want) <= 1e-12
+    worst = 0.0
+    cases = [(s, g) for s in shapes(prec, Q) for g in GRIDS]
+    banner(f"[gpu] single {prec} Q={Q}: {len(cases)} reduction shapes x grids")
+    for (vec, G, cpl, u), grid in cases:
+        _force(cache, key, ["quad", vec, G, cpl, u, 256, grid] + tok[7:])
+        p.autotune()
+        got = p.execute(fx).cpu().numpy()
+        torch.cuda.synchronize()
+        e = rel_err(got, ref)
+        worst = max(worst, e)
+        assert e <= 1e-13, (vec, G, cpl, u, grid, e)
+    banner(f"    worst difference to the default shape {worst:.2e}")
+    p.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_shapes(lc, tmp_path, monkeypatch, prec):
+    import torch
+    from workloads.gpu import fill_closed_form_arena
+    cache = str(tmp_path / "tune.txt")
+    monkeypatch.setenv("LC_AUTOTUNE_CACHE", cache)
+    Ns = [40, 300, 77, 1000, 5]
+    Ms = [96, 1200, 200, 2400, 10]
+    funcs = [W.Exponential(a) for a in (-1.0, 2.0, -3.5, 0.5, 1.5)]
+    bp = lc.plan_batch(Ns, Ms, [Q] * len(Ns), prec)
+    f_off, x_off, c_off = bp.offsets()
+    H = [expected_grid(m) // 2 for m in Ms]
+    arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
+    fill_closed_form_arena(bp.nodes, arena, x_off, f_off, H, [Q] * len(Ns), funcs, [prec == "fp32"] * len(Ns))
+    ref = bp.execute(arena).cpu().numpy()
+    bp.autotune()
+    key, tok = _last_entry(cache, "batch")
+    assert tok[0] == "1"  # one (Q, precision) class: its six shape numbers follow
+    worst = 0.0
+    cases = [(s, g) for s in shapes(prec, Q) for g in GRIDS]
+    banner(f"[gpu] batch {prec} Q={Q}: {len(cases)} reduction shapes x grids")
+    for (vec, G, cpl, u), grid in cases:
+        _force(cache, key, ["1", vec, G, cpl, u, 256, grid] + tok[7:])
+        bp.autotune()
+        got = bp.execute(arena).cpu().numpy()
+        torch.cuda.synchronize()
+        e = rel_err(got, ref)
+        worst = max(worst, e)
+        assert e <= 1e-13, (vec, G, cpl, u, grid, e)
+    banner(f"    worst difference to the default shape {worst:.2e}")
+    bp.destroy()
