@@ -42,6 +42,7 @@ struct GemmState {
     double *LT = nullptr;  // direct form: Lmat^T [P][N] FP64
     int64_t Hpad = 0, Bpad = 0;  // operand rows padded to the MFMA block tile
     int h16 = kBF16, npc = 1, kmode = 1, scaled = 0;
+    int ks = 0, ns = 0, kch = 0;  // MFMA product shape (0: per-mode defaults)
     int64_t N = 0, M = 0, M_eff = 0, H = 0, L = 0;
     double *xc = nullptr, *lam = nullptr, *A = nullptr;
     void *Y = nullptr;
@@ -156,16 +157,10 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
     GemmState *g = new (std::nothrow) GemmState();
     if (!g) return fail_status(LC_ERR_NOMEM, who + "host allocation failed");
     g->direct = direct;
-    if (const char *kc = getenv("LC_MGEMM_KCH")) {
-        const int k = atoi(kc);
-        mgemm_kch = (k == 2 || k == 4 || k == 8) ? k : 0;
-    }
+    // tuning overrides, fixed for the plan's lifetime
+    if (const char *kc = getenv("LC_MGEMM_KCH")) g->kch = atoi(kc);
     if (const char *st = getenv("LC_MGEMM_STAGES")) {
-        int ks = 0, ns = 0;
-        if (sscanf(st, "%d,%d", &ks, &ns) == 2) {
-            mgemm_ks = ks;
-            mgemm_ns = ns;
-        }
+        if (sscanf(st, "%d,%d", &g->ks, &g->ns) != 2) g->ks = g->ns = -1;
     }
     g->P = P;
     g->Kp = (P + 31) / 32 * 32;
@@ -177,6 +172,10 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
         case LC_GEMM_FP16X3: g->h16 = kF16; g->npc = 2; g->kmode = 3; g->scaled = 1; break;
         case LC_GEMM_FP16X1: g->h16 = kF16; g->npc = 1; g->kmode = 1; g->scaled = 1; break;
         default: g->npc = 0; break;
+    }
+    if (g->kmode && g->npc && !mgemm_shape_supported(g->kmode, g->ks, g->ns, g->kch)) {
+        free_gemm(g);
+        return fail_status(LC_ERR_INVALID, who + "LC_MGEMM_STAGES / LC_MGEMM_KCH name no built product kernel");
     }
     g->N = N;
     g->M = M;
@@ -336,10 +335,11 @@ lc_status lc_execute_gemm(lc_plan_t p, const double *F_dev, int32_t B, double *C
     if ((e = timing_begin(p, stream, &slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
     if (g->direct)
         e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->N, g->Kp, nullptr, (int)g->N,
-                         C_dev, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, stream);
+                         C_dev, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, g->ks, g->ns,
+                         g->kch, stream);
     else
         e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->H, g->Kp, g->Out32,
-                         (int)g->H, nullptr, nullptr, nullptr, stream);
+                         (int)g->H, nullptr, nullptr, nullptr, g->ks, g->ns, g->kch, stream);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: mfma: ") + hipGetErrorString(e));
     if ((e = timing_end(p, stream, slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
     if (g->direct) return LC_OK;

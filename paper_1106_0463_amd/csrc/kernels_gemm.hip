@@ -555,25 +555,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
 // stage depth (k per stage, ring length) of each mode: LDS per block is
 // NS * (NX + NY) * 4 * KS/16 KiB, at most 80 KiB so that two blocks share a CU
-int mgemm_ks = 0, mgemm_ns = 0;  // 0: the per-mode default; LC_MGEMM_STAGES="KS,NS" overrides
-int mgemm_kch = 0;  // FP64-total chunk of the direct form (2, 4 or 8; 0: per mode); LC_MGEMM_KCH overrides
-
-hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
-                        int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
-                        hipStream_t s) {
-    if (Kp % 32) return hipErrorInvalidValue;
-    const int K16 = Kp / 16;
-    int KS = mgemm_ks, NS = mgemm_ns;
-    if (!KS) {
-        KS = mode == 1 ? 32 : 16;
-        NS = mode == 6 ? 3 : 4;
+static void mgemm_defaults(int mode, int h16, bool d64, int &ks, int &ns, int &kch) {
+    if (!ks) {
+        ks = mode == 1 ? 32 : 16;
+        ns = mode == 6 ? 3 : 4;
     }
-    const bool d64 = C64 != nullptr;
     // FP64 chunk length of the direct form: 4 K-steps for fp16x3 and bf16x6
     // (at 8 their E_a reaches 1.0e-7 and 1.25e-7), 8 for bf16x3 and fp16x1,
     // whose 16-bit representation limits them above that anyway
     const bool long_chunks = mode == 1 || (mode == 3 && h16 == kBF16);
-    const int kch = d64 ? (mgemm_kch ? mgemm_kch : (long_chunks ? 8 : 4)) : 8;
+    kch = d64 ? (kch ? kch : (long_chunks ? 8 : 4)) : 8;
+}
+
+bool mgemm_shape_supported(int mode, int ks, int ns, int kch) {
+    if (kch != 0 && kch != 2 && kch != 4 && kch != 8) return false;
+    if (ks == 0 && ns == 0) return true;
+    static const int built[][3] = {{1, 32, 2}, {1, 32, 4}, {1, 16, 4}, {3, 32, 2}, {3, 16, 2},
+                                   {3, 16, 3}, {3, 16, 4}, {6, 16, 2}, {6, 16, 3}};
+    for (auto &b : built)
+        if (b[0] == mode && b[1] == ks && b[2] == ns) return true;
+    return false;
+}
+
+hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
+                        int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp, int ks,
+                        int ns, int kch, hipStream_t s) {
+    if (Kp % 32) return hipErrorInvalidValue;
+    const int K16 = Kp / 16;
+    const bool d64 = C64 != nullptr;
+    int KS = ks, NS = ns;
+    mgemm_defaults(mode, h16, d64, KS, NS, kch);
     const int grid = ((Bn + kGemmBM - 1) / kGemmBM) * ((Hn + 127) / 128);
     const int npx = mode == 1 ? 1 : (mode == 3 ? 2 : 3);
     const size_t lds = (size_t)NS * 2 * npx * 4 * (KS / 16) * 1024;

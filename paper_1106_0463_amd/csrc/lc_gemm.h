@@ -14,11 +14,11 @@ constexpr int kBF16 = 0, kF16 = 1;
 // the fragment-order operands)
 constexpr int kGemmBM = 128;
 
-// k per LDS stage and ring length of the MFMA product (0: per-mode default)
-extern int mgemm_ks, mgemm_ns;
-// K-steps of 16 per FP64 flush of the direct form's accumulators (2, 4 or 8;
-// 0 = per mode)
-extern int mgemm_kch;
+// MFMA product shape of a plan: k per LDS stage and ring length (ks, ns;
+// 0: the per-mode default), and K-steps of 16 per FP64 flush of the direct
+// form's accumulators (kch: 2, 4 or 8; 0: per mode).  True when the library
+// holds a kernel for it.
+bool mgemm_shape_supported(int mode, int ks, int ns, int kch);
 
 hipError_t launch_amat(int H, int P, int QA, const double *xc, const double *lam, const double2 *rowA,
                        const double2 *omt2, const double *wq, const double *s2, double *A, hipStream_t s);
@@ -32,8 +32,8 @@ hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int
 // C64 == nullptr: FP32 sums into Out[Bn][ldo]; otherwise finished FP64
 // values into C64[Bn][ldo] scaled by 2^(rowexp[j] + colexp[b])
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
-                        int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
-                        hipStream_t s);
+                        int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp, int ks,
+                        int ns, int kch, hipStream_t s);
 hipError_t launch_gdst(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,
                        int64_t H, int64_t L, int64_t N, const double2 *tw_pre, const double2 *tw_pack,
                        const double2 *tw_fft, const FftSched &sch, double *C, hipStream_t s);

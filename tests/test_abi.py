@@ -117,3 +117,14 @@ def test_plan_2d_rejects_invalid(args):
 
 def test_execute_2d_rejects_null(lib):
     assert lib.lc_execute_2d(None, None, None, None) == 1
+
+
+@pytest.mark.parametrize("env", [("LC_MGEMM_STAGES", "64,7"), ("LC_MGEMM_STAGES", "16"), ("LC_MGEMM_KCH", "3")])
+def test_gemm_overrides_without_kernel_rejected(monkeypatch, env):
+    # a product shape the library holds no kernel for fails at plan time,
+    # before any device work
+    import paper_1106_0463_amd as lc
+    monkeypatch.setenv(*env)
+    with pytest.raises(lc.LCError) as ei:
+        lc.plan_gemm(512, 1024, 512, "bf16x3")
+    assert ei.value.status == 1

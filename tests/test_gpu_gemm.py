@@ -224,3 +224,40 @@ def test_legendre_matrix_full_size_sampled(lc):
         g.destroy()
         del F, C
         torch.cuda.empty_cache()
+
+
+# every product kernel the library builds: (mode, k per stage, ring length)
+BUILT_SHAPES = [("fp16x1", 32, 2), ("fp16x1", 32, 4), ("fp16x1", 16, 4), ("bf16x3", 32, 2), ("bf16x3", 16, 2),
+                ("bf16x3", 16, 3), ("fp16x3", 16, 4), ("bf16x6", 16, 2), ("bf16x6", 16, 3)]
+BOUND = {"bf16x6": 1e-7, "fp16x3": 1e-7, "bf16x3": 5e-7, "fp16x1": 1e-3}
+
+
+@pytest.mark.parametrize("mode,ks,ns", BUILT_SHAPES)
+def test_product_stage_shapes(lc, monkeypatch, mode, ks, ns):
+    # each stage shape of the MFMA product on ragged sizes (P not a multiple
+    # of 32, B not a multiple of the block tile), Abel and direct forms
+    monkeypatch.setenv("LC_MGEMM_STAGES", f"{ks},{ns}")
+    banner(f"[gpu] gemm {mode} stages k={ks} x {ns}")
+    for run in (_run, _run_direct):
+        C, coef = run(lc, mode, 1000, 1600, 777, 77, 500, seed=9)
+        E_c, E_a = _errors(C, coef, 777)
+        banner(f"    {run.__name__}: E_c {E_c:.2e} E_a {E_a:.2e}")
+        assert E_a <= BOUND[mode]
+
+
+DEFAULT_KCH = {"fp16x3": 4, "bf16x6": 4, "bf16x3": 8, "fp16x1": 8}
+
+
+@pytest.mark.parametrize("kch", [2, 4, 8])
+@pytest.mark.parametrize("mode", ["fp16x3", "bf16x3", "bf16x6", "fp16x1"])
+def test_direct_chunk_lengths(lc, monkeypatch, mode, kch):
+    # every FP64 flush length of the direct form's accumulators computes the
+    # product; chunks longer than a mode's default let the FP32 chain grow
+    # past the mixed class (fp16x3 at 8 reads E_a 1.0e-7 here: the reason its
+    # default is 4), so those are held to twice the class bound
+    monkeypatch.setenv("LC_MGEMM_KCH", str(kch))
+    banner(f"[gpu] legendre matrix {mode} KCH={kch}")
+    C, coef = _run_direct(lc, mode, 1000, 1600, 777, 77, 500, seed=9)
+    E_c, E_a = _errors(C, coef, 777)
+    banner(f"    E_c {E_c:.2e} E_a {E_a:.2e}")
+    assert E_a <= BOUND[mode] * (1 if kch <= DEFAULT_KCH[mode] else 2)
