@@ -62,6 +62,9 @@ struct DstGroup {
     int threads = 0, Lmax = 0, n = 0;
     int32_t *list = nullptr;
     int lstart[kParts + 1] = {};  // list entries of part k (list sorted by part, then length)
+    // short functions packed kMultiSlots list entries per 64-thread block
+    // (blocks of one FFT length each; n and lstart count blocks)
+    bool multi = false;
 };
 
 // tiles are in function order and parts are contiguous function ranges, so
@@ -167,7 +170,10 @@ hipError_t launch_part_dst(BatchState *st, int k, double *c_arena, hipStream_t s
         const int n = g.lstart[k + 1] - g.lstart[k];
         const int w = (s2 && load[1] < load[0]) ? 1 : 0;
         load[w] += cost(i);
-        e = launch_bdst(g.threads, g.Lmax, st->phi_arena, st->dfn, g.list + g.lstart[k], n, c_arena, w ? s2 : s);
+        e = g.multi ? launch_bdst_multi(st->phi_arena, st->dfn, g.list + (int64_t)g.lstart[k] * kMultiSlots, n,
+                                        c_arena, w ? s2 : s)
+                    : launch_bdst(g.threads, g.Lmax, st->phi_arena, st->dfn, g.list + g.lstart[k], n, c_arena,
+                                  w ? s2 : s);
         if (e != hipSuccess) return e;
     }
     return launch_bbig(st->phi_arena, st->dbig, st->ctiles + st->cst[k], st->cst[k + 1] - st->cst[k],
@@ -317,6 +323,10 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         for (auto &g : st->groups) {
             double best = 1e30;
             int bt = g.threads;
+            if (g.multi) {
+                gthreads.push_back(bt);
+                continue;
+            }
             for (int T : {64, 256, 1024}) {
                 if (e != hipSuccess || g.Lmax > 8 * T || prepare_bdst(T, g.Lmax) != hipSuccess) continue;
                 hipError_t er;
@@ -348,6 +358,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         qc.cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>(qc.ntiles, c.grid));
     }
     for (size_t i = 0; i < st->groups.size(); ++i) {
+        if (st->groups[i].multi) continue;  // 64 threads by construction
         if (prepare_bdst(gthreads[i], st->groups[i].Lmax) == hipSuccess) st->groups[i].threads = gthreads[i];
     }
     if (st->gexec) {
@@ -540,12 +551,20 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         chk(upload(st, &qc.tiles, tiles));
         st->classes.push_back(qc);
     }
-    // ---- DST groups (one workgroup per function, longest first)
+    // ---- DST groups (one workgroup per function, longest first; short
+    // functions of equal FFT length packed several per workgroup)
     std::map<int, std::vector<int>> grp;
+    std::map<std::pair<int, int64_t>, std::vector<int>> packed;  // (part, L) -> functions
+    bool pack = true;
+    if (const char *ev = getenv("LC_BATCH_MULTI")) pack = atoi(ev) != 0;
     for (int b = 0; b < B; ++b) {
         const int64_t L = st->fn[b].L;
         if (is_big(L)) {
             st->large.push_back(b);
+            continue;
+        }
+        if (pack && L <= kMultiMaxL) {
+            packed[{st->part_of[b], L}].push_back(b);
             continue;
         }
         // group by power-of-two length class so that the LDS reserved per
@@ -624,6 +643,38 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         std::vector<int32_t> list(v.begin(), v.end());
         chk(upload(st, &g.list, list));
         chk(prepare_bdst(g.threads, g.Lmax));
+        st->groups.push_back(g);
+    }
+    if (!packed.empty()) {
+        // blocks of multi_slots(L) functions of one length, by part, longest
+        // lengths first within a part
+        DstGroup g;
+        g.multi = true;
+        g.threads = 64;
+        g.Lmax = kMultiMaxL;
+        std::vector<int32_t> list;
+        int k = 0;
+        g.lstart[0] = 0;
+        for (auto it = packed.begin(); it != packed.end();) {
+            const int part = it->first.first;
+            while (k < part) g.lstart[++k] = (int)(list.size() / kMultiSlots);
+            auto end = it;
+            while (end != packed.end() && end->first.first == part) ++end;
+            std::vector<std::pair<int64_t, const std::vector<int> *>> byL;
+            for (auto jt = it; jt != end; ++jt) byL.push_back({jt->first.second, &jt->second});
+            std::sort(byL.begin(), byL.end(), [](auto &a, auto &b) { return a.first > b.first; });
+            for (auto &pl : byL) {
+                const int slots = multi_slots((int)pl.first);
+                const std::vector<int> &fs = *pl.second;
+                for (size_t i = 0; i < fs.size(); i += slots)
+                    for (int u = 0; u < kMultiSlots; ++u)
+                        list.push_back(u < slots && i + u < fs.size() ? fs[i + u] : -1);
+            }
+            it = end;
+        }
+        while (k < st->nparts) g.lstart[++k] = (int)(list.size() / kMultiSlots);
+        g.n = (int)(list.size() / kMultiSlots);
+        chk(upload(st, &g.list, list));
         st->groups.push_back(g);
     }
     if (e != hipSuccess) {

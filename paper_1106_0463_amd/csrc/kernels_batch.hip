@@ -247,6 +247,72 @@ hipError_t launch_bdst(int threads, int Lmax, const double *phi_arena, const Bat
     return hipGetLastError();
 }
 
+// Short functions of one FFT length L, up to kMultiSlots per 64-thread
+// workgroup (slot u of block b is list[b kMultiSlots + u], -1 when empty):
+// they share H, twiddles and radix schedule, so their FFTs are nsub
+// transforms of one LDS pass sequence.  The slots' phi offset, coefficient
+// offset and N are staged in LDS first; an empty slot transforms the first
+// slot's phi again and is not unpacked.
+__global__ __launch_bounds__(64) void k_bdst_multi(const double *__restrict__ phi_arena,
+                                                   const BatchFn *__restrict__ fns,
+                                                   const int32_t *__restrict__ list,
+                                                   double *__restrict__ c_arena) {
+    constexpr int T = 64;
+    extern __shared__ double2 lds[];
+    __shared__ int64_t sphi[kMultiSlots], scoff[kMultiSlots];
+    __shared__ int sn[kMultiSlots];
+    const int32_t *mine = list + (int64_t)blockIdx.x * kMultiSlots;
+    const BatchFn &f0 = fns[mine[0]];
+    const int64_t H = f0.H;
+    const int L = (int)f0.L;
+    const int fpb = multi_slots(L);
+    if ((int)threadIdx.x < fpb) {
+        const int32_t fi = mine[threadIdx.x];
+        const BatchFn &f = fns[fi < 0 ? mine[0] : fi];
+        sphi[threadIdx.x] = f.phi_off;
+        scoff[threadIdx.x] = f.c_off;
+        sn[threadIdx.x] = fi < 0 ? 0 : (int)f.N;
+    }
+    __syncthreads();
+    const int tot = fpb * L;
+    const float rL = 1.0f / (float)L;
+    struct Phi {
+        const double *p;
+        __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
+    };
+#pragma unroll 1
+    for (int e0 = 0; e0 < tot; e0 += 4 * T) {  // four values' reads in flight per thread
+        double2 z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int k;
+            const int sl = fdivmod(min(e0 + (int)threadIdx.x + u * T, tot - 1), L, rL, k);
+            z[u] = dst_pack(k, Phi{phi_arena + sphi[sl]}, H, L, f0.tw_pre, f0.tw_pack);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + (int)threadIdx.x + u * T < tot) lds[e0 + threadIdx.x + u * T] = z[u];
+    }
+    __syncthreads();
+    fft_passes<T, 8, false>(lds, L, fpb, f0.sched, f0.tw_fft, 1);  // fpb >= 2
+    const int tot2 = fpb * (int)H;  // N <= H per slot
+    const float rH = 1.0f / (float)H;
+#pragma unroll 1
+    for (int e = threadIdx.x; e < tot2; e += T) {
+        int n;
+        const int sl = fdivmod(e, (int)H, rH, n);
+        if (n < sn[sl]) c_arena[scoff[sl] + n] = dst_post(n, lds + sl * L, H);
+    }
+}
+
+hipError_t launch_bdst_multi(const double *phi_arena, const BatchFn *fns, const int32_t *list, int nblocks,
+                             double *c_arena, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bdst_multi, dim3(nblocks), dim3(64), (size_t)8 * 64 * sizeof(double2), s, phi_arena, fns,
+                       list, c_arena);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------- batched four-step ---
 // The same three passes as the single-function four-step FFT, for every
 // long function of a batch in one launch each: block t works on function

@@ -214,6 +214,17 @@ hipError_t launch_bquad(const QuadCfg &cfg, int prec, const void *f_arena, const
 hipError_t launch_bdst(int threads, int Lmax, const double *phi_arena, const BatchFn *fns,
                        const int32_t *list, int nlist, double *c_arena, hipStream_t s);
 hipError_t prepare_bdst(int threads, int Lmax);
+// Short functions packed per 64-thread workgroup: kMultiSlots list entries
+// per block (-1 = empty), all of one FFT length L <= kMultiMaxL, of which the
+// first multi_slots(L) are used.
+constexpr int kMultiSlots = 32;
+constexpr int kMultiMaxL = 256;  // at least 2 functions per workgroup
+__host__ __device__ inline int multi_slots(int L) {
+    const int n = 512 / L;
+    return n < kMultiSlots ? n : kMultiSlots;
+}
+hipError_t launch_bdst_multi(const double *phi_arena, const BatchFn *fns, const int32_t *list, int nblocks,
+                             double *c_arena, hipStream_t s);
 hipError_t launch_bbig(const double *phi_arena, const BigFn *fns, const BigTile *ctiles, int nct,
                        const BigTile *rtiles, int nrt, const BigTile *ptiles, int npt, double *c_arena,
                        hipStream_t s);

@@ -187,3 +187,33 @@ def test_uneven_series_full_batch_stated_q(lc):
         err = rel_err(got, ref)
         banner(f"    fn {b} N={n}: rel err {err:.2e}; vs truth {rel_err(got, sb.coeffs[b]):.2e}")
         assert err <= TOL
+
+
+@pytest.mark.parametrize("parts", [1, 2])
+def test_short_functions_packed(lc, monkeypatch, parts):
+    # many short functions: those of equal FFT length (L <= 256) share
+    # workgroups, up to 32 per workgroup; full and partly filled workgroups,
+    # every length from 1 to 216 packed, across pipeline parts
+    import torch
+    monkeypatch.setenv("LC_BATCH_PARTS", str(parts))
+    rng = np.random.default_rng(11)
+    Ns = [int(n) for n in rng.choice([1, 2, 5, 16, 30, 31, 64, 100, 128, 200], size=150)]
+    M = [4 * n for n in Ns]
+    fams = [W.GeneratingFunction(0.3), W.Exponential(-1.5), W.Cosine(3.0)]
+    funcs = [fams[b % 3] for b in range(len(Ns))]
+    prec = ["fp64" if b % 4 else "fp32" for b in range(len(Ns))]
+    Q = [24] * len(Ns)
+    banner(f"[gpu] {len(Ns)} short functions, {parts} part(s)")
+    bp, arena, c_off = _build(lc, funcs, Ns, M, Q, prec)
+    c = bp.execute(arena)
+    torch.cuda.synchronize()
+    c = c.cpu().numpy()
+    for b, (f, n, m, pr) in enumerate(zip(funcs, Ns, M, prec)):
+        got = c[c_off[b]:c_off[b + 1]]
+        ref = np.array(oracle.method_coeffs(f, n, expected_grid(m), 24), dtype=float)
+        if pr == "fp64":
+            assert rel_err(got, ref) <= TOL, b
+        else:
+            k = 2 * np.arange(n) + 1
+            assert rel_err(got / k, ref / k) <= 1e-7, b
+    bp.destroy()
