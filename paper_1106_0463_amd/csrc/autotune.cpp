@@ -111,6 +111,18 @@ std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu, bool
                 c.Qv = Q;
                 add(c);
             }
+    for (int G : {8, 16, 32, 64})
+        for (int u : {1, 2, 4, 8}) {
+            QuadCfg c{};
+            c.vec = vfit;
+            c.G = G;
+            c.cpl = -1;
+            c.unroll = u;
+            c.block = 256;
+            c.grid = 1;
+            c.Qv = Q;
+            add(c);
+        }
     for (int vec : {1, 2})
         for (int G : {4, 8, 16, 32, 64}) {
             QuadCfg c{};

@@ -78,6 +78,61 @@ __global__ __launch_bounds__(256) void k_bquad_fit(const unsigned char *__restri
     }
 }
 
+// One 16-byte chunk per lane for short rows (G/2 < Q/VEC <= G, lanes past
+// Q/VEC idle): the 64/G rows of a load instruction are adjacent, so it reads
+// whole cache lines where the exact-fit shape would read halves of them.
+template <typename T, int VEC, int G, int U>
+__global__ __launch_bounds__(256) void k_bquad_one(const unsigned char *__restrict__ f_arena,
+                                                   const double *__restrict__ w, int Q,
+                                                   const BatchTile *__restrict__ tiles, int ntiles,
+                                                   double *__restrict__ phi_arena) {
+    using V = typename VecOf<T, VEC>::type;
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int rg = lane / G;
+    const int wv = threadIdx.x >> 6;
+    const bool act = g < Q / VEC;
+    double wr[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) wr[e] = act ? w[g * VEC + e] : 0.0;
+
+    BatchTile nx{};
+    if ((int)blockIdx.x < ntiles) nx = tiles[blockIdx.x];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile tl = nx;
+        const T *f = reinterpret_cast<const T *>(f_arena + tl.f_off);
+        double *phi = phi_arena + tl.phi_off;
+        const int rend = tl.nrows;
+        const int r0 = wv * (RPW * U);
+        V val[U];
+        double s2v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int row = r0 + u * RPW + rg;
+            val[u] = (V)(T)0;
+            s2v[u] = 0.0;
+            if (row < rend) {
+                if (act) val[u] = ld_stream(reinterpret_cast<const V *>(f + (int64_t)row * Q) + g);
+                s2v[u] = ld_global(tl.s2 + row);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + (int)gridDim.x < ntiles) nx = tiles[t + gridDim.x];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double d[VEC];
+            to_d(val[u], d);
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc = fma(wr[e], d[e], acc);
+            acc = group_sum<G>(acc);
+            const int row = r0 + u * RPW + rg;
+            if (g == 0 && row < rend) phi[row] = s2v[u] * acc;
+        }
+    }
+}
+
 template <typename T, int VEC, int G>
 __global__ __launch_bounds__(256) void k_bquad_gen(const unsigned char *__restrict__ f_arena,
                                                    const double *__restrict__ w, int Q,
@@ -117,6 +172,17 @@ static hipError_t bfit(const QuadCfg &c, const void *f, const double *w, const B
                                                             c.block, 0);
     hipLaunchKernelGGL((k_bquad_fit<T, VEC, G, CPL, U>), dim3(c.grid), dim3(c.block), 0, s,
                        (const unsigned char *)f, w, tiles, ntiles, phi);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC, int G, int U>
+static hipError_t bone(const QuadCfg &c, const void *f, const double *w, int Q, const BatchTile *tiles,
+                       int ntiles, double *phi, hipStream_t s) {
+    if (g_bocc)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_bocc, (const void *)k_bquad_one<T, VEC, G, U>,
+                                                            c.block, 0);
+    hipLaunchKernelGGL((k_bquad_one<T, VEC, G, U>), dim3(c.grid), dim3(c.block), 0, s,
+                       (const unsigned char *)f, w, Q, tiles, ntiles, phi);
     return hipGetLastError();
 }
 
@@ -161,6 +227,29 @@ static hipError_t bdispatch(const QuadCfg &c, const void *f, const double *w, in
             LC_BFIT_CASES(T, 4, 4)
             LC_BFIT_CASES(T, 4, 8)
             LC_BFIT_CASES(T, 4, 16)
+        }
+        return hipErrorInvalidValue;
+    }
+    if (c.cpl < 0) {
+        constexpr int V = 16 / sizeof(T);
+        switch (c.G * 16 + c.unroll) {
+            case 8 * 16 + 1: return bone<T, V, 8, 1>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 8 * 16 + 2: return bone<T, V, 8, 2>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 8 * 16 + 4: return bone<T, V, 8, 4>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 8 * 16 + 8: return bone<T, V, 8, 8>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 16 * 16 + 1: return bone<T, V, 16, 1>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 16 * 16 + 2: return bone<T, V, 16, 2>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 16 * 16 + 4: return bone<T, V, 16, 4>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 16 * 16 + 8: return bone<T, V, 16, 8>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 32 * 16 + 1: return bone<T, V, 32, 1>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 32 * 16 + 2: return bone<T, V, 32, 2>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 32 * 16 + 4: return bone<T, V, 32, 4>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 32 * 16 + 8: return bone<T, V, 32, 8>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 64 * 16 + 1: return bone<T, V, 64, 1>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 64 * 16 + 2: return bone<T, V, 64, 2>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 64 * 16 + 4: return bone<T, V, 64, 4>(c, f, w, Q, tiles, ntiles, phi, s);
+            case 64 * 16 + 8: return bone<T, V, 64, 8>(c, f, w, Q, tiles, ntiles, phi, s);
+            default: break;
         }
         return hipErrorInvalidValue;
     }

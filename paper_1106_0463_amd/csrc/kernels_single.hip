@@ -127,6 +127,55 @@ __global__ __launch_bounds__(256) void k_quad_fit(const T *__restrict__ f, const
     }
 }
 
+// One-chunk variant for short rows of NCH = Q/VEC chunks, G/2 < NCH <= G:
+// lane g < NCH reads chunk g, the other lanes idle.  The 64/G rows of one
+// load instruction are adjacent in memory, so it reads whole cache lines
+// even where a row is not a multiple of 128 bytes (FP32, Q = 48: four
+// 192-byte rows per instruction, where the exact-fit shape has 4 lanes read
+// 64-byte halves of lines).
+template <typename T, int VEC, int G, int U>
+__global__ __launch_bounds__(256) void k_quad_one(const T *__restrict__ f, const double *__restrict__ w,
+                                                  const double *__restrict__ s2, int64_t rows, int Q,
+                                                  double *__restrict__ phi) {
+    using V = typename VecOf<T, VEC>::type;
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int rg = lane / G;
+    const bool act = g < Q / VEC;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    double wr[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) wr[e] = act ? w[g * VEC + e] : 0.0;
+
+    for (int64_t r0 = wave * (RPW * U); r0 < rows; r0 += nwaves * (RPW * U)) {
+        V val[U];
+        double s2v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = r0 + u * RPW + rg;
+            val[u] = (V)(T)0;
+            s2v[u] = 0.0;
+            if (row < rows) {
+                if (act) val[u] = ld_stream(reinterpret_cast<const V *>(f + row * Q) + g);
+                s2v[u] = s2[row];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double d[VEC];
+            to_d(val[u], d);
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc = fma(wr[e], d[e], acc);
+            acc = group_sum<G>(acc);
+            const int64_t row = r0 + u * RPW + rg;
+            if (g == 0 && row < rows) phi[row] = s2v[u] * acc;
+        }
+    }
+}
+
 // Generic variant for any Q (row_partial in quad_device.h).
 template <typename T, int VEC, int G>
 __global__ __launch_bounds__(256) void k_quad_gen(const T *__restrict__ f, const double *__restrict__ w,
@@ -161,6 +210,16 @@ static hipError_t go_fit(const QuadCfg &c, const void *f, const double *w, const
                                                             c.block, 0);
     hipLaunchKernelGGL((k_quad_fit<T, VEC, G, CPL, U>), dim3(c.grid), dim3(c.block), 0, s,
                        (const T *)f, w, s2, rows, phi);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC, int G, int U>
+static hipError_t go_one(const QuadCfg &c, const void *f, const double *w, const double *s2, int64_t rows,
+                         int Q, double *phi, hipStream_t s) {
+    if (g_occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_occ, (const void *)k_quad_one<T, VEC, G, U>,
+                                                                    c.block, 0);
+    hipLaunchKernelGGL((k_quad_one<T, VEC, G, U>), dim3(c.grid), dim3(c.block), 0, s, (const T *)f, w, s2,
+                       rows, Q, phi);
     return hipGetLastError();
 }
 
@@ -209,6 +268,29 @@ static hipError_t dispatch_quad(const QuadCfg &c, const void *f, const double *w
         }
         return hipErrorInvalidValue;
     }
+    if (c.cpl < 0) {
+        constexpr int V = 16 / sizeof(T);
+        switch (c.G * 16 + c.unroll) {
+            case 8 * 16 + 1: return go_one<T, V, 8, 1>(c, f, w, s2, rows, Q, phi, s);
+            case 8 * 16 + 2: return go_one<T, V, 8, 2>(c, f, w, s2, rows, Q, phi, s);
+            case 8 * 16 + 4: return go_one<T, V, 8, 4>(c, f, w, s2, rows, Q, phi, s);
+            case 8 * 16 + 8: return go_one<T, V, 8, 8>(c, f, w, s2, rows, Q, phi, s);
+            case 16 * 16 + 1: return go_one<T, V, 16, 1>(c, f, w, s2, rows, Q, phi, s);
+            case 16 * 16 + 2: return go_one<T, V, 16, 2>(c, f, w, s2, rows, Q, phi, s);
+            case 16 * 16 + 4: return go_one<T, V, 16, 4>(c, f, w, s2, rows, Q, phi, s);
+            case 16 * 16 + 8: return go_one<T, V, 16, 8>(c, f, w, s2, rows, Q, phi, s);
+            case 32 * 16 + 1: return go_one<T, V, 32, 1>(c, f, w, s2, rows, Q, phi, s);
+            case 32 * 16 + 2: return go_one<T, V, 32, 2>(c, f, w, s2, rows, Q, phi, s);
+            case 32 * 16 + 4: return go_one<T, V, 32, 4>(c, f, w, s2, rows, Q, phi, s);
+            case 32 * 16 + 8: return go_one<T, V, 32, 8>(c, f, w, s2, rows, Q, phi, s);
+            case 64 * 16 + 1: return go_one<T, V, 64, 1>(c, f, w, s2, rows, Q, phi, s);
+            case 64 * 16 + 2: return go_one<T, V, 64, 2>(c, f, w, s2, rows, Q, phi, s);
+            case 64 * 16 + 4: return go_one<T, V, 64, 4>(c, f, w, s2, rows, Q, phi, s);
+            case 64 * 16 + 8: return go_one<T, V, 64, 8>(c, f, w, s2, rows, Q, phi, s);
+            default: break;
+        }
+        return hipErrorInvalidValue;
+    }
     switch (c.vec * 1000 + c.G) {
         case 1004: return go_gen<T, 1, 4>(c, f, w, s2, rows, Q, phi, s);
         case 1008: return go_gen<T, 1, 8>(c, f, w, s2, rows, Q, phi, s);
@@ -235,7 +317,7 @@ int quad_blocks_per_cu(const QuadCfg &cfg, int prec) {
     return (e == hipSuccess && n > 0) ? n : 0;
 }
 
-int quad_rows_per_block(const QuadCfg &c) { return (c.block / 64) * (64 / c.G) * (c.cpl > 0 ? c.unroll : 1); }
+int quad_rows_per_block(const QuadCfg &c) { return (c.block / 64) * (64 / c.G) * (c.cpl != 0 ? c.unroll : 1); }
 
 bool quad_cfg_supported(const QuadCfg &c, int prec, int Q) {
     const int esz = prec == LC_FP64 ? 8 : 4;
@@ -251,6 +333,13 @@ bool quad_cfg_supported(const QuadCfg &c, int prec, int Q) {
         for (int k : ok)
             if (k == key) return true;
         return false;
+    }
+    if (c.cpl < 0) {  // one chunk per lane: G/2 < Q/vec <= G
+        const int nch = Q / c.vec;
+        if (c.cpl != -1 || c.vec != 16 / esz) return false;
+        if (!(c.G == 8 || c.G == 16 || c.G == 32 || c.G == 64)) return false;
+        if (!(c.unroll == 1 || c.unroll == 2 || c.unroll == 4 || c.unroll == 8)) return false;
+        return 2 * nch > c.G && nch <= c.G;
     }
     if (c.vec == 1) return c.G == 4 || c.G == 8 || c.G == 16 || c.G == 32 || c.G == 64;
     if (c.vec == 2) return c.G == 16 || c.G == 32 || c.G == 64;

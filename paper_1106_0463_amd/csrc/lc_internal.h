@@ -29,7 +29,8 @@ struct FftSched {
 struct QuadCfg {
     int vec;        // elements per lane load (16 B loads where the row allows)
     int G;          // lanes per row (power of two, <= 64)
-    int cpl;        // chunks per lane (0: generic loop with bounds checks)
+    int cpl;        // chunks per lane (0: generic loop with bounds checks; -1: one
+                    // 16-byte chunk per lane, lanes past Q/vec idle)
     int unroll;     // rows per row-group per iteration
     int block;      // threads per block
     int grid;       // blocks

@@ -38,10 +38,29 @@ __device__ __forceinline__ double ld_global(const double *p) {
     return *(const __attribute__((address_space(1))) double *)p;
 }
 
+// Lane i takes lane i + K of its 16-lane row (0 past the row's end): a DPP
+// row shift, so a VALU move rather than a trip through the LDS crossbar.
+template <int K>
+__device__ __forceinline__ double row_shl(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x100 + K, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x100 + K, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Total of each aligned group of G lanes, valid in the group's first lane
+// (the others hold partial sums).  The offsets halve from G/2 down, so that
+// lane sums the fixed pairwise tree of an xor butterfly; the steps inside a
+// 16-lane row are DPP shifts, the steps across rows lane shuffles.  Every
+// lane of a group must be active (groups never straddle divergent rows).
 template <int G>
 __device__ __forceinline__ double group_sum(double acc) {
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if constexpr (G >= 64) acc += __shfl_down(acc, 32, 64);
+    if constexpr (G >= 32) acc += __shfl_down(acc, 16, 64);
+    if constexpr (G >= 16) acc += row_shl<8>(acc);
+    if constexpr (G >= 8) acc += row_shl<4>(acc);
+    if constexpr (G >= 4) acc += row_shl<2>(acc);
+    if constexpr (G >= 2) acc += row_shl<1>(acc);
     return acc;
 }
 

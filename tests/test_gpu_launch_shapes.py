@@ -4,7 +4,8 @@ The autotuner times all supported shapes of the single and batched
 quadrature reductions but only the chosen one reaches a caller.  Here each
 shape is forced through the autotuner's cache file (its last entry for a
 plan wins) and executed: exact-fit variants (weights in registers, rows
-unrolled) and generic variants (any Q), each with a one-block grid (one
+unrolled), one-chunk-per-lane variants (rows shorter than a lane group, the
+spare lanes idle) and generic variants (any Q), each with a one-block grid (one
 block strides over every row), a few blocks and more blocks than rows.
 Every result must equal the default shape's up to summation order, and the
 single FP64 plan also matches the method oracle.
@@ -17,7 +18,7 @@ import workloads as W
 from helpers import banner, expected_grid, rel_err
 
 pytestmark = pytest.mark.gpu
-Q = 48
+QS = (48, 20)  # 20: rows of 5 (FP32) or 10 (FP64) 16-byte chunks
 GRIDS = (1, 5, 1 << 20)
 FIT_KEYS = {17, 18, 20, 33, 34, 36, 49, 50, 65, 66, 97, 129}  # 16 cpl + unroll of the built variants
 
@@ -39,6 +40,10 @@ def shapes(prec: str, q: int):
             for u in (1, 2, 4):
                 if G * cpl * vfit == q and cpl * 16 + u in FIT_KEYS:
                     out.append((vfit, G, cpl, u))
+    nch = q // vfit  # one 16-byte chunk per lane, lanes past nch idle
+    for G in (8, 16, 32, 64):
+        if q % vfit == 0 and G < 2 * nch <= 2 * G:
+            out.extend((vfit, G, -1, u) for u in (1, 2, 4, 8))
     for vec in (1, 2):
         for G in (4, 8, 16, 32, 64):
             if q % vec == 0 and (vec == 1 or G >= 16):
@@ -58,8 +63,9 @@ def _force(path, key, tokens):
         fh.write(key + "\t" + " ".join(str(t) for t in tokens) + "\n")
 
 
+@pytest.mark.parametrize("Q", QS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_single_shapes(lc, tmp_path, monkeypatch, prec):
+def test_single_shapes(lc, tmp_path, monkeypatch, prec, Q):
     import torch
     cache = str(tmp_path / "tune.txt")
     monkeypatch.setenv("LC_AUTOTUNE_CACHE", cache)
@@ -93,8 +99,9 @@ def test_single_shapes(lc, tmp_path, monkeypatch, prec):
     p.destroy()
 
 
+@pytest.mark.parametrize("Q", QS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_shapes(lc, tmp_path, monkeypatch, prec):
+def test_batch_shapes(lc, tmp_path, monkeypatch, prec, Q):
     import torch
     from workloads.gpu import fill_closed_form_arena
     cache = str(tmp_path / "tune.txt")
