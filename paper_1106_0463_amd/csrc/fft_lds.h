@@ -167,6 +167,72 @@ __device__ void fft_lds(double2 *__restrict__ lds, int Lsub, int nsub, const Fft
     else fft_passes<T, EPT, false>(lds, Lsub, nsub, sch, tw, (int)tw_stride);
 }
 
+// One transform of power-of-two length LS whose pass stride NS is a
+// compile-time constant: the butterfly's quotient and remainder by NS and
+// its twiddle offsets are shifts, masks and constants, where the run-time
+// pass divides.  Same butterflies, twiddles and order as stockham_pass.
+template <int R, int T, int LS, int NS>
+__device__ __forceinline__ void stockham_fixed(double2 *__restrict__ lds, const double2 *__restrict__ tw) {
+    constexpr int nbs = LS / R, span = NS * R, twstep = LS / span;
+    constexpr int MAXB = (nbs + T - 1) / T;
+    const int tid = threadIdx.x;
+    double2 v[MAXB][R];
+    double2 w[MAXB][R > 1 ? R - 1 : 1];
+    int base[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * T;
+        if (nbs % T == 0 || b < nbs) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = lds[b + r * nbs];
+            const int k = b % NS, q = b / NS;
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[i][r - 1] = tw[k * r * twstep];
+            }
+            base[i] = q * span + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * T;
+        if (nbs % T == 0 || b < nbs) {
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[i][r - 1]);
+            }
+            Dft<R>::run(v[i]);
+#pragma unroll
+            for (int s = 0; s < R; ++s) lds[base[i] + s * NS] = v[i][s];
+        }
+    }
+    __syncthreads();
+}
+
+// Radix-8 passes, then one radix-4 or radix-2 pass for what is left.
+template <int T, int LS, int NS>
+__device__ __forceinline__ void fixed_passes(double2 *__restrict__ lds, const double2 *__restrict__ tw) {
+    if constexpr (NS < LS) {
+        constexpr int rest = LS / NS;
+        constexpr int R = rest % 8 == 0 ? 8 : (rest % 4 == 0 ? 4 : 2);
+        stockham_fixed<R, T, LS, NS>(lds, tw);
+        fixed_passes<T, LS, NS * R>(lds, tw);
+    }
+}
+
+// One transform of length L <= EPT T in LDS (as fft_lds with nsub = 1):
+// the power-of-two lengths 2T, 4T and 8T take compile-time passes, every
+// other length the run-time schedule.
+template <int T, int EPT>
+__device__ void fft_lds_one(double2 *__restrict__ lds, int L, const FftSched &sch, const double2 *__restrict__ tw) {
+    static_assert(EPT == 8, "compile-time lengths assume 8 values per thread");
+    if (L == 8 * T) fixed_passes<T, 8 * T, 1>(lds, tw);
+    else if (L == 4 * T) fixed_passes<T, 4 * T, 1>(lds, tw);
+    else if (L == 2 * T) fixed_passes<T, 2 * T, 1>(lds, tw);
+    else fft_passes<T, EPT, true>(lds, L, 1, sch, tw, 1);
+}
+
 // DST-III pack.  With phi_m = phi[m-1] for m = 1..H (H = 2L) and
 //   V_k = e^{i pi k / (2H)} (phi_{H-k} - i phi_k)   (1 <= k < H),  V_0 = phi_H,
 //   Z_k = (V_k + V_{k+L}) + i e^{2 pi i k / H} (V_k - V_{k+L}),  0 <= k < L,

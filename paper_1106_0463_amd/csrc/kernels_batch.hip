@@ -301,7 +301,7 @@ __global__ __launch_bounds__(T) void k_bdst_lds(const double *__restrict__ phi_a
     } ph{phi_arena + fn.phi_off};
     dst_pack_lds<T, 8>(lds, ph, H, L, fn.tw_pre, fn.tw_pack);
     __syncthreads();
-    fft_lds<T, 8>(lds, L, 1, sch, fn.tw_fft, 1);
+    fft_lds_one<T, 8>(lds, L, sch, fn.tw_fft);
     double *c = c_arena + fn.c_off;
     for (int64_t n = threadIdx.x; n < fn.N; n += T) c[n] = dst_post(n, lds, H);
 }

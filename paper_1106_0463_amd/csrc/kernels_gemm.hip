@@ -644,7 +644,7 @@ __global__ __launch_bounds__(T) void k_gdst_lds(const PhiT *__restrict__ Out, in
     } ph{row, rowexp, ce};
     dst_pack_lds<T, 8>(lds, ph, H, L, tw_pre, tw_pack);
     __syncthreads();
-    fft_lds<T, 8>(lds, L, 1, sch, tw_fft, 1);
+    fft_lds_one<T, 8>(lds, L, sch, tw_fft);
     double *c = C + (int64_t)b * N;
     for (int64_t n = threadIdx.x; n < N; n += T) c[n] = dst_post(n, lds, H);
 }

@@ -375,7 +375,7 @@ __global__ __launch_bounds__(T) void k_dst_lds(const double *__restrict__ phi, i
     GlobalPhi ph{phi};
     dst_pack_lds<T, 8>(lds, ph, H, L, tw_pre, tw_pack);
     __syncthreads();
-    fft_lds<T, 8>(lds, L, 1, sch, tw_fft, 1);
+    fft_lds_one<T, 8>(lds, L, sch, tw_fft);
     for (int64_t n = threadIdx.x; n < N; n += T) c[n] = dst_post(n, lds, H);
 }
 
