@@ -41,8 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel from the two rocprofv3 counter passes
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from the 4 GiB copy calibration),
 # with the kernel they were taken on
-TRAFFIC = {"single_large_band": (4.9571e9, "k_aflat<double>"),
-           "batch_fp64": (7.8004e9, "k_bquad_fit<double, 2, 8, 3, 2>")}
+TRAFFIC = {"single_large_band": (4.9571e9, "k_aflat<double>")}
 METRIC = "Legendre coeffs/sec at 1 GPU (FP64 ≤1e-12 vs split-BF16 ≤1e-7 rel.)"
 Q_RESOLVING = 8384
 
@@ -336,7 +335,7 @@ def run_batch(args):
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_series(sb, np.random.default_rng(3).choice(4096, 64, replace=False))
     line = _batch_common(args, bp, arena, int(sb.N.sum()), alg, cfg, cpu)
-    if prec == "fp64":
+    if prec == "fp64" and "batch_fp64" in TRAFFIC:
         line["roofline"]["traffic"], line["roofline"]["traffic_kernel"] = TRAFFIC["batch_fp64"]
     bp.destroy()
     return line

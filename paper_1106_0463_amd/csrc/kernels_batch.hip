@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_bquad_fit(const unsigned char *__restri
             }
             acc = group_sum<G>(acc);
             const int row = r0 + u * RPW + rg;
-            if (g == 0 && row < rend) phi[row] = s2v[u] * acc;
+            if (g == 0 && row < rend) st_stream(phi + row, s2v[u] * acc);
         }
     }
 }
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_bquad_one(const unsigned char *__restri
             for (int e = 0; e < VEC; ++e) acc = fma(wr[e], d[e], acc);
             acc = group_sum<G>(acc);
             const int row = r0 + u * RPW + rg;
-            if (g == 0 && row < rend) phi[row] = s2v[u] * acc;
+            if (g == 0 && row < rend) st_stream(phi + row, s2v[u] * acc);
         }
     }
 }
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_bquad_gen(const unsigned char *__restri
         double acc = 0.0;
         if (row < tl.nrows) acc = row_partial<T, VEC, G>(f + (int64_t)row * Q, w, NC, g);
         acc = group_sum<G>(acc);
-        if (g == 0 && row < tl.nrows) phi_arena[tl.phi_off + row] = s2v * acc;
+        if (g == 0 && row < tl.nrows) st_stream(phi_arena + tl.phi_off + row, s2v * acc);
     }
 }
 

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_quad_fit(const T *__restrict__ f, const
             }
             acc = group_sum<G>(acc);
             const int64_t row = r0 + u * RPW + rg;
-            if (g == 0 && row < rows) phi[row] = s2v[u] * acc;
+            if (g == 0 && row < rows) st_stream(phi + row, s2v[u] * acc);
         }
     }
 }
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_quad_one(const T *__restrict__ f, const
             for (int e = 0; e < VEC; ++e) acc = fma(wr[e], d[e], acc);
             acc = group_sum<G>(acc);
             const int64_t row = r0 + u * RPW + rg;
-            if (g == 0 && row < rows) phi[row] = s2v[u] * acc;
+            if (g == 0 && row < rows) st_stream(phi + row, s2v[u] * acc);
         }
     }
 }
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k_quad_gen(const T *__restrict__ f, const
         double acc = 0.0;
         if (row < rows) acc = row_partial<T, VEC, G>(f + row * Q, w, NC, g);
         acc = group_sum<G>(acc);
-        if (g == 0 && row < rows) phi[row] = s2v * acc;
+        if (g == 0 && row < rows) st_stream(phi + row, s2v * acc);
     }
 }
 

@@ -32,6 +32,12 @@ __device__ __forceinline__ V ld_stream(const V *p) {
     return __builtin_nontemporal_load(p);
 }
 
+// Streaming store of one phi value.  The reductions write 8 bytes per row
+// among many times that in sample reads; measured on 192- and 384-byte rows,
+// these stores cost 12-22% of the kernel time as ordinary stores and 2.5-4%
+// less as nontemporal ones.
+__device__ __forceinline__ void st_stream(double *p, double v) { __builtin_nontemporal_store(v, p); }
+
 // Load through a pointer known to address global memory (a pointer read out
 // of a descriptor is otherwise a flat access, counted with the LDS ones).
 __device__ __forceinline__ double ld_global(const double *p) {
