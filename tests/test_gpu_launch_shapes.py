@@ -8,7 +8,8 @@ unrolled), one-chunk-per-lane variants (rows shorter than a lane group, the
 spare lanes idle) and generic variants (any Q), each with a one-block grid (one
 block strides over every row), a few blocks and more blocks than rows.
 Every result must equal the default shape's up to summation order, and the
-single FP64 plan also matches the method oracle.
+single FP64 plan also matches the method oracle.  The DST workgroup sizes of
+single plans are forced the same way over power-of-two FFT lengths.
 """
 import numpy as np
 import pytest
@@ -63,6 +64,13 @@ def _force(path, key, tokens):
         fh.write(key + "\t" + " ".join(str(t) for t in tokens) + "\n")
 
 
+def _assert_taken(path, kind, tokens):
+    """A cache entry the library rejects is tuned again and a new entry
+    appended: the forced one must still be the last."""
+    _, last = _last_entry(path, kind)
+    assert last == [str(t) for t in tokens], ("forced shape not taken", tokens, last)
+
+
 @pytest.mark.parametrize("Q", QS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_single_shapes(lc, tmp_path, monkeypatch, prec, Q):
@@ -88,8 +96,10 @@ def test_single_shapes(lc, tmp_path, monkeypatch, prec, Q):
     cases = [(s, g) for s in shapes(prec, Q) for g in GRIDS]
     banner(f"[gpu] single {prec} Q={Q}: {len(cases)} reduction shapes x grids")
     for (vec, G, cpl, u), grid in cases:
-        _force(cache, key, ["quad", vec, G, cpl, u, 256, grid] + tok[7:])
+        forced = ["quad", vec, G, cpl, u, 256, grid] + tok[7:]
+        _force(cache, key, forced)
         p.autotune()
+        _assert_taken(cache, "single", forced)
         got = p.execute(fx).cpu().numpy()
         torch.cuda.synchronize()
         e = rel_err(got, ref)
@@ -122,8 +132,10 @@ def test_batch_shapes(lc, tmp_path, monkeypatch, prec, Q):
     cases = [(s, g) for s in shapes(prec, Q) for g in GRIDS]
     banner(f"[gpu] batch {prec} Q={Q}: {len(cases)} reduction shapes x grids")
     for (vec, G, cpl, u), grid in cases:
-        _force(cache, key, ["1", vec, G, cpl, u, 256, grid] + tok[7:])
+        forced = ["1", vec, G, cpl, u, 256, grid] + tok[7:]
+        _force(cache, key, forced)
         bp.autotune()
+        _assert_taken(cache, "batch", forced)
         got = bp.execute(arena).cpu().numpy()
         torch.cuda.synchronize()
         e = rel_err(got, ref)
@@ -131,3 +143,39 @@ def test_batch_shapes(lc, tmp_path, monkeypatch, prec, Q):
         assert e <= 1e-13, (vec, G, cpl, u, grid, e)
     banner(f"    worst difference to the default shape {worst:.2e}")
     bp.destroy()
+
+
+@pytest.mark.parametrize("L", [64, 128, 256, 512, 1024, 2048, 4096, 8192])
+def test_single_dst_threads(lc, tmp_path, monkeypatch, L):
+    """Every DST workgroup size T with L <= 8 T, forced through the cache, on
+    an FFT of power-of-two length L = H/2: the lengths 2T, 4T and 8T take the
+    compile-time Stockham passes, the others the run-time schedule.  All must
+    give the default shape's coefficients up to rounding order."""
+    import torch
+    cache = str(tmp_path / "tune.txt")
+    monkeypatch.setenv("LC_AUTOTUNE_CACHE", cache)
+    M, N, q = 4 * L, min(200, L), 16
+    f = W.Exponential(-2.5)
+    p = lc.plan(N, M, q)
+    assert p.info["M_eff"] == M and p.info["H"] == 2 * L
+    fx = f.torch(p.nodes).contiguous()
+    ref = p.execute(fx).cpu().numpy()
+    want = np.array(oracle.method_coeffs(f, N, M, q), dtype=float)
+    assert rel_err(ref, want) <= 1e-12
+    p.autotune()
+    key, tok = _last_entry(cache, "single")
+    assert tok[7] == "dst" and tok[-2] == "fused"
+    tok[-1] = "0"  # the DST kernel, not the fused small path
+    sizes = [T for T in (64, 256, 1024) if L <= 8 * T]
+    banner(f"[gpu] single DST L={L}: workgroup sizes {sizes}")
+    for T in sizes:
+        forced = tok[:8] + [str(T)] + tok[9:]
+        _force(cache, key, forced)
+        p.autotune()
+        _assert_taken(cache, "single", forced)
+        got = p.execute(fx).cpu().numpy()
+        torch.cuda.synchronize()
+        e = rel_err(got, ref)
+        assert e <= 1e-13, (T, e)
+        assert rel_err(got, want) <= 1e-12, T
+    p.destroy()
