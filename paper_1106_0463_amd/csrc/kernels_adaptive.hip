@@ -11,6 +11,8 @@
 // a row's panels in order of increasing t.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "dd_device.h"
 #include "lc_internal.h"
 #include "quad_device.h"
@@ -108,13 +110,30 @@ __device__ __forceinline__ void aflat_rows(const T *__restrict__ f, const ARow *
                 }
                 acc = fma(sc, a0 + a1, acc);
             } else {
+                // a window across panel boundaries: the panel of each chunk
+                // (and of the next window's first chunk) is the number of
+                // panel starts at or below it.  Starts 1..k lie at or below
+                // c0; the later ones are counted eight at a time with
+                // independent LDS reads (no dependent walk), until a start
+                // past the window ends the count.
+                int kc[4] = {k, k, k, k};
+                int kw = k;
+                for (int j0 = k + 1; j0 < S; j0 += 8) {
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) {
+                        const int j = j0 + jj;
+                        const int cs = j < S ? st[j].cst : INT_MAX;
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) kc[m] += cs <= c + m * G ? 1 : 0;
+                        kw += cs <= c0 + W ? 1 : 0;
+                    }
+                    if (kw < j0 + 7) break;
+                }
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int cc = c + m * G;
                     if (cc < nc) {
-                        int kk = k;
-                        while (kk + 1 < S && st[kk + 1].cst <= cc) ++kk;
-                        const ATab t = st[kk];
+                        const ATab t = st[kc[m]];
                         double d[VEC], w[VEC];
                         to_d(v[m], d);
                         chunk_weights<VEC, true>(wtab, t.wbase + cc, w);
@@ -124,7 +143,7 @@ __device__ __forceinline__ void aflat_rows(const T *__restrict__ f, const ARow *
                         acc = fma(t.scale, part, acc);
                     }
                 }
-                while (k + 1 < S && st[k + 1].cst <= c0 + W) ++k;
+                k = kw;
                 wb = st[k].wbase;
                 sc = st[k].scale;
                 nxt = k + 1 < S ? st[k + 1].cst : nc;
