@@ -477,20 +477,38 @@ hipError_t launch_dst(const DstCfg &cfg, const double *phi, int64_t H, int64_t L
         }
         return hipGetLastError();
     }
-    // four-step through global memory (256 threads, <= 2048 elements per block)
+    // four-step through global memory.  Sub-transforms of up to 512 points
+    // run in one-wave blocks, as few per block as leave 256 blocks (one per
+    // CU: at L1 = L2 = 256 a block per column), longer ones in 256-thread
+    // blocks of up to 2048 elements
     const int L1 = cfg.L1, L2 = cfg.L2;
     if ((int64_t)L1 * L2 != L || L1 > 2048 || L2 > 2048) return hipErrorInvalidValue;
-    // columns (rows) per block: the largest divisor of L2 (L1) that fits
-    int CB = 2048 / L1 < L2 ? 2048 / L1 : L2;
-    while (CB > 1 && L2 % CB) --CB;
-    int RB = 2048 / L2 < L1 ? 2048 / L2 : L1;
-    while (RB > 1 && L1 % RB) --RB;
-    if (CB < 1 || RB < 1 || CB * L1 > 2048 || RB * L2 > 2048) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fft_cols<256>, dim3(L2 / CB), dim3(256), (size_t)CB * L1 * sizeof(double2), s, phi, H,
-                       L1, L2, CB, cfg.s1, tw_pre, tw_pack, tw_fft, zA);
+    // sub-transforms of length Lsub per block out of n: the largest divisor
+    // of n with Lsub x <= cap and n / x >= min(n, 256)
+    auto per_block = [](int Lsub, int n, int cap) {
+        int x = cap / Lsub < n ? cap / Lsub : n;
+        const int want = n < 256 ? n : 256;
+        while (x > 1 && (n % x || n / x < want)) --x;
+        return x;
+    };
+    const bool c64 = L1 <= 512, r64 = L2 <= 512;
+    const int CB = c64 ? per_block(L1, L2, 512) : per_block(L1, L2, 2048);
+    const int RB = r64 ? per_block(L2, L1, 512) : per_block(L2, L1, 2048);
+    if (CB < 1 || RB < 1 || L2 % CB || L1 % RB || CB * L1 > (c64 ? 512 : 2048) || RB * L2 > (r64 ? 512 : 2048))
+        return hipErrorInvalidValue;
+    if (c64)
+        hipLaunchKernelGGL(k_fft_cols<64>, dim3(L2 / CB), dim3(64), (size_t)CB * L1 * sizeof(double2), s, phi, H,
+                           L1, L2, CB, cfg.s1, tw_pre, tw_pack, tw_fft, zA);
+    else
+        hipLaunchKernelGGL(k_fft_cols<256>, dim3(L2 / CB), dim3(256), (size_t)CB * L1 * sizeof(double2), s, phi,
+                           H, L1, L2, CB, cfg.s1, tw_pre, tw_pack, tw_fft, zA);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fft_rows<256>, dim3(L1 / RB), dim3(256), (size_t)RB * L2 * sizeof(double2), s, zA, L1,
-                       L2, RB, cfg.s2, tw_fft, zB);
+    if (r64)
+        hipLaunchKernelGGL(k_fft_rows<64>, dim3(L1 / RB), dim3(64), (size_t)RB * L2 * sizeof(double2), s, zA, L1,
+                           L2, RB, cfg.s2, tw_fft, zB);
+    else
+        hipLaunchKernelGGL(k_fft_rows<256>, dim3(L1 / RB), dim3(256), (size_t)RB * L2 * sizeof(double2), s, zA,
+                           L1, L2, RB, cfg.s2, tw_fft, zB);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int64_t blocks = (N + 255) / 256;
     if (blocks > 4096) blocks = 4096;
