@@ -217,3 +217,45 @@ def test_short_functions_packed(lc, monkeypatch, parts):
             k = 2 * np.arange(n) + 1
             assert rel_err(got / k, ref / k) <= 1e-7, b
     bp.destroy()
+
+
+def _four_step_split(L: int) -> tuple[int, int]:
+    """The documented four-step split: L1 the largest divisor <= sqrt(L) with
+    both factors <= 2048."""
+    best, a = 0, 2
+    while a * a <= L:
+        if L % a == 0 and a <= 2048 and L // a <= 2048:
+            best = a
+        a += 1
+    return best, L // best
+
+
+def test_long_function_wide_four_step(lc):
+    """A function whose FFT has four-step factors above 512 points (M =
+    2.2e6: L = 559872 = 729 x 768) beside a short one: the batched four-step
+    and the single-function four-step (256-thread blocks at these factors)
+    must both give the generating function's t^n."""
+    import torch
+    from closed_forms import genfn_coeffs
+    t = 0.5
+    N, M, Q = [2000, 64], [2_200_000, 256], [24, 32]  # Q = 16 leaves the rule's 2e-11 in c_0..c_2
+    L1, L2 = _four_step_split(expected_grid(M[0]) // 4)
+    assert max(L1, L2) > 512, (L1, L2)
+    banner(f"[gpu] batch with a long function: L = {L1} x {L2}")
+    funcs = [W.GeneratingFunction(t), W.GeneratingFunction(0.3)]
+    bp, arena, c_off = _build(lc, funcs, N, M, Q, ["fp64", "fp64"])
+    c = bp.execute(arena).cpu().numpy()
+    torch.cuda.synchronize()
+    got = c[c_off[0]:c_off[1]]
+    exact = np.array(genfn_coeffs(t, N[0]), dtype=float)
+    assert float(np.max(np.abs(got - exact))) <= 1e-12
+    short = c[c_off[1]:c_off[2]]
+    assert float(np.max(np.abs(short - np.array(genfn_coeffs(0.3, N[1]), dtype=float)))) <= 1e-12
+    bp.destroy()
+    del arena
+    p = lc.plan(N[0], M[0], Q[0])
+    fx = funcs[0].torch(p.nodes).contiguous()
+    cs = p.execute(fx).cpu().numpy()
+    torch.cuda.synchronize()
+    assert rel_err(got, cs) <= 5e-14
+    p.destroy()
