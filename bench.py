@@ -550,7 +550,7 @@ def main():
                     help="gemm workload: Abel product + batched FFT, or the direct Legendre matrix")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(functions shard trivially across GPUs; see the design notes)", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -52,7 +52,7 @@ typedef enum {
     LC_ERR_INVALID = 1,      /* bad argument (sizes, null pointer, wrong plan kind) */
     LC_ERR_NOMEM = 2,        /* device or host allocation failed                   */
     LC_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed          */
-    LC_ERR_UNSUPPORTED = 4,  /* valid request outside what this build implements   */
+    LC_ERR_UNSUPPORTED = 4,  /* valid request outside what this library implements */
     LC_ERR_INTERNAL = 5
 } lc_status;
 
@@ -135,7 +135,7 @@ typedef struct {
 } lc_plan_desc;
 
 /* Size rule for the y-grid (host only, no device work).  The FFT of eq. (2.4)
- * is computed as a complex FFT of length H/2; this build supports lengths
+ * is computed as a complex FFT of length H/2; this library supports lengths
  * 2^a 3^b.  M_eff is the smallest M' >= max(M, 4) with M' = 4 * 2^a 3^b.
  * Using M_eff >= M only refines the trapezoid grid of eq. (2.4).
  * Errors: LC_ERR_INVALID if M < 2 or M_eff is null or the size overflows. */

@@ -306,7 +306,7 @@ const char *lc_status_string(lc_status s) {
         case LC_ERR_INVALID: return "LC_ERR_INVALID: invalid argument";
         case LC_ERR_NOMEM: return "LC_ERR_NOMEM: allocation failed";
         case LC_ERR_HIP: return "LC_ERR_HIP: HIP runtime error";
-        case LC_ERR_UNSUPPORTED: return "LC_ERR_UNSUPPORTED: not supported by this build";
+        case LC_ERR_UNSUPPORTED: return "LC_ERR_UNSUPPORTED: not supported by this library";
         case LC_ERR_INTERNAL: return "LC_ERR_INTERNAL: internal error";
     }
     return "unknown lc_status";
@@ -377,7 +377,7 @@ lc_status lc_plan(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t 
         return fail(LC_ERR_UNSUPPORTED, "lc_plan: FFT length %lld has no supported four-step split",
                     (long long)L);
     if ((double)H * (double)Q > 4.0e10)
-        return fail(LC_ERR_UNSUPPORTED, "lc_plan: H*Q=%.3g samples exceeds this build's limit",
+        return fail(LC_ERR_UNSUPPORTED, "lc_plan: H*Q=%.3g samples exceeds the library's limit",
                     (double)H * (double)Q);
 
     lc_plan_s *p = new (std::nothrow) lc_plan_s();

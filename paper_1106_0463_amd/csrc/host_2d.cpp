@@ -99,7 +99,7 @@ lc_status lc_plan_2d(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan
     t->S = d.H * (int64_t)Q;
     if ((double)t->S * (double)t->S > 4.0e10 || t->S > 2000000) {
         free_2d(t);
-        return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_2d: (H Q)^2 samples exceed this build's limit");
+        return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_2d: (H Q)^2 samples exceed the library's limit");
     }
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
