@@ -170,7 +170,8 @@ __device__ void fft_lds(double2 *__restrict__ lds, int Lsub, int nsub, const Fft
 // One transform of power-of-two length LS whose pass stride NS is a
 // compile-time constant: the butterfly's quotient and remainder by NS and
 // its twiddle offsets are shifts, masks and constants, where the run-time
-// pass divides.  Same butterflies, twiddles and order as stockham_pass.
+// pass divides.  Each pass computes what stockham_pass computes for the same
+// radix and stride.
 template <int R, int T, int LS, int NS>
 __device__ __forceinline__ void stockham_fixed(double2 *__restrict__ lds, const double2 *__restrict__ tw) {
     constexpr int nbs = LS / R, span = NS * R, twstep = LS / span;
@@ -222,8 +223,10 @@ __device__ __forceinline__ void fixed_passes(double2 *__restrict__ lds, const do
 }
 
 // One transform of length L <= EPT T in LDS (as fft_lds with nsub = 1):
-// the power-of-two lengths 2T, 4T and 8T take compile-time passes, every
-// other length the run-time schedule.
+// the power-of-two lengths 2T, 4T and 8T take compile-time passes (radix 8
+// first, whatever radix order the schedule names: the results differ from
+// the schedule's by rounding only), every other length the run-time
+// schedule.
 template <int T, int EPT>
 __device__ void fft_lds_one(double2 *__restrict__ lds, int L, const FftSched &sch, const double2 *__restrict__ tw) {
     static_assert(EPT == 8, "compile-time lengths assume 8 values per thread");
