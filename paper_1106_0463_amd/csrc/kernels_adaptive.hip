@@ -116,7 +116,16 @@ __device__ __forceinline__ void aflat_rows(const T *__restrict__ f, const ARow *
                 // c0; the later ones are counted eight at a time with
                 // independent LDS reads (no dependent walk), until a start
                 // past the window ends the count.
-                int kc[4] = {k, k, k, k};
+                // Chunks past the row end (zero samples) take the last
+                // chunk's panel and weights, so that all four weight loads
+                // are unconditional and in flight together; their products
+                // are dropped.
+                int ce[4], kc[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    ce[m] = c + m * G < nc ? c + m * G : nc - 1;
+                    kc[m] = k;
+                }
                 int kw = k;
                 for (int j0 = k + 1; j0 < S; j0 += 8) {
 #pragma unroll
@@ -124,24 +133,22 @@ __device__ __forceinline__ void aflat_rows(const T *__restrict__ f, const ARow *
                         const int j = j0 + jj;
                         const int cs = j < S ? st[j].cst : INT_MAX;
 #pragma unroll
-                        for (int m = 0; m < 4; ++m) kc[m] += cs <= c + m * G ? 1 : 0;
+                        for (int m = 0; m < 4; ++m) kc[m] += cs <= ce[m] ? 1 : 0;
                         kw += cs <= c0 + W ? 1 : 0;
                     }
                     if (kw < j0 + 7) break;
                 }
+                double w[4][VEC];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) chunk_weights<VEC, true>(wtab, st[kc[m]].wbase + ce[m], w[m]);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const int cc = c + m * G;
-                    if (cc < nc) {
-                        const ATab t = st[kc[m]];
-                        double d[VEC], w[VEC];
-                        to_d(v[m], d);
-                        chunk_weights<VEC, true>(wtab, t.wbase + cc, w);
-                        double part = 0.0;
+                    double d[VEC];
+                    to_d(v[m], d);
+                    double part = 0.0;
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) part = fma(w[e], d[e], part);
-                        acc = fma(t.scale, part, acc);
-                    }
+                    for (int e = 0; e < VEC; ++e) part = fma(w[m][e], d[e], part);
+                    acc = fma(c + m * G < nc ? st[kc[m]].scale : 0.0, part, acc);  // + 0 past the end
                 }
                 k = kw;
                 wb = st[k].wbase;

@@ -293,20 +293,33 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int b = rb * 32 + (lane & 31);
     const double sc = (colexp && b < B) ? ldexp(1.0, -max(colexp[b], -1000)) : 1.0;
+    // every load of the wave's kSplitKW fragments first, branch-free (indices
+    // past F clamped, their values zeroed below), so that all are in flight
+    // together; masked loads would each wait for the one before
+    const int bc = b < B ? b : B - 1;
+    double v[kSplitKW][8];
+#pragma unroll
+    for (int j = 0; j < kSplitKW; ++j) {
+        const int k = ((kg * 4 + w) * kSplitKW + j) * 16 + (lane >> 5) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            v[j][e] = __builtin_nontemporal_load(F + (int64_t)(k + e < P ? k + e : P - 1) * B + bc);
+    }
+    // (the pieces of fragments past K16 are computed and dropped: only their
+    // stores are conditional, so the loads above stay ahead of every use)
 #pragma unroll
     for (int j = 0; j < kSplitKW; ++j) {
         const int k16 = (kg * 4 + w) * kSplitKW + j;
-        if (k16 >= K16) break;
         const int k = k16 * 16 + (lane >> 5) * 8;
-        double v[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-            v[e] = (b < B && k + e < P) ? __builtin_nontemporal_load(F + (int64_t)(k + e) * B + b) * sc : 0.0;
+        for (int e = 0; e < 8; ++e) v[j][e] = (b < B && k + e < P) ? v[j][e] * sc : 0.0;
         u32x4 out[NPC];
-        split8<H16, NPC>(v, out);
+        split8<H16, NPC>(v[j], out);
+        if (k16 < K16) {
 #pragma unroll
-        for (int i = 0; i < NPC; ++i)
-            *reinterpret_cast<u32x4 *>(X + i * piece_stride + fo_offset(b, k, K16)) = out[i];
+            for (int i = 0; i < NPC; ++i)
+                *reinterpret_cast<u32x4 *>(X + i * piece_stride + fo_offset(b, k, K16)) = out[i];
+        }
     }
 }
 
