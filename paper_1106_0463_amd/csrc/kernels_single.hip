@@ -426,9 +426,11 @@ __global__ __launch_bounds__(T) void k_fft_rows(const double2 *__restrict__ A, i
         double2 z[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) z[u] = A[(int64_t)p10 * L2 + min(e0 + (int)threadIdx.x + u * T, RB * L2 - 1)];
+        // unconditional stores (past the end: the last element again, the
+        // value loaded for it), so that no masked store pulls its load after
+        // the previous one's wait
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (e0 + (int)threadIdx.x + u * T < RB * L2) lds[e0 + threadIdx.x + u * T] = z[u];
+        for (int u = 0; u < 4; ++u) lds[min(e0 + (int)threadIdx.x + u * T, RB * L2 - 1)] = z[u];
     }
     __syncthreads();
     fft_lds<T, 8>(lds, L2, RB, s2, tw_fft, L1);
