@@ -13,7 +13,16 @@ twist, FFT and rescale over one resident batch of samples):
                  "uniform_rule_point" (--rule uniform swaps the two), and the
                  Q = 64 point under "stated_q_point".
 
-Other workloads (--workload): single_small (N=64, M=256, Q=32), batch
+The default line verifies what it times: E_c of the timed output on the
+seeded 512-index subset against eq. (2.3) (the definition oracle with a
+49152-point rule over all 65536 coefficients, computed once by the
+cpu_baseline leg, which times it).  It also carries the other workloads
+under "workloads", each with its throughput, its dominant kernel's roofline
+fraction and its accuracy: the uneven batch (FP64 and FP32 samples),
+Abel-as-GEMM (fp16x3, bf16x6), the mixed stream and the 2-D transform
+(--main-only skips them).
+
+Single workloads (--workload): single_small (N=64, M=256, Q=32), batch
 (4096 ragged random Legendre series, Q=48), gemm (Abel-as-GEMM, P=4096,
 B=16384; --form direct: the direct Legendre-matrix product), stream
 (65536-function Pareto mix), tensor2d (2-D tensor-product transform, N=256
@@ -45,11 +54,19 @@ TRAFFIC = {"single_large_band": (4.9517e9, "k_aflat<double>"),
            "batch_fp64": (7.7919e9, "k_bquad_fit<double, 2, 8, 3, 2>")}
 METRIC = "Legendre coeffs/sec at 1 GPU (FP64 ≤1e-12 vs split-BF16 ≤1e-7 rel.)"
 Q_RESOLVING = 8384
+FP64_CLASS = 1e-12   # E_c = max|dc| / max|c|
+MIXED_CLASS = 1e-7   # E_a = max|da| / max|a|, a_n = c_n / (2n+1)
 
 
 def _sync():
     import torch
     torch.cuda.synchronize()
+
+
+def _free():
+    import torch
+    _sync()
+    torch.cuda.empty_cache()
 
 
 def time_steps(step, steps: int, warmup: int):
@@ -67,29 +84,45 @@ def time_steps(step, steps: int, warmup: int):
     return (t1 - t0) / steps
 
 
-def cpu_baseline_single_large(budget_s: float = 20.0):
-    """Time the definition oracle on the large single function: the first
-    N_s coefficients with a K-point rule that resolves f P_n
-    (K = (N_s + 16600)/2 + 256), N_s doubling from 16384 up to the whole
-    N = 65536 while the time stays within the budget."""
+def _closed_forms():
+    """The test suite's closed-form coefficients (t^n of eq. (2.2), the
+    modified spherical Bessel form of e^{ax}): exact answers, not the oracle."""
+    here = os.path.join(ROOT, "tests")
+    if here not in sys.path:
+        sys.path.insert(0, here)
+    import closed_forms
+    return closed_forms
+
+
+def _errors(got, ref):
+    """(E_c, E_a): max|dc|/max|c| and the same on a_n = c_n / (2n+1)."""
+    import numpy as np
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    k = 2.0 * np.arange(ref.shape[-1]) + 1.0
+    E_c = float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+    E_a = float(np.max(np.abs((got - ref) / k)) / max(np.max(np.abs(ref / k)), 1e-300))
+    return E_c, E_a
+
+
+def cpu_baseline_single_large():
+    """The definition oracle on the large single function: all 65536
+    coefficients by eq. (2.3) with a 49152-point long-double Gauss-Legendre
+    rule (it resolves f P_n: degree <= 65535 + ~16600), timed with the rule
+    construction.  Returns the baseline record and the coefficients, which
+    are the reference of the timed GPU output."""
+    import numpy as np
+
     import oracle
     import workloads as W
     wl = W.single_large()
-    N_s, dt, K = 16384, 0.0, 0
-    while True:
-        K = (N_s + 16600) // 2 + 256
-        t0 = time.perf_counter()
-        oracle.legendre_coeffs(wl.f, N_s, K)
-        dt = time.perf_counter() - t0
-        # cost ~ N K: the next size takes about 3x as long
-        if N_s >= wl.N or dt * 3.5 > budget_s:
-            break
-        N_s *= 2
-    what = "all" if N_s >= wl.N else "the first"
-    return {"value": N_s / dt, "unit": "coefficients/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{what} {N_s} coefficients of the same f, eq. (2.3) by a {K}-point "
-                      f"long-double Gauss-Legendre rule (rule construction included), {dt:.2f} s"}
+    K = 49152
+    t0 = time.perf_counter()
+    ref = np.array(oracle.legendre_coeffs(wl.f, wl.N, K), dtype=np.float64)
+    dt = time.perf_counter() - t0
+    return ({"value": wl.N / dt, "unit": "coefficients/s", "cores": oracle.threads(), "kind": "oracle",
+             "sample": f"all {wl.N} coefficients of the same f, eq. (2.3) by a {K}-point "
+                       f"long-double Gauss-Legendre rule (rule construction included), {dt:.2f} s"}, ref)
 
 
 def read_ceiling_gbs(nbytes: int = 4 << 30, reps: int = 10) -> float:
@@ -126,6 +159,8 @@ def bench_single(args, N, M, Q, f, name, rule=None):
     step = lambda: p.execute(fx, out)
     p.set_timing(False)
     sec = time_steps(step, args.steps, args.warmup)
+    # the output of the timed steps, kept for the accuracy check
+    timed_out = out.cpu().numpy()
     # kernel timing over a second timed pass (events recorded by the library)
     p.set_timing(True)
     for _ in range(args.steps):
@@ -138,7 +173,7 @@ def bench_single(args, N, M, Q, f, name, rule=None):
     # samples counts against the kernel) + phi written and re-read
     alg_bytes = 8.0 * info["samples"] + 16.0 * H
     res = {"sec": sec, "kernel_ms": kms, "kernel_count": cnt, "alg_bytes": alg_bytes,
-           "info": info, "coefs": out}
+           "info": info, "coefs": timed_out}
     return p, fx, res
 
 
@@ -181,8 +216,7 @@ def run_single_large(args):
                                   else f", uniform Abel rule Q={wl.Q}"),
                    "N": N, "M": M, "M_eff": r["info"]["M_eff"],
                    "abel_rule": dict(BAND_RULE) if band else {"Q": wl.Q},
-                   "samples": r["info"]["samples"], "Q_stated": 64,
-                   "precision_class": "FP64 (<=1e-12 max|c|)"},
+                   "samples": r["info"]["samples"], "Q_stated": 64},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": TRAFFIC[TKEY][0] if (band or wl.Q == Q_RESOLVING) and TKEY in TRAFFIC else None,
@@ -193,9 +227,10 @@ def run_single_large(args):
     TK = TRAFFIC.get(TKEY)
     if TK:
         line["roofline"]["traffic_kernel"] = TK[1]
+    timed = r["coefs"]
     p.destroy()
     del fx
-    torch.cuda.empty_cache()
+    _free()
     # a measured read ceiling beside the nominal peak: one plain read-only
     # stream of the vendor library over 4 GiB
     rc = read_ceiling_gbs()
@@ -203,17 +238,19 @@ def run_single_large(args):
                                                  "frac_of_measured": achieved / rc}
     # the other rule beside it: the uniform rule at the resolving Q (or the
     # band rule when the uniform one is the main line)
+    other = None
     if not args.skip_stated:
         ro = None if band else BAND_RULE
         po, fxo, rr = bench_single(args, N, M, Q_RESOLVING, wl.f, wl.name, rule=ro)
         ao = rr["alg_bytes"] / (rr["kernel_ms"] * 1e-3) / 1e9
+        other = rr["coefs"]
         line["uniform_rule_point" if band else "band_rule_point"] = {
             "abel_rule": {"Q": Q_RESOLVING} if band else dict(BAND_RULE), "samples": rr["info"]["samples"],
             "value": N / rr["sec"], "ms_per_step": rr["sec"] * 1e3, "kernel_ms": rr["kernel_ms"],
             "achieved_GBs": ao, "frac": ao / HBM_PEAK_GBS}
         po.destroy()
         del fxo
-        torch.cuda.empty_cache()
+        _free()
     # stated-Q point (bandwidth only: the stated Q does not resolve f)
     if not args.skip_stated:
         wl64 = W.single_large(Q=64)
@@ -224,17 +261,35 @@ def run_single_large(args):
                                   "note": "Q=64 under-resolves cos(16384x): throughput only"}
         p64.destroy()
         del fx64
+        _free()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_single_large()
+        cpu, ref = cpu_baseline_single_large()
+        line["cpu_baseline"] = cpu
+        idx = W.subset_indices()
+        scale = float(np.max(np.abs(ref)))
+        E_c = float(np.max(np.abs(timed[idx] - ref[idx])) / scale)
+        line["accuracy"] = {"E_c": E_c, "class": "FP64" if E_c <= FP64_CLASS else "outside the FP64 class",
+                            "reference": "eq. (2.3), 49152-point long-double Gauss-Legendre rule "
+                                         "(the cpu_baseline run)",
+                            "indices": "seeded subset of 512 n (rng(2).choice(65536, 512))",
+                            "of": "the output of the timed steps"}
+        line["config"]["precision_class"] = ("FP64 (<=1e-12 max|c|)" if E_c <= FP64_CLASS
+                                             else f"E_c {E_c:.2e}: outside the FP64 class")
+        if other is not None:
+            E_o = float(np.max(np.abs(other[idx] - ref[idx])) / scale)
+            line["uniform_rule_point" if band else "band_rule_point"]["E_c"] = E_o
     return line
 
 
 def run_single_small(args):
+    import numpy as np
+
     import workloads as W
     wl = W.single_small()[0]
     p, fx, r = bench_single(args, wl.N, wl.M, wl.Q, wl.f, wl.name)
     sec, kms = r["sec"], r["kernel_ms"]
     achieved = r["alg_bytes"] / (kms * 1e-3) / 1e9
+    E_c, _ = _errors(r["coefs"], 0.5 ** np.arange(wl.N))
     line = {"metric": METRIC, "value": wl.N / sec, "unit": "coefficients/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -245,31 +300,23 @@ def run_single_small(args):
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "kernel": "k_fused_small (latency bound)", "kernel_ms": kms,
                          "alg_bytes_per_launch": r["alg_bytes"]},
+            "accuracy": {"E_c": E_c, "reference": "c_n = 0.5^n (eq. (2.2))",
+                         "class": "FP64" if E_c <= FP64_CLASS else "outside the FP64 class"},
             "us_per_call": sec * 1e6}
     p.destroy()
     return line
 
 
-def stream_request(ms, b):
-    """(M_b, Q_b) for one request of the mixed stream: M_b = 4 N_b, enlarged
-    for the generating function so that the aliased tail t^{n+M} is below
-    1e-13 (M_b >= N_b + ln(1e-13)/ln t + 1); Q_b = 48."""
-    N = int(ms.N[b])
-    M = 4 * N
-    if ms.kind[b] == 0:
-        t = float(ms.param[b])
-        M = max(M, N + int(math.ceil(math.log(1e-13) / math.log(t))) + 1)
-    M += M % 2
-    return M, 48
-
-
 def _batch_common(args, bp, arena, Nsum, alg_bytes, workload_cfg, cpu):
+    """Times the graph-replayed batch execution on a side stream; returns
+    the line and the coefficient arena of the timed steps (host)."""
     import torch
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         c = torch.empty(int(bp.offsets()[2][-1]), dtype=torch.float64, device="cuda")
         step = lambda: bp.execute(arena, c, stream=s)
         sec = time_steps(step, args.steps, args.warmup)
+        timed = c.cpu().numpy()
         bp.set_timing(True)
         for _ in range(min(args.steps, 10)):
             step()
@@ -287,12 +334,10 @@ def _batch_common(args, bp, arena, Nsum, alg_bytes, workload_cfg, cpu):
                          "kernel_ms": kms, "alg_bytes_per_launch": alg_bytes}}
     if cpu is not None:
         line["cpu_baseline"] = cpu
-    return line
+    return line, timed
 
 
-def cpu_baseline_series(sb, idx):
-    import numpy as np
-
+def cpu_baseline_series(sb, idx, budget_s: float = 20.0):
     import oracle
     import workloads as W
     t0 = time.perf_counter()
@@ -301,7 +346,7 @@ def cpu_baseline_series(sb, idx):
         N = int(sb.N[b])
         oracle.legendre_coeffs(W.LegendreSeries(sb.coeffs[b]), N, N + 32)
         n += N
-        if time.perf_counter() - t0 > 20:
+        if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "coefficients/s", "cores": oracle.threads(), "kind": "oracle",
@@ -309,7 +354,7 @@ def cpu_baseline_series(sb, idx):
                       f"(N_b+32)-point long-double Gauss-Legendre rule, {dt:.2f} s"}
 
 
-def run_batch(args):
+def run_batch(args, prec=None, cpu_budget=20.0):
     import numpy as np
     import torch
 
@@ -317,7 +362,7 @@ def run_batch(args):
     import workloads as W
     from workloads.gpu import series_ragged
     sb = W.batch_uneven(B=4096)
-    prec = args.precision
+    prec = prec or args.precision
     bp = lc.plan_batch(sb.N, sb.M, sb.Q, prec)
     if args.autotune:
         bp.autotune()
@@ -333,16 +378,114 @@ def run_batch(args):
            "B": 4096, "sum_N": int(sb.N.sum()), "Q": 48, "precision": prec,
            "dtype": "f64" if prec == "fp64" else "f32 samples / f64 arithmetic"}
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline_series(sb, np.random.default_rng(3).choice(4096, 64, replace=False))
-    line = _batch_common(args, bp, arena, int(sb.N.sum()), alg, cfg, cpu)
+    if not args.no_cpu_baseline and cpu_budget > 0:
+        cpu = cpu_baseline_series(sb, np.random.default_rng(3).choice(4096, 64, replace=False), cpu_budget)
+    line, c = _batch_common(args, bp, arena, int(sb.N.sum()), alg, cfg, cpu)
     if prec == "fp64" and "batch_fp64" in TRAFFIC:
         line["roofline"]["traffic"], line["roofline"]["traffic_kernel"] = TRAFFIC["batch_fp64"]
     bp.destroy()
+    del arena
+    _free()
+    # accuracy against the series' own coefficients: Q = 48 resolves only
+    # degree <= 95, so this is the discretization error of the stated Q
+    # (arithmetic parity with the oracle at the same Q is a GPU test)
+    E = np.array([_errors(c[c_off[b]:c_off[b + 1]], sb.coeffs[b]) for b in range(4096)])
+    line["accuracy"] = {"E_c_vs_true_max": float(E[:, 0].max()), "E_c_vs_true_median": float(np.median(E[:, 0])),
+                        "E_a_vs_true_max": float(E[:, 1].max()),
+                        "class": "none at the stated Q=48: it under-resolves degree N_b-1 (discretization "
+                                 "error); arithmetic parity with the method oracle at the same Q is tested "
+                                 "to 1e-12"}
     return line
 
 
-def run_stream(args):
+def stream_request(ms, b):
+    """(M_b, Q_b) for one request of the mixed stream: M_b = 4 N_b, enlarged
+    for the generating function so that the aliased tail t^{n+M} is below
+    1e-13 (M_b >= N_b + ln(1e-13)/ln t + 1); Q_b = 48."""
+    N = int(ms.N[b])
+    M = 4 * N
+    if ms.kind[b] == 0:
+        t = float(ms.param[b])
+        M = max(M, N + int(math.ceil(math.log(1e-13) / math.log(t))) + 1)
+    M += M % 2
+    return M, 48
+
+
+def stream_exact(ms):
+    """Exact coefficients of every request of the mixed stream (t^n for the
+    generating functions, eq. (2.2); (2n+1) sgn(a)^n i_n(|a|) for e^{ax}),
+    as a list of float64 arrays."""
+    import numpy as np
+    cf = _closed_forms()
+    B = ms.N.size
+    out = [None] * B
+    exp_ids = np.where(ms.kind == 1)[0]
+    for k0 in range(0, exp_ids.size, 4096):
+        ids = exp_ids[k0:k0 + 4096]
+        tab = cf.exp_coeffs_many(ms.param[ids], top=600)
+        for j, b in enumerate(ids):
+            c = np.zeros(int(ms.N[b]))
+            m = min(c.size, 601)
+            c[:m] = tab[j, :m]
+            out[b] = c
+    for b in np.where(ms.kind == 0)[0]:
+        out[b] = float(ms.param[b]) ** np.arange(int(ms.N[b]), dtype=np.float64)
+    return out
+
+
+def stream_accuracy(ms, c, c_off):
+    """E_c of the FP64 requests, E_a of the FP32-sample requests against the
+    exact coefficients, and the requests outside their class."""
+    import numpy as np
+    exact = stream_exact(ms)
+    B = ms.N.size
+    Ec = np.zeros(B)
+    Ea = np.zeros(B)
+    for b in range(B):
+        Ec[b], Ea[b] = _errors(c[c_off[b]:c_off[b + 1]], exact[b])
+    f64 = ms.fp64
+    out64 = f64 & (Ec > FP64_CLASS)
+    out32 = (~f64) & (Ea > MIXED_CLASS)
+    gen = ms.kind == 0
+    return {"E_c_fp64_max": float(Ec[f64].max()), "E_a_fp32_max": float(Ea[~f64].max()),
+            "out_of_class": int(out64.sum() + out32.sum()),
+            "out_of_class_fp64": int(out64.sum()), "out_of_class_fp32": int(out32.sum()),
+            "out_of_class_t_min": float(ms.param[(out64 | out32) & gen].min()) if np.any((out64 | out32) & gen)
+            else None,
+            "E_c_fp64_max_exp": float(Ec[f64 & ~gen].max()) if np.any(f64 & ~gen) else None,
+            "reference": "exact c_n: t^n (eq. (2.2)) and (2n+1) sgn(a)^n i_n(|a|) for e^(ax)",
+            "class": "FP64 requests: E_c <= 1e-12; FP32-sample requests: E_a <= 1e-7"}
+
+
+def cpu_baseline_stream(ms, budget_s: float = 20.0):
+    """The definition oracle on seeded requests of the stream (a seeded
+    permutation, as many as fit the budget): eq. (2.3) with a K-point rule
+    that resolves f P_n (K = (N_b + D_f)/2 + 32, D_f the degree beyond which
+    the request's coefficients fall below 1e-16)."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    order = np.random.default_rng(5).permutation(ms.N.size)
+    t0 = time.perf_counter()
+    n = 0
+    for b in order:
+        N = int(ms.N[b])
+        if ms.kind[b] == 0:
+            D = int(math.ceil(math.log(1e-16) / math.log(float(ms.param[b]))))
+        else:
+            D = int(math.e * abs(float(ms.param[b])) / 2) + 40
+        oracle.legendre_coeffs(W.stream_function(ms, b), N, (N + D) // 2 + 32)
+        n += N
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "coefficients/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n} coefficients of seeded requests of the same stream, eq. (2.3) by a "
+                      f"(N_b + D_f)/2 + 32-point long-double Gauss-Legendre rule, {dt:.2f} s"}
+
+
+def run_stream(args, cpu_budget=20.0):
     import numpy as np
     import torch
 
@@ -361,9 +504,7 @@ def run_stream(args):
     f_off, x_off, c_off = bp.offsets()
     arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
     funcs = [W.stream_function(ms, b) for b in range(B)]
-    Heff = np.diff(x_off)  # upper bound only for fill; exact rows from the plan grid
-    import paper_1106_0463_amd as _lc
-    H = np.array([_lc.grid_size(int(m)) // 2 for m in M], dtype=np.int64)
+    H = np.array([lc.grid_size(int(m)) // 2 for m in M], dtype=np.int64)
     fill_closed_form_arena(bp.nodes, arena, x_off, f_off, H, Q, funcs, [p == "fp32" for p in prec])
     esz = np.where(ms.fp64, 8, 4)
     alg = float(np.sum(esz * (M // 2) * Q) + 16 * np.sum(M // 2))
@@ -371,16 +512,44 @@ def run_stream(args):
                        f"t~U(0.1,0.999) and e^(ax) a~U(-20,20), FP64 and FP32-sample requests alternating, Q=48",
            "B": B, "sum_N": int(ms.N.sum()), "Q": 48, "autotuned": bool(args.autotune),
            "dtype": "f64 (half the requests with f32 samples)"}
-    line = _batch_common(args, bp, arena, int(ms.N.sum()), alg, cfg, None)
+    cpu = None if args.no_cpu_baseline or cpu_budget <= 0 else cpu_baseline_stream(ms, cpu_budget)
+    line, c = _batch_common(args, bp, arena, int(ms.N.sum()), alg, cfg, cpu)
     bp.destroy()
+    del arena
+    _free()
+    line["accuracy"] = stream_accuracy(ms, c, c_off)
     return line
 
 
 PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x6": 2500.0, "fp16x3": 2500.0, "fp16x1": 2500.0, "fp64": 78.6}
 NPROD = {"bf16x3": 3, "bf16x6": 6, "fp16x3": 3, "fp16x1": 1, "fp64": 1}
+IN_MIXED_CLASS = {"fp16x3", "bf16x6"}   # bf16x3 and fp16x1 stay above E_a = 1e-7
 
 
-def run_gemm(args):
+def cpu_baseline_gemm(coef, N, budget_s: float = 20.0):
+    """The definition oracle on seeded functions of the fixed-grid batch
+    (degree 3000 series, N = 4096 coefficients each; a 3580-point rule
+    resolves f P_n), as many as fit the budget."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    order = np.random.default_rng(4).permutation(coef.shape[0])
+    K = (N + coef.shape[1]) // 2 + 32
+    t0 = time.perf_counter()
+    n = 0
+    for b in order:
+        oracle.legendre_coeffs(W.LegendreSeries(coef[b]), N, K)
+        n += N
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "coefficients/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n // N} seeded functions of the same batch ({n} coefficients), eq. (2.3) by a "
+                      f"{K}-point long-double Gauss-Legendre rule, {dt:.2f} s"}
+
+
+def run_gemm(args, mode=None, form=None, cpu_budget=20.0):
     import numpy as np
     import torch
 
@@ -388,14 +557,18 @@ def run_gemm(args):
     import workloads as W
     from workloads.gpu import series_grid
     B, P, M, N, deg = 16384, 4096, 8192, 4096, 3000
-    mode = args.mode
+    mode = mode or args.mode
+    form = form or args.form
     coef = W.gemm_batch_coeffs(B, deg, seed=4)
-    direct = args.form == "direct"
+    direct = form == "direct"
     g = (lc.plan_legendre_matrix if direct else lc.plan_gemm)(P, M, N, mode)
     F = series_grid(coef, g.nodes)
     C = torch.empty((B, N), dtype=torch.float64, device="cuda")
     step = lambda: g.execute(F, C)
     sec = time_steps(step, args.steps, args.warmup)
+    # accuracy of the timed output on 256 sampled functions (true coefficients known)
+    sel = np.random.default_rng(41).choice(B, 256, replace=False)
+    Cs = C[torch.from_numpy(sel).cuda()].cpu().numpy()
     g.set_timing(True)
     for _ in range(args.steps):
         step()
@@ -405,15 +578,13 @@ def run_gemm(args):
     R = N if direct else g.info["H"]  # rows of the matrix operand
     flops = 2.0 * B * R * P * NPROD[mode]
     achieved = flops / (kms * 1e-3) / 1e12
-    # accuracy of this run on 256 sampled functions (true coefficients known)
-    sel = np.random.default_rng(41).choice(B, 256, replace=False)
-    Cs = C[torch.from_numpy(sel).cuda()].cpu().numpy()
-    ref = coef[sel]
     refN = np.zeros((256, N))
-    refN[:, :deg + 1] = ref
-    n = np.arange(N)
-    E_c = float(np.max(np.abs(Cs - refN)) / np.max(np.abs(refN)))
-    E_a = float(np.max(np.abs(Cs / (2 * n + 1) - refN / (2 * n + 1))) / np.max(np.abs(refN / (2 * n + 1))))
+    refN[:, :deg + 1] = coef[sel]
+    E_c, E_a = _errors(Cs, refN)
+    if mode == "fp64":
+        cls = "FP64" if E_c <= FP64_CLASS else "outside the FP64 class"
+    else:
+        cls = "mixed (E_a <= 1e-7)" if E_a <= MIXED_CLASS else "outside the mixed class"
     peak = PEAK_TFLOPS[mode]
     line = {"metric": METRIC, "value": B * N / sec, "unit": "coefficients/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
@@ -424,16 +595,21 @@ def run_gemm(args):
             "config": {"workload": ("direct Legendre matrix" if direct else "Abel-as-GEMM")
                                    + f", P=4096 Chebyshev-Gauss samples, B=16384 random Legendre "
                                    f"series of degree 3000, M=8192, N=4096, mode {mode}",
-                       "B": B, "P": P, "M": M, "N": N, "mode": mode, "form": args.form,
-                       "E_a": E_a, "E_c": E_c},
+                       "B": B, "P": P, "M": M, "N": N, "mode": mode, "form": form},
+            "accuracy": {"E_a": E_a, "E_c": E_c, "class": cls,
+                         "reference": "the series' own coefficients, 256 sampled functions of the timed output"},
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                          "frac": achieved / peak, "traffic": None,
                          "kernel": "k_mgemm (split-precision MFMA product)" if mode != "fp64" else "rocblas dgemm",
                          "kernel_ms": kms, "flops_per_launch": flops}}
     g.destroy()
-    if mode != "fp64":
+    del F, C
+    _free()
+    if mode != "fp64" and not args.no_library_point:
         line["library_gemm_point"] = library_gemm_point(B, P, R, torch.bfloat16 if mode.startswith("bf16")
                                                         else torch.float16, peak, args.steps)
+    if not args.no_cpu_baseline and cpu_budget > 0:
+        line["cpu_baseline"] = cpu_baseline_gemm(coef, N, cpu_budget)
     return line
 
 
@@ -455,6 +631,8 @@ def library_gemm_point(B, K, R, dtype, peak, steps):
     _sync()
     ms = e0.elapsed_time(e1) / steps
     tf = 2.0 * B * K * R / (ms * 1e-3) / 1e12
+    del a, b
+    _free()
     return {"op": f"torch.matmul [{B},{K}] x [{K},{R}] {str(dtype).replace('torch.', '')}",
             "ms": ms, "achieved_TFLOPs": tf, "frac": tf / peak}
 
@@ -462,7 +640,9 @@ def library_gemm_point(B, K, R, dtype, peak, steps):
 def run_tensor2d(args):
     """Two-dimensional tensor-product plan: f(x1, x2) = exp(x1 x2) + x1^2
     cos(3 x2), N = 256 per axis, M = 1024, Q = 32 (S = 16384 nodes per axis,
-    S^2 = 2.7e8 FP64 samples)."""
+    S^2 = 2.7e8 FP64 samples).  The cpu_baseline leg computes every
+    coefficient by eq. (2.3) along both axes; that is the reference of the
+    timed output."""
     import numpy as np
     import torch
 
@@ -476,6 +656,7 @@ def run_tensor2d(args):
     C = torch.empty((N, N), dtype=torch.float64, device="cuda")
     step = lambda: p.execute(F, C)
     sec = time_steps(step, args.steps, args.warmup)
+    timed = C.cpu().numpy()
     p.set_timing(True)
     for _ in range(args.steps):
         step()
@@ -497,7 +678,8 @@ def run_tensor2d(args):
                          "kernel": "k_quad_* over the S*H rows of the first pass",
                          "kernel_ms": kms, "alg_bytes_per_launch": alg_bytes}}
     p.destroy()
-    del F
+    del F, C
+    _free()
     if not args.no_cpu_baseline:
         import oracle
         t0 = time.perf_counter()
@@ -506,13 +688,16 @@ def run_tensor2d(args):
         xl = x.astype(np.longdouble)
         Fk = np.exp(xl[:, None] * xl[None, :]) + xl[:, None] ** 2 * np.cos(3 * xl[None, :])
         step1 = np.stack([oracle.legendre_coeffs_from_samples(x, w, Fk[:, k], N) for k in range(K)], axis=1)
-        for n in range(N):
-            oracle.legendre_coeffs_from_samples(x, w, step1[n, :], N)
+        ref = np.stack([oracle.legendre_coeffs_from_samples(x, w, step1[n, :], N) for n in range(N)], axis=0)
         dt = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": N * N / dt, "unit": "coefficients/s", "cores": oracle.threads(),
                                 "kind": "oracle",
                                 "sample": f"all {N}x{N} coefficients of the same f by eq. (2.3) along both "
                                           f"axes with a {K}-point long-double Gauss-Legendre rule, {dt:.2f} s"}
+        ref = np.asarray(ref, dtype=np.float64)
+        E_c = float(np.max(np.abs(timed - ref)) / np.max(np.abs(ref)))
+        line["accuracy"] = {"E_c": E_c, "class": "FP64" if E_c <= FP64_CLASS else "outside the FP64 class",
+                            "reference": "eq. (2.3) along both axes (the cpu_baseline run)"}
     return line
 
 
@@ -529,6 +714,40 @@ def run_copy(args):
             "higher_is_better": True, "bytes_read_per_launch": 8 * n, "bytes_written_per_launch": 8 * n}
 
 
+def _sub(line):
+    """The keys of a workload line that the default line carries."""
+    keep = ("value", "unit", "ms_per_step", "dtype", "config", "accuracy", "cpu_baseline",
+            "library_gemm_point")
+    out = {k: line[k] for k in keep if k in line}
+    rf = line["roofline"]
+    out["roofline"] = {k: rf[k] for k in ("bound", "kernel", "kernel_ms", "achieved", "unit", "peak", "frac")}
+    return out
+
+
+def other_workloads(args):
+    """Every other workload at its full size, each with throughput, its
+    dominant kernel's roofline fraction and accuracy; a workload that fails
+    reports its error instead of ending the run."""
+    runs = [("batch_fp64", lambda: run_batch(args, "fp64", cpu_budget=5.0)),
+            ("batch_fp32", lambda: run_batch(args, "fp32", cpu_budget=0.0)),
+            ("gemm_fp16x3", lambda: run_gemm(args, "fp16x3", "abel", cpu_budget=5.0)),
+            ("gemm_bf16x6", lambda: run_gemm(args, "bf16x6", "abel", cpu_budget=0.0)),
+            ("direct_fp16x3", lambda: run_gemm(args, "fp16x3", "direct", cpu_budget=0.0)),
+            ("stream", lambda: run_stream(args, cpu_budget=5.0)),
+            ("tensor2d", lambda: run_tensor2d(args))]
+    out = {}
+    for name, fn in runs:
+        t0 = time.perf_counter()
+        try:
+            out[name] = _sub(fn())
+        except Exception as e:  # reported in the line, the other workloads still run
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+        out[name]["wall_s"] = round(time.perf_counter() - t0, 1)
+        print(f"[bench] {name} done in {out[name]['wall_s']} s", file=sys.stderr, flush=True)
+        _free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -536,16 +755,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_large",
                     choices=["single_large", "single_small", "batch", "gemm", "stream", "tensor2d", "copy"])
+    ap.add_argument("--main-only", action="store_true",
+                    help="single_large: leave out the other workloads")
     ap.add_argument("--q", type=int, default=0, help="override Q (single_large, uniform rule)")
     ap.add_argument("--rule", default="band", choices=["band", "uniform"],
                     help="single_large: composite Abel rule with per-row node counts, or the uniform rule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-library-point", action="store_true")
     ap.add_argument("--skip-stated", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--stream-b", type=int, default=65536)
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the default launch shapes instead of the autotuner's")
-    ap.add_argument("--mode", default="bf16x3", help="gemm mode")
+    ap.add_argument("--mode", default="fp16x3", help="gemm mode (fp16x3 and bf16x6 hold the mixed class)")
     ap.add_argument("--form", default="abel", choices=["abel", "direct"],
                     help="gemm workload: Abel product + batched FFT, or the direct Legendre matrix")
     args = ap.parse_args()
@@ -560,6 +782,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "single_large":
         line = run_single_large(args)
+        print("[bench] single_large done", file=sys.stderr, flush=True)
+        if not args.main_only:
+            line["workloads"] = other_workloads(args)
     elif args.workload == "single_small":
         line = run_single_small(args)
     elif args.workload == "copy":

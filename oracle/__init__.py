@@ -11,15 +11,18 @@ code with the HIP library and imports nothing from it.
   c_n = (2n+1) a_n), long double, with a plain O(M N) Fourier sum; also the
   composite Abel rule (breakpoints, grading toward x = 1, per-row node
   counts).
-* :mod:`oracle.closed_forms` -- closed-form coefficients and Abel transforms
-  used to pin the two above.
+
+The closed-form coefficients and Abel transforms that pin the two modules
+above live with the tests (``tests/closed_forms.py``), not in this package.
 
 Pins (the tests under ``tests/test_oracle_*.py``): textbook Gauss-Legendre
 nodes, monomial exactness, f = P_m, the generating function eq. (2.2),
 e^{ax} through modified spherical Bessel functions, |x|^{3/2} against the
 True column of Table 1, reconstruction by eq. (2.1), mpmath brute-force
 quadrature of eq. (2.3) and eq. (2.14), polynomial exactness of the
-discretized method and its aliasing law.
+discretized method and its aliasing law, and the subset transform
+(eq. (2.4) at listed indices) and the [M/2][Q] sample builder against
+closed forms and an independent Gauss-Legendre routine.
 """
 from ._lib import build, load, threads  # noqa: F401
 from .definition import (gauss_legendre, legendre_coeffs,  # noqa: F401

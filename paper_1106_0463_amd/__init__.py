@@ -36,6 +36,18 @@ def _stream_handle(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+def _check_out(out, n: int, what: str, device=None) -> None:
+    """A caller-supplied output buffer must be a contiguous float64 CUDA
+    tensor of at least n elements (the kernels write n doubles into it),
+    on the device of the inputs when one is given."""
+    torch = _torch()
+    if (not isinstance(out, torch.Tensor) or out.dtype != torch.float64 or not out.is_cuda
+            or not out.is_contiguous() or out.numel() < int(n)):
+        raise ValueError(f"{what} must be a contiguous float64 CUDA tensor of at least {int(n)} elements")
+    if device is not None and out.device != device:
+        raise ValueError(f"{what} must be on {device}")
+
+
 def grid_size(M: int) -> int:
     """Effective y-grid size the library uses for a requested M."""
     out = C.c_int64()
@@ -122,8 +134,8 @@ class Plan:
             raise ValueError(f"f has {f.numel()} samples, plan expects {info['samples']}")
         if out is None:
             out = torch.empty(info["N"], dtype=torch.float64, device=f.device)
-        elif out.dtype != torch.float64 or out.numel() < info["N"] or not out.is_contiguous():
-            raise ValueError("out must be a contiguous float64 tensor of N elements")
+        else:
+            _check_out(out, info["N"], "out", f.device)
         check(self._lib.lc_execute(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr()),
                                    _stream_handle(stream)), "lc_execute")
         return out
@@ -177,6 +189,8 @@ class Plan2D(Plan):
         N = info["N"]
         if out is None:
             out = torch.empty((N, N), dtype=torch.float64, device=F.device)
+        else:
+            _check_out(out, N * N, "out", F.device)
         check(self._lib.lc_execute_2d(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(out.data_ptr()),
                                       _stream_handle(stream)), "lc_execute_2d")
         return out

@@ -6,7 +6,7 @@ import ctypes as C
 
 import numpy as np
 
-from . import Plan, _stream_handle, _view
+from . import Plan, _check_out, _stream_handle, _view
 from ._lib import PRECISIONS, check, load
 
 
@@ -36,10 +36,13 @@ class BatchPlan(Plan):
         (layout of :meth:`offsets`); returns the float64 coefficient arena."""
         import torch
         f_off, _, c_off = self.offsets()
-        if f_arena.numel() * f_arena.element_size() < f_off[-1] or not f_arena.is_cuda:
-            raise ValueError("f_arena too small or not on the GPU")
+        if (not isinstance(f_arena, torch.Tensor) or not f_arena.is_cuda or not f_arena.is_contiguous()
+                or f_arena.numel() * f_arena.element_size() < f_off[-1]):
+            raise ValueError(f"f_arena must be a contiguous CUDA tensor of at least {int(f_off[-1])} bytes")
         if c_arena is None:
             c_arena = torch.empty(int(c_off[-1]), dtype=torch.float64, device=f_arena.device)
+        else:
+            _check_out(c_arena, int(c_off[-1]), "c_arena", f_arena.device)
         check(self._lib.lc_execute_batch(self._h, C.c_void_p(f_arena.data_ptr()),
                                          C.c_void_p(c_arena.data_ptr()), _stream_handle(stream)),
               "lc_execute_batch")

@@ -4,7 +4,7 @@ from __future__ import annotations
 
 import ctypes as C
 
-from . import Plan, _stream_handle, _view
+from . import Plan, _check_out, _stream_handle, _view
 from ._lib import GEMM_MODES, check, load
 
 
@@ -35,6 +35,8 @@ class GemmPlan(Plan):
         B = F.shape[1]
         if out is None:
             out = torch.empty((B, N), dtype=torch.float64, device=F.device)
+        else:
+            _check_out(out, B * N, "out", F.device)
         check(self._lib.lc_execute_gemm(self._h, C.c_void_p(F.data_ptr()), int(B),
                                         C.c_void_p(out.data_ptr()), _stream_handle(stream)),
               "lc_execute_gemm")
@@ -44,15 +46,18 @@ class GemmPlan(Plan):
 LEGENDRE_MATRIX = 3  # lc_plan_kind of lc_plan_legendre_matrix plans
 
 
-def plan_gemm(P: int, M: int, N: int, mode: str = "bf16x3") -> GemmPlan:
-    """Abel product phi = A F, then the batched twist/FFT/rescale."""
+def plan_gemm(P: int, M: int, N: int, mode: str = "fp16x3") -> GemmPlan:
+    """Abel product phi = A F, then the batched twist/FFT/rescale.  The
+    default fp16x3 and bf16x6 hold E_a <= 1e-7 (the mixed class); bf16x3
+    and fp16x1 are faster and less accurate (outside that class)."""
     h = C.c_void_p()
     check(load().lc_plan_gemm(int(P), int(M), int(N), GEMM_MODES[mode], C.byref(h)), "lc_plan_gemm")
     return GemmPlan(h)
 
 
-def plan_legendre_matrix(P: int, M: int, N: int, mode: str = "bf16x3") -> GemmPlan:
-    """One product C = F^T Lmat^T with the FP64-built N x P Legendre matrix."""
+def plan_legendre_matrix(P: int, M: int, N: int, mode: str = "fp16x3") -> GemmPlan:
+    """One product C = F^T Lmat^T with the FP64-built N x P Legendre matrix
+    (modes and classes as in :func:`plan_gemm`)."""
     h = C.c_void_p()
     check(load().lc_plan_legendre_matrix(int(P), int(M), int(N), GEMM_MODES[mode], C.byref(h)),
           "lc_plan_legendre_matrix")

@@ -133,3 +133,71 @@ def phi_cos(omega: float, y) -> mp.mpf:
     z = 2 * mp.sin(y / 2) * mp.sqrt(w / mp.pi)
     cy = mp.cos(y)
     return mp.sqrt(mp.pi / w) * (mp.cos(w * cy) * mp.fresnelc(z) - mp.sin(w * cy) * mp.fresnels(z))
+
+
+def exp_coeffs_fast(a: float, N: int) -> np.ndarray:
+    """The coefficients of :func:`exp_coeffs` in float64 for large N:
+    c_n = (2n+1) sgn(a)^n i_n(|a|), with i_n by Miller's backward
+    recurrence i_{n-1}(z) = i_{n+1}(z) + (2n+1)/z i_n(z) (stable downward:
+    i_n is the recurrence's minimal solution) in long double, normalised by
+    i_0(z) = sinh(z)/z.  Values below the float64 range come out as 0; the
+    start index lies 60 above the last index kept (at most 600: beyond it
+    every c_n with |a| <= 40 is far below 1e-300)."""
+    N = int(N)
+    out = np.zeros(N, dtype=np.float64)
+    if a == 0:
+        out[0] = 1.0
+        return out
+    z = np.longdouble(abs(a))
+    top = min(N - 1, 600)
+    start = top + 60 + int(abs(a))
+    vals = np.zeros(top + 1, dtype=np.longdouble)
+    big = np.longdouble("1e4000")
+    ip1, i = np.longdouble(0), np.longdouble("1e-4000")
+    for n in range(start, 0, -1):
+        im1 = ip1 + (2 * n + 1) / z * i
+        if n - 1 <= top:
+            vals[n - 1] = im1
+        ip1, i = i, im1
+        if i > big:                         # rescale (long double range)
+            ip1 /= big
+            i /= big
+            vals /= big
+    i0 = np.sinh(z) / z
+    vals *= i0 / vals[0]
+    n = np.arange(top + 1)
+    sgn = np.where((a > 0) | (n % 2 == 0), 1.0, -1.0)
+    out[:top + 1] = ((2 * n + 1) * vals).astype(np.float64) * sgn
+    return out
+
+
+def exp_coeffs_many(a, top: int = 600) -> np.ndarray:
+    """:func:`exp_coeffs_fast` for many exponents at once: row k holds
+    c_0..c_top of e^{a_k x} (|a_k| <= 40), the same backward recurrence run
+    on all rows together in long double."""
+    a = np.asarray(a, dtype=np.float64)
+    z = np.abs(a).astype(np.longdouble)
+    zs = np.where(z == 0, np.longdouble(1), z)
+    big = np.longdouble("1e4000")
+    start = top + 60 + 40
+    vals = np.zeros((a.size, top + 1), dtype=np.longdouble)
+    ip1 = np.zeros(a.size, dtype=np.longdouble)
+    i = np.full(a.size, np.longdouble("1e-4000"))
+    for n in range(start, 0, -1):
+        im1 = ip1 + (2 * n + 1) / zs * i
+        if n - 1 <= top:
+            vals[:, n - 1] = im1
+        ip1, i = i, im1
+        hot = i > big
+        if np.any(hot):
+            ip1[hot] /= big
+            i[hot] /= big
+            vals[hot] /= big
+    i0 = np.sinh(zs) / zs
+    vals *= (i0 / vals[:, 0])[:, None]
+    n = np.arange(top + 1)
+    sgn = np.where((a[:, None] > 0) | (n[None, :] % 2 == 0), 1.0, -1.0)
+    out = ((2 * n + 1)[None, :] * vals).astype(np.float64) * sgn
+    out[z == 0] = 0.0
+    out[z == 0, 0] = 1.0
+    return out

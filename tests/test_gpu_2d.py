@@ -81,3 +81,40 @@ def test_2d_fp32_samples(lc):
     E_a = np.max(np.abs((c32 - c64) / scale)) / np.max(np.abs(c64 / scale))
     banner(f"    E_a {E_a:.2e}")
     assert E_a <= 1e-7
+
+
+def test_2d_bench_size(lc):
+    # the benchmark's size N = 256, M = 1024, Q = 32 (S = 16384 nodes per
+    # axis, 2.7e8 samples), element by element:
+    #  * a rank-two separable f: the method is linear and acts on each axis
+    #    alone, so its 2-D result is the sum of outer products of the 1-D
+    #    method oracle's coefficients at the same (N, M, Q);
+    #  * the benchmark's f = exp(x1 x2) + x1^2 cos(3 x2) against eq. (2.3)
+    #    along both axes (a 304-point long-double Gauss-Legendre rule per axis)
+    import torch
+    from helpers import expected_grid
+    N, M, Q = 256, 1024, 32
+    Me = expected_grid(M)
+    banner(f"[gpu] 2-D plan at the benchmark size N={N} M={M} Q={Q}")
+    g1, h1 = W.Exponential(0.9), W.GeneratingFunction(0.4)
+    g2, h2 = W.Cosine(3.0), W.Exponential(-1.7)
+    f2 = lambda x1, x2: g1.torch(x1) * h1.torch(x2) + g2.torch(x1) * h2.torch(x2)
+    got, info = _run(lc, N, M, Q, f2)
+    assert info["H"] * info["Q"] == 16384
+    cm = {k: np.array(oracle.method_coeffs(f, N, Me, Q, fp64_nodes=True), dtype=float)
+          for k, f in (("g1", g1), ("h1", h1), ("g2", g2), ("h2", h2))}
+    ref = np.outer(cm["g1"], cm["h1"]) + np.outer(cm["g2"], cm["h2"])
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    banner(f"    separable: rel err {err:.2e} vs the 1-D method oracle")
+    assert err <= 1e-13
+    got, _ = _run(lc, N, M, Q, _f2_torch)
+    K = N + 48
+    x, w = oracle.gauss_legendre(K)
+    xl = x.astype(np.longdouble)
+    Fk = np.exp(xl[:, None] * xl[None, :]) + xl[:, None] ** 2 * np.cos(3 * xl[None, :])  # [k1][k2]
+    step1 = np.stack([oracle.legendre_coeffs_from_samples(x, w, Fk[:, k], N) for k in range(K)], axis=1)
+    ref = np.stack([oracle.legendre_coeffs_from_samples(x, w, step1[n, :], N) for n in range(N)], axis=0)
+    ref = np.asarray(ref, dtype=float)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    banner(f"    exp(x1 x2) + x1^2 cos(3 x2): rel err {err:.2e} vs eq. (2.3) along both axes")
+    assert err <= 1e-12

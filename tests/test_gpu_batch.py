@@ -160,33 +160,63 @@ def test_uneven_series_resolving_q_exact(lc):
 
 
 def test_uneven_series_full_batch_stated_q(lc):
-    # the full 4096-function batch at the stated Q = 48 (under-resolving):
-    # arithmetic parity on a seeded subset of small functions against the
-    # method oracle at the same discretization and the same FP64 nodes
+    # The full 4096-function batch at the stated Q = 48 (under-resolving), in
+    # the launch the benchmark times: executed on a side stream, so the
+    # captured graph runs (first call captures, the second replays).
+    # Arithmetic parity on 64 seeded members, the longest (N_b = 8191, an FFT
+    # of 8192 points in LDS) and the shortest among them, against the method
+    # oracle.  Those members are sampled at the oracle's own nodes (rounded
+    # to FP64) and the same samples go to both sides, so the comparison is
+    # arithmetic only.
     import torch
     from workloads.gpu import series_ragged
-    banner("[gpu] uneven series batch B=4096, Q=48")
+    banner("[gpu] uneven series batch B=4096, Q=48: 64 members through the captured graph")
     sb = W.batch_uneven(B=4096)
     bp = lc.plan_batch(sb.N, sb.M, sb.Q, "fp64")
     f_off, x_off, c_off = bp.offsets()
     arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
     series_ragged(sb.coeffs, bp.nodes, x_off, arena, f_off, np.zeros(4096, dtype=np.int32))
-    c = bp.execute(arena)
-    torch.cuda.synchronize()
-    c = c.cpu().numpy()
+    rng = np.random.default_rng(35)
+    pick = set(rng.choice(4096, 62, replace=False).tolist())
+    pick |= {int(np.argmax(sb.N)), int(np.argmin(sb.N))}
+    pick = np.array(sorted(pick))
+    assert pick.size == 64 and max(expected_grid(int(m)) // 4 for m in sb.M[pick]) == 8192
+    # oracle nodes of the picked members, sampled by the input generator
+    Heff = [expected_grid(int(sb.M[b])) // 2 for b in pick]
+    xo = np.zeros(pick.size + 1, dtype=np.int64)
+    xo[1:] = np.cumsum([h * 48 for h in Heff])
+    xs = torch.empty(int(xo[-1]), dtype=torch.float64, device="cuda")
+    for k, b in enumerate(pick):
+        X = oracle.abel_node_set(expected_grid(int(sb.M[b])), 48).astype(np.float64).reshape(-1)
+        xs[int(xo[k]):int(xo[k + 1])] = torch.from_numpy(X).cuda()
+    fo = xo * 8
+    tmp = torch.zeros(int(fo[-1]), dtype=torch.uint8, device="cuda")
+    series_ragged([sb.coeffs[b] for b in pick], xs, xo, tmp, fo, np.zeros(pick.size, dtype=np.int32))
+    for k, b in enumerate(pick):
+        arena[int(f_off[b]):int(f_off[b]) + int(fo[k + 1] - fo[k])] = tmp[int(fo[k]):int(fo[k + 1])]
+    samples = tmp.view(torch.float64).cpu().numpy()
+    del tmp, xs
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        c1 = bp.execute(arena, stream=s)
+        c2 = torch.full_like(c1, float("nan"))
+        bp.execute(arena, c2, stream=s)
+        s.synchronize()
+    assert torch.equal(c1, c2)
+    c = c2.cpu().numpy()
     bp.destroy()
-    del arena
+    del arena, c1, c2
     torch.cuda.empty_cache()
-    small = np.where(sb.N <= 400)[0]
-    pick = np.random.default_rng(35).choice(small, 4, replace=False)
-    for b in pick:
-        n, m = int(sb.N[b]), int(sb.M[b])
-        f = W.LegendreSeries(sb.coeffs[b])
-        ref = np.array(oracle.method_coeffs(f, n, expected_grid(m), 48, fp64_nodes=True), dtype=float)
+    worst = 0.0
+    for k, b in enumerate(pick):
+        n, Me, H = int(sb.N[b]), expected_grid(int(sb.M[b])), Heff[k]
+        sk = samples[int(xo[k]):int(xo[k + 1])].reshape(H, 48)
+        ref = np.array(oracle.method_coeffs_from_samples(sk, n, Me, 48), dtype=float)
         got = c[c_off[b]:c_off[b + 1]]
         err = rel_err(got, ref)
-        banner(f"    fn {b} N={n}: rel err {err:.2e}; vs truth {rel_err(got, sb.coeffs[b]):.2e}")
-        assert err <= TOL
+        worst = max(worst, err)
+        assert err <= TOL, (int(b), n, err)
+    banner(f"    64 members (N_b {int(sb.N[pick].min())}..{int(sb.N[pick].max())}): worst rel err {worst:.2e}")
 
 
 @pytest.mark.parametrize("parts", [1, 2])

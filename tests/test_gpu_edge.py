@@ -118,3 +118,51 @@ def test_fixed_grid_tiny(lc, kind):
     ref[:, :21] = coef
     n = np.arange(40)
     assert rel_err(C / (2 * n + 1), ref / (2 * n + 1)) <= 1e-7
+
+
+def test_output_buffers_validated_before_launch(lc):
+    # a wrong dtype, a short buffer, a strided view or a host tensor as the
+    # output of any execute raises ValueError before anything is launched;
+    # the buffer is left untouched
+    import torch
+    banner("[gpu] output buffers: dtype, size, contiguity and device checked")
+    f = W.Exponential(0.5)
+    p = lc.plan(20, 64, 8)
+    fx = f.torch(p.nodes).contiguous()
+    bad = [torch.zeros(20, dtype=torch.float32, device="cuda"),
+           torch.zeros(19, dtype=torch.float64, device="cuda"),
+           torch.zeros(40, dtype=torch.float64, device="cuda")[::2],
+           torch.zeros(20, dtype=torch.float64)]
+    for out in bad:
+        with pytest.raises(ValueError):
+            p.execute(fx, out)
+    p.destroy()
+    p2 = lc.plan_2d(4, 16, 3)
+    X = p2.nodes.reshape(-1)
+    F2 = torch.exp(X[None, :] * X[:, None]).contiguous()
+    for out in (torch.zeros(15, dtype=torch.float64, device="cuda"),
+                torch.zeros(16, dtype=torch.float32, device="cuda")):
+        with pytest.raises(ValueError):
+            p2.execute(F2, out)
+        assert int(torch.count_nonzero(out)) == 0
+    p2.destroy()
+    bp = lc.plan_batch([5, 9], [16, 40], [4, 6], "fp64")
+    f_off, _, c_off = bp.offsets()
+    arena = torch.zeros(int(f_off[-1]), dtype=torch.uint8, device="cuda")
+    for out in (torch.zeros(int(c_off[-1]) - 1, dtype=torch.float64, device="cuda"),
+                torch.zeros(int(c_off[-1]), dtype=torch.float32, device="cuda")):
+        with pytest.raises(ValueError):
+            bp.execute(arena, out)
+        assert int(torch.count_nonzero(out)) == 0
+    with pytest.raises(ValueError):
+        bp.execute(arena[: int(f_off[-1]) - 8])
+    bp.destroy()
+    from workloads.gpu import series_grid
+    g = lc.plan_gemm(32, 64, 16, "fp16x3")
+    F = series_grid(W.gemm_batch_coeffs(3, 10, seed=13), g.nodes)
+    for out in (torch.zeros((3, 15), dtype=torch.float64, device="cuda"),
+                torch.zeros((3, 16), dtype=torch.float32, device="cuda")):
+        with pytest.raises(ValueError):
+            g.execute(F, out)
+        assert int(torch.count_nonzero(out)) == 0
+    g.destroy()

@@ -77,7 +77,19 @@ def test_gemm_fp64_exact(lc):
     assert E_c <= 1e-12
 
 
-@pytest.mark.parametrize("mode,bound", [("bf16x6", 1e-7), ("fp16x3", 1e-7), ("bf16x3", 5e-7), ("fp16x1", 1e-3)])
+# bf16x3 (two 8-bit-mantissa pieces per operand) and fp16x1 are outside the
+# mixed class E_a <= 1e-7: their representation error alone reaches ~1.2e-7
+# and ~1e-5 at full size.  They are built and tested to their own bounds,
+# with "out_of_class" in the test id, and are never quoted as mixed class.
+OUT_OF_CLASS = {"bf16x3", "fp16x1"}
+
+
+def _mode_param(mode, *bounds):
+    return pytest.param(mode, *bounds, id=f"{mode}-out_of_class" if mode in OUT_OF_CLASS else mode)
+
+
+@pytest.mark.parametrize("mode,bound", [_mode_param("bf16x6", 1e-7), _mode_param("fp16x3", 1e-7),
+                                        _mode_param("bf16x3", 5e-7), _mode_param("fp16x1", 1e-3)])
 def test_gemm_split_modes(lc, mode, bound):
     banner(f"[gpu] gemm {mode}")
     C, coef = _run(lc, mode, 1024, 2048, 1024, 256, 700)
@@ -184,8 +196,10 @@ def test_legendre_matrix_fp64_exact(lc):
 # which their 16-bit representation limits anyway); its error is then relative to max|c| as well:
 # E_c bounds hold for the three- and six-product modes (the Abel form's E_c
 # is ~1e-4 at these sizes).
-@pytest.mark.parametrize("mode,bound_a,bound_c", [("bf16x6", 1e-7, 1e-6), ("fp16x3", 1e-7, 1e-6),
-                                                  ("bf16x3", 5e-7, 1e-4), ("fp16x1", 1e-3, 1.0)])
+@pytest.mark.parametrize("mode,bound_a,bound_c", [_mode_param("bf16x6", 1e-7, 1e-6),
+                                                  _mode_param("fp16x3", 1e-7, 1e-6),
+                                                  _mode_param("bf16x3", 5e-7, 1e-4),
+                                                  _mode_param("fp16x1", 1e-3, 1.0)])
 def test_legendre_matrix_split_modes(lc, mode, bound_a, bound_c):
     banner(f"[gpu] legendre matrix {mode}")
     C, coef = _run_direct(lc, mode, 1024, 2048, 1024, 256, 700)

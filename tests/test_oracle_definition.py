@@ -183,3 +183,27 @@ def test_planted_mistakes_are_caught():
     ref = 0.5 ** np.arange(8)
     assert np.max(np.abs(c - ref)) < 1e-16
     assert np.max(np.abs(c / (np.arange(8) + 0.5) - ref)) > 0.1
+
+
+@pytest.mark.parametrize("a", [-20.0, -3.5, 0.7, 13.0, 20.0])
+def test_exp_closed_form_fast_matches_mpmath(a):
+    # the float64 backward-recurrence closed form of e^{ax} used for long
+    # coefficient vectors, against mpmath's Bessel function I_{n+1/2}
+    from closed_forms import exp_coeffs, exp_coeffs_fast
+    N = 90
+    ref = np.array([float(v) for v in exp_coeffs(a, N)])
+    got = exp_coeffs_fast(a, N)
+    assert np.max(np.abs(got - ref)) <= 2e-16 * np.max(np.abs(ref))
+    nz = np.abs(ref) > 1e-280
+    assert np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz])) <= 1e-14
+    long = exp_coeffs_fast(a, 70000)
+    assert np.array_equal(long[:N], got) and np.all(long[700:] == 0.0)
+
+
+def test_exp_closed_form_many_matches_single():
+    from closed_forms import exp_coeffs_fast, exp_coeffs_many
+    a = np.array([-20.0, -7.25, -0.3, 0.0, 1.0, 19.99])
+    many = exp_coeffs_many(a, top=200)
+    for k, ak in enumerate(a):
+        one = exp_coeffs_fast(ak, 201)
+        assert np.max(np.abs(many[k] - one)) <= 4e-16 * np.max(np.abs(one)), ak

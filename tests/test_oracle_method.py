@@ -131,3 +131,83 @@ def test_planted_twist_sign_is_caught():
     e = np.zeros(M // 2)
     e[m] = 1.0
     assert np.max(np.abs(c - e)) > 0.1
+
+
+# ---------------------------------------------------------------------------
+# The subset transform (eq. (2.4) evaluated only at listed indices n) and the
+# sample builder of the [M/2][Q] layout.  Both feed full-size GPU parity
+# tests, so each is pinned to closed forms, not only to the full transform.
+
+@pytest.mark.parametrize("m,M", [(0, 16), (7, 64), (40, 256)])
+def test_subset_transform_of_legendre_is_delta(m, M):
+    # exact phi of P_m through eq. (2.5), then the trapezoid form of eq. (2.4)
+    # at listed indices only: c_n = delta_{nm} (no aliasing for n + m + 1 < M)
+    y = oracle.y_grid(M)
+    phi = np.array([phi_legendre(m, float(abs(v))) for v in y], dtype=float).astype(LD)
+    fh = oracle.fhat_from_phi(phi, y)
+    H = M // 2
+    idx = np.array(sorted({0, 1, m, max(0, m - 1), m + 1, H - 2, H - 1}), dtype=np.int64)
+    a = oracle.fourier_coeffs_at(fh, idx)
+    c = np.array((2 * idx.astype(LD) + 1) * a.real, dtype=float)
+    assert np.max(np.abs(c - (idx == m))) < 1e-14
+    assert float(np.max(np.abs(a.imag))) < 1e-16
+
+
+def test_subset_transform_equals_full_transform():
+    # the subset sum at indices 0, N-1 and both parities equals the full sum
+    M, N = 200, 100
+    f = W.Exponential(-2.5)
+    fh = oracle.abel_fhat(f, oracle.y_grid(M), 24)
+    full = oracle.fourier_coeffs(fh, N)
+    idx = np.array([0, 1, 2, 37, 50, 98, N - 1], dtype=np.int64)
+    sub = oracle.fourier_coeffs_at(fh, idx)
+    assert np.max(np.abs(np.asarray(sub - full[idx], dtype=complex))) <= 1e-18
+
+
+def test_method_coeffs_at_generating_function_closed_form():
+    # t = 0.6 resolved by (M, Q): c_n = t^n (eq. (2.2)) at sampled indices
+    t, M, Q = 0.6, 512, 48
+    idx = np.array([0, 1, 2, 3, 10, 21, 40, 63, 255], dtype=np.int64)
+    got = np.array(oracle.method_coeffs_at(W.GeneratingFunction(t), idx, M, Q), dtype=float)
+    assert np.max(np.abs(got - t ** idx.astype(float))) < 5e-16
+    full = oracle.method_coeffs(W.GeneratingFunction(t), 256, M, Q)
+    assert np.max(np.abs(np.asarray(oracle.method_coeffs_at(W.GeneratingFunction(t), idx, M, Q)
+                                    - full[idx], dtype=float))) <= 1e-18
+
+
+def test_positive_half_samples_layout():
+    # f(x) = x returns the nodes themselves: row j-1 holds y = pi j / H,
+    # column q the q-th largest positive node T_q of the 2Q-point
+    # Gauss-Legendre rule (numpy's leggauss here, an independent routine),
+    # x = cos y + (1 - cos y) T_q^2 rounded to FP64
+    M, Q = 40, 6
+    H = M // 2
+    s = oracle.positive_half_samples(lambda x: x, M, Q)
+    assert s.shape == (H, Q) and s.dtype == np.float64
+    T = np.sort(npleg.leggauss(2 * Q)[0])[::-1][:Q]
+    y = np.pi * np.arange(1, H + 1) / H
+    ref = np.cos(y)[:, None] + (1 - np.cos(y))[:, None] * T[None, :] ** 2
+    assert np.max(np.abs(s - ref)) < 4e-16
+
+
+@pytest.mark.parametrize("D,N", [(21, 16), (40, 32)])
+def test_positive_half_samples_exact_polynomial(D, N):
+    # samples of a degree-D series through the folded rule (2Q-1 >= D) and
+    # the trapezoid (M >= N + D + 1) return its own coefficients
+    coef = np.random.default_rng(100 + D).standard_normal(D + 1)
+    f = W.LegendreSeries(coef)
+    Q = (D + 1) // 2 + 1
+    M = N + D + 2 + ((N + D) % 2)
+    s = oracle.positive_half_samples(f, M, Q)
+    c = np.array(oracle.method_coeffs_from_samples(s, N, M, Q), dtype=float)
+    assert np.max(np.abs(c - coef[:N])) < 2e-14
+
+
+def test_positive_half_samples_match_method_fp64_nodes():
+    # the samples path equals the method with FP64-rounded nodes
+    M, Q, N = 256, 20, 100
+    f = W.Sum(W.GeneratingFunction(0.8), W.Exponential(3.0))
+    s = oracle.positive_half_samples(f, M, Q)
+    a = np.array(oracle.method_coeffs_from_samples(s, N, M, Q), dtype=float)
+    b = np.array(oracle.method_coeffs(f, N, M, Q, fp64_nodes=True), dtype=float)
+    assert np.max(np.abs(a - b)) < 1e-15 * np.max(np.abs(b))
