@@ -202,6 +202,28 @@ lc_status lc_plan_nodes(lc_plan_t plan, const double **x_dev, int64_t *rows, int
  * LC_ERR_HIP (launch failure). */
 lc_status lc_execute(lc_plan_t plan, const void *f_dev, double *c_dev, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * execute call of a single plan (lc_plan or lc_plan_adaptive) whose
+ * workspace -- phi[H] and, when H/2 > 8192, two four-step buffers of H/2
+ * complex values -- lives in one static device array of the library
+ * (LC_NOALLOC_SCRATCH_BYTES per device, held from the first call on that
+ * device until the process ends) instead of the plan's workspace.  Same
+ * arguments, kernels and results (bit for bit) as lc_execute; it calls no
+ * allocation routine and records no timing events.  The plan needs
+ * 8 H bytes (H/2 <= 8192) or 8 H + 32 (H/2) bytes, each part rounded up to
+ * 256 bytes; larger plans are rejected.  The current device must be the
+ * plan's.  Every call on one device shares that device's array: calls that
+ * overlap in time on one device (two streams, or two threads) race and give
+ * wrong results; calls ordered on one stream are safe.  Nothing in the
+ * array needs clearing between calls (every value is written before it is
+ * read).
+ * Errors: LC_ERR_INVALID (as lc_execute; a plan larger than the array; the
+ * current device is not the plan's), LC_ERR_HIP (symbol lookup or launch
+ * failure), LC_ERR_UNSUPPORTED (device ordinal >= 64). */
+#define LC_NOALLOC_SCRATCH_BYTES (8u << 20)
+lc_status lc_execute_noalloc(lc_plan_t plan, const void *f_dev, double *c_dev, hipStream_t stream);
+
 /* Batched plan for B independent functions of uneven sizes (N[b], M[b],
  * Q[b], prec[b], host arrays of length B, each entry validated as in
  * lc_plan).  Samples live in one device arena (byte offsets f_off, every

@@ -140,6 +140,22 @@ class Plan:
                                    _stream_handle(stream)), "lc_execute")
         return out
 
+    def execute_noalloc(self, f, out, stream=None):
+        """lc_execute_noalloc: as ``execute`` with the workspace in the
+        library's static device array; ``out`` (N float64 values) is
+        required, so that nothing is allocated."""
+        torch = _torch()
+        info = self.info
+        want = torch.float64 if info["precision"] == LC_FP64 else torch.float32
+        if f.dtype != want or not f.is_cuda or not f.is_contiguous():
+            raise ValueError(f"f must be a contiguous {want} CUDA tensor")
+        if f.numel() != info["samples"]:
+            raise ValueError(f"f has {f.numel()} samples, plan expects {info['samples']}")
+        _check_out(out, info["N"], "out", f.device)
+        check(self._lib.lc_execute_noalloc(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr()),
+                                           _stream_handle(stream)), "lc_execute_noalloc")
+        return out
+
     def set_timing(self, enable: bool = True) -> None:
         check(self._lib.lc_plan_set_timing(self._h, 1 if enable else 0), "lc_plan_set_timing")
 

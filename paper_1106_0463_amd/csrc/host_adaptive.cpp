@@ -277,6 +277,11 @@ lc_status nodes_adaptive(lc_plan_s *p, const double **x, int64_t *rows, int32_t 
     return LC_OK;
 }
 
+// The plan's reduction launches writing phi[H] to the given buffer.
+hipError_t adaptive_reduce(const lc_plan_s *p, const void *f, double *phi, hipStream_t s) {
+    return launch_reductions((const AdaptiveState *)p->ext, p->fn.prec, f, p->s2, phi, s);
+}
+
 lc_status execute_adaptive(lc_plan_s *p, const void *f, double *c, hipStream_t s) {
     const AdaptiveState *a = (const AdaptiveState *)p->ext;
     const FnDesc &d = p->fn;

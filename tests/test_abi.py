@@ -81,6 +81,7 @@ def test_plan_rejects_invalid(args):
 def test_null_arguments_rejected(lib):
     assert lib.lc_plan(8, 256, 32, 0, None) == 1
     assert lib.lc_execute(None, None, None, None) == 1
+    assert lib.lc_execute_noalloc(None, None, None, None) == 1
     assert lib.lc_plan_info(None, None) == 1
     assert lib.lc_plan_destroy(None) == 0
     assert "null" in lib.lc_last_error().decode() or lib.lc_last_error().decode() != ""
