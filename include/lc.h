@@ -194,6 +194,18 @@ lc_status lc_plan_info(lc_plan_t plan, lc_plan_desc *desc);
  * rows / Q may be null.  Errors: LC_ERR_INVALID. */
 lc_status lc_plan_nodes(lc_plan_t plan, const double **x_dev, int64_t *rows, int32_t *Q);
 
+/* Complements of the nodes: writes 1 - x for every node of a single,
+ * adaptive or batch plan into omx_dev (device FP64, the node array's layout
+ * and length: H*Q, the sample count, or the node arena), each the FP64 value
+ * nearest 2 s_j^2 (1 - t^2) (computed in double-double).  Near x = 1 the
+ * FP64 node x carries an absolute rounding error of up to 2^-53 that is
+ * large relative to 1 - x; a caller sampling f with a singularity just
+ * beyond x = 1 (e.g. (1 - 2xt + t^2)^{-1/2} = ((1-t)^2 + 2t(1-x))^{-1/2} with
+ * t near 1) evaluates f from 1 - x instead, at the same node.  Asynchronous
+ * on stream.  Errors: LC_ERR_INVALID (null argument), LC_ERR_UNSUPPORTED
+ * (other plan kinds), LC_ERR_HIP. */
+lc_status lc_plan_nodes_complement(lc_plan_t plan, double *omx_dev, hipStream_t stream);
+
 /* Executes a single plan: f_dev is the device array of samples f[H][Q]
  * (FP64, or FP32 for LC_FP32_QUAD), c_dev a device array of N doubles that
  * receives c_0..c_{N-1}.  Asynchronous on stream (0 = null stream); no
@@ -233,6 +245,27 @@ lc_status lc_execute_noalloc(lc_plan_t plan, const void *f_dev, double *c_dev, h
  * replayed afterwards.  Errors: LC_ERR_INVALID, LC_ERR_NOMEM, LC_ERR_HIP. */
 lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int32_t *Q,
                         const lc_precision *prec, lc_plan_t *out);
+
+/* Batched plan with a composite Abel rule per function (the remarks after
+ * eq. (2.14): a change of variable and Gauss-Legendre panels), for batches
+ * that mix smooth functions with functions singular just beyond x = 1
+ * (e.g. the generating function eq. (2.2) with t near 1).  rules[b] follows
+ * lc_abel_rule with the batch's restriction that every row has the same
+ * panels: band = 0 and nbreak = 0 (LC_ERR_UNSUPPORTED otherwise); grading
+ * (grade_ratio, grade_levels) and the node count q are free per function,
+ * except that every cut grade_ratio^k must be kept by the cut rule of
+ * lc_abel_rule (none at or below 1e-15, none merged: LC_ERR_INVALID
+ * otherwise).  Function b has R_b = (grade_levels + 1) * (q rounded up to a
+ * multiple of 4) samples per row (grade_levels = 0 when grade_ratio = 0), in the
+ * row layout of lc_plan_adaptive with the same rule (panels by increasing t,
+ * each padded to a multiple of 4 with the last node repeated at weight 0),
+ * rows j = 1..M_eff/2 in order: [H_b][R_b].  Everything else -- arenas,
+ * offsets (lc_plan_batch_offsets), nodes (lc_plan_nodes), execution
+ * (lc_execute_batch), autotuning, timing -- is that of lc_plan_batch.
+ * Limits: those of lc_plan_batch with Q = R_b <= 65536.
+ * Errors: LC_ERR_INVALID, LC_ERR_UNSUPPORTED, LC_ERR_NOMEM, LC_ERR_HIP. */
+lc_status lc_plan_batch_rules(int32_t B, const int64_t *N, const int64_t *M, const lc_abel_rule *rules,
+                              const lc_precision *prec, lc_plan_t *out);
 
 /* Host copies of the batch layout, each array of length B+1 (may be null):
  * f_off  byte offset of function b's samples in the f arena (f_off[B] =

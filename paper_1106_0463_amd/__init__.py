@@ -20,7 +20,7 @@ import ctypes as C
 from ._lib import (GEMM_MODES, LC_FP32_QUAD, LC_FP64, PRECISIONS, LCError,  # noqa: F401
                    PlanDesc, check, load)
 
-__all__ = ["grid_size", "plan", "plan_2d", "plan_adaptive", "plan_batch", "plan_gemm", "plan_legendre_matrix",
+__all__ = ["grid_size", "plan", "plan_2d", "plan_adaptive", "plan_batch", "plan_batch_rules", "plan_gemm", "plan_legendre_matrix",
            "Plan", "Plan2D", "LCError"]
 
 
@@ -121,6 +121,16 @@ class Plan:
             return _view(ptr.value, (rows.value, q.value), self)
         return _view(ptr.value, (rows.value,), self)
 
+    def nodes_complement(self, stream=None):
+        """1 - x for every node (lc_plan_nodes_complement), a float64 CUDA
+        tensor shaped like :attr:`nodes` (single, adaptive and batch plans)."""
+        torch = _torch()
+        x = self.nodes
+        out = torch.empty_like(x)
+        check(self._lib.lc_plan_nodes_complement(self._h, C.c_void_p(out.data_ptr()), _stream_handle(stream)),
+              "lc_plan_nodes_complement")
+        return out
+
     # -- execution ----------------------------------------------------
     def execute(self, f, out=None, stream=None):
         """c_0..c_{N-1} from samples f[H][Q] (float64, or float32 for an
@@ -219,5 +229,5 @@ def plan_2d(N: int, M: int, Q: int, precision: str = "fp64") -> Plan2D:
     return Plan2D(h)
 
 
-from .batch import BatchPlan, plan_batch  # noqa: E402,F401
+from .batch import BatchPlan, plan_batch, plan_batch_rules, rule_row_length  # noqa: E402,F401
 from .gemm import GemmPlan, plan_gemm, plan_legendre_matrix  # noqa: E402,F401

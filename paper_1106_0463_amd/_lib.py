@@ -42,9 +42,12 @@ SIGNATURES = [
     ("lc_execute_2d", C.c_int, [_vp, _vp, _vp, _vp]),
     ("lc_plan_info", C.c_int, [_vp, C.POINTER(PlanDesc)]),
     ("lc_plan_nodes", C.c_int, [_vp, C.POINTER(_vp), _pi64, _pi32]),
+    ("lc_plan_nodes_complement", C.c_int, [_vp, _vp, _vp]),
     ("lc_execute", C.c_int, [_vp, _vp, _vp, _vp]),
     ("lc_execute_noalloc", C.c_int, [_vp, _vp, _vp, _vp]),
     ("lc_plan_batch", C.c_int, [_i32, _pi64, _pi64, _pi32, C.POINTER(C.c_int), C.POINTER(_vp)]),
+    ("lc_plan_batch_rules", C.c_int, [_i32, _pi64, _pi64, C.POINTER(AbelRule), C.POINTER(C.c_int),
+                                      C.POINTER(_vp)]),
     ("lc_plan_batch_offsets", C.c_int, [_vp, _pi64, _pi64, _pi64]),
     ("lc_execute_batch", C.c_int, [_vp, _vp, _vp, _vp]),
     ("lc_plan_gemm", C.c_int, [_i32, _i64, _i64, C.c_int, C.POINTER(_vp)]),

@@ -67,3 +67,35 @@ def plan_batch(N, M, Q, precision) -> BatchPlan:
                                Q.ctypes.data_as(C.POINTER(C.c_int32)),
                                pr.ctypes.data_as(C.POINTER(C.c_int)), C.byref(h)), "lc_plan_batch")
     return BatchPlan(h)
+
+
+def rule_row_length(rule: dict) -> int:
+    """Samples per row R of a batch rule (lc_plan_batch_rules):
+    (grade_levels + 1) * (q rounded up to a multiple of 4)."""
+    q = int(rule["q"])
+    levels = int(rule.get("grade_levels", 0)) if float(rule.get("grade_ratio", 0.0)) > 0 else 0
+    return (levels + 1) * ((q + 3) // 4 * 4)
+
+
+def plan_batch_rules(N, M, rules, precision) -> BatchPlan:
+    """N, M: integer sequences of length B; rules: sequence of dicts with
+    keys q, grade_ratio, grade_levels (lc_abel_rule without band or
+    breakpoints); precision: sequence of 'fp64' / 'fp32' (or one string)."""
+    from ._lib import AbelRule
+    N = np.ascontiguousarray(N, dtype=np.int64)
+    M = np.ascontiguousarray(M, dtype=np.int64)
+    B = N.size
+    if isinstance(precision, str):
+        precision = [precision] * B
+    pr = np.ascontiguousarray([PRECISIONS[p] for p in precision], dtype=np.int32)
+    if not (M.size == len(rules) == pr.size == B):
+        raise ValueError("N, M, rules, precision must have one length")
+    arr = (AbelRule * B)()
+    for b, r in enumerate(rules):
+        arr[b] = AbelRule(int(r["q"]), int(r.get("q_max", 0)), float(r.get("band", 0.0)), 0, None,
+                          float(r.get("grade_ratio", 0.0)), int(r.get("grade_levels", 0)))
+    h = C.c_void_p()
+    check(load().lc_plan_batch_rules(int(B), N.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     M.ctypes.data_as(C.POINTER(C.c_int64)), arr,
+                                     pr.ctypes.data_as(C.POINTER(C.c_int)), C.byref(h)), "lc_plan_batch_rules")
+    return BatchPlan(h)

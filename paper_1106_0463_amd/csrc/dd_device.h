@@ -19,6 +19,16 @@ __device__ __forceinline__ double node_dd(double2 a, double2 b) {
     return s + (err - e);
 }
 
+// a b for double-double a, b, rounded to FP64 (the complement 1 - x of the
+// node node_dd(a, b)).
+__device__ __forceinline__ double omx_dd(double2 a, double2 b) {
+#pragma clang fp contract(off)
+    const double p = a.x * b.x;
+    double e = fma(a.x, b.x, -p);
+    e = fma(a.x, b.y, fma(a.y, b.x, e));
+    return p + e;
+}
+
 __device__ __forceinline__ double2 dd_quick_two_sum(double a, double b) {
 #pragma clang fp contract(off)
     const double s = a + b;

@@ -543,6 +543,8 @@ void info_gemm(lc_plan_s *p, lc_plan_desc *d);
 void info_adaptive(lc_plan_s *p, lc_plan_desc *d);
 void info_2d(lc_plan_s *p, lc_plan_desc *d);
 lc_status nodes_batch(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
+hipError_t adaptive_complement(const lc_plan_s *p, double *comp, hipStream_t s);
+hipError_t batch_complement(const lc_plan_s *p, double *comp, hipStream_t s);
 lc_status nodes_gemm(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
 lc_status nodes_adaptive(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
 lc_status nodes_2d(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q);
@@ -586,6 +588,22 @@ lc_status lc_plan_nodes(lc_plan_t p, const double **x_dev, int64_t *rows, int32_
     *x_dev = p->x;
     if (rows) *rows = p->fn.H;
     if (Q) *Q = p->fn.Q;
+    return LC_OK;
+}
+
+lc_status lc_plan_nodes_complement(lc_plan_t p, double *omx_dev, hipStream_t stream) {
+    if (!p || !omx_dev) return fail(LC_ERR_INVALID, "lc_plan_nodes_complement: null argument");
+    hipError_t e;
+    switch (p->kind) {
+        case LC_PLAN_SINGLE:
+            e = launch_nodes(p->fn.H, p->fn.Q, p->rowA, p->omt2, omx_dev, stream, true);
+            break;
+        case LC_PLAN_ADAPTIVE: e = adaptive_complement(p, omx_dev, stream); break;
+        case LC_PLAN_BATCH: e = batch_complement(p, omx_dev, stream); break;
+        default:
+            return fail(LC_ERR_UNSUPPORTED, "lc_plan_nodes_complement: single, adaptive and batch plans only");
+    }
+    if (e != hipSuccess) return hip_fail(e, "lc_plan_nodes_complement: launch");
     return LC_OK;
 }
 

@@ -277,6 +277,12 @@ lc_status nodes_adaptive(lc_plan_s *p, const double **x, int64_t *rows, int32_t 
     return LC_OK;
 }
 
+// 1 - x of every node of the plan into comp (the node array's layout).
+hipError_t adaptive_complement(const lc_plan_s *p, double *comp, hipStream_t s) {
+    const AdaptiveState *a = (const AdaptiveState *)p->ext;
+    return launch_anodes(a->segs, a->nseg, a->dtab, p->rowA, comp, s, true);
+}
+
 // The plan's reduction launches writing phi[H] to the given buffer.
 hipError_t adaptive_reduce(const lc_plan_s *p, const void *f, double *phi, hipStream_t s) {
     return launch_reductions((const AdaptiveState *)p->ext, p->fn.prec, f, p->s2, phi, s);

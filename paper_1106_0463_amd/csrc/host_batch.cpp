@@ -1,11 +1,15 @@
 // Batched plans: B independent functions of uneven N/M/Q/precision.
 //
-// Layout: one sample arena (per function [H_b][Q_b] FP64 or FP32 at a
-// 256-byte aligned byte offset), one node arena (per function [H_b][Q_b]
+// Layout: one sample arena (per function [H_b][R_b] FP64 or FP32 at a
+// 256-byte aligned byte offset), one node arena (per function [H_b][R_b]
 // FP64), one coefficient arena (N_b doubles each, packed) and a phi
-// workspace arena (H_b doubles each).  Gauss rules are shared by all
-// functions with the same Q, twiddles and row factors by all functions with
-// the same H.
+// workspace arena (H_b doubles each).  R_b is the number of Abel nodes per
+// row: Q_b for the uniform rule, or the padded panel counts of a composite
+// rule whose panels are the same in every row (grading toward x = 1, no
+// breakpoints, no band).  Either way a row is phi_j = 2 s_j sum_i W_i f_ji
+// with weights W and nodes 1 - 2 s_j^2 (1 - t_i^2) shared by the row, so
+// both run on the same kernels.  Rules are shared by all functions with the
+// same rule, twiddles and row factors by all functions with the same H.
 //
 // Execution: the Abel quadrature reduction of every function runs as one
 // launch per (Q, precision) class over a table of row tiles (each tile a run
@@ -16,7 +20,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <cstdlib>
 #include <map>
 #include <sstream>
@@ -41,11 +47,87 @@ struct HSet {
     double2 *rowA = nullptr, *tw_pre = nullptr, *tw_pack = nullptr, *tw_fft = nullptr;
     DstCfg dcfg{};
 };
-struct QSet {
-    int Q = 0;
-    double *w = nullptr;
-    double2 *omt2 = nullptr;
+// A quadrature rule of a batch: the uniform rule (kind 0: the positive half
+// of the 2q-point Gauss-Legendre rule) or a composite rule with the grading
+// cuts 1 - t = ratio^k, k = 1..levels (kind 1), R nodes per row.
+struct RuleKey {
+    int kind = 0, q = 0;
+    double ratio = 0.0;
+    int levels = 0;
+    bool operator<(const RuleKey &o) const {
+        if (kind != o.kind) return kind < o.kind;
+        if (q != o.q) return q < o.q;
+        if (ratio != o.ratio) return ratio < o.ratio;
+        return levels < o.levels;
+    }
 };
+struct QSet {
+    RuleKey key;
+    int Q = 0;                 // R: nodes per row
+    double *w = nullptr;       // [R] weights W_i (0 on padding)
+    double2 *omt2 = nullptr;   // [R] 1 - t_i^2, double-double
+};
+
+// Weights and 1 - t^2 of a composite rule whose panels are the same in every
+// row: the specification of lc_abel_rule without breakpoints or band, in
+// long double.  Cuts e = 1 - t = ratio^k (decreasing; cuts outside
+// (1e-15, 1 - 1e-7) are dropped and cuts closer than 1e-12 of the first
+// merge); the first panel [0, 1 - e_1] takes the positive half of the
+// 2q-point rule (nodes in decreasing t), every later panel [1 - e_k,
+// 1 - e_{k+1}] the q-point rule (nodes in increasing t); every panel is
+// padded to a multiple of 4 nodes (the last node repeated, weight 0).  This
+// is the row layout of an adaptive plan with the same rule.
+std::vector<long double> grade_cuts(double ratio, int levels) {
+    std::vector<long double> cuts;
+    for (int i = 1; i <= levels && ratio > 0; ++i) {
+        const long double e = powl((long double)ratio, (long double)i);
+        if (!(e > 1e-15L && e < 1 - 1e-7L)) continue;
+        if (!cuts.empty() && cuts.back() - e < 1e-12L * cuts.front()) continue;
+        cuts.push_back(e);
+    }
+    return cuts;
+}
+
+void composite_rule(const RuleKey &k, std::vector<double> &w, std::vector<double2> &omt2) {
+    const std::vector<long double> cuts = grade_cuts(k.ratio, k.levels);
+    w.clear();
+    omt2.clear();
+    std::vector<long double> x, wq, d, ww;
+    auto panel = [&](bool first, long double E, long double h, long double scale) {
+        const int q = k.q;
+        d.assign(q, 0.0L);
+        ww.assign(q, 0.0L);
+        if (first) {
+            gauss_positive_half_ld(2 * q, x, wq);
+            for (int i = 0; i < q; ++i) {
+                d[i] = 1 - x[i];
+                ww[i] = wq[i];
+            }
+        } else {
+            gauss_positive_half_ld(q, x, wq);
+            for (int i = 0; i < q / 2; ++i) {
+                d[i] = 1 + x[i];
+                ww[i] = wq[i];
+                d[q - 1 - i] = 1 - x[i];
+                ww[q - 1 - i] = wq[i];
+            }
+        }
+        const int qp = (q + 3) / 4 * 4;
+        for (int i = 0; i < qp; ++i) {
+            const int ii = i < q ? i : q - 1;
+            const long double e = E + h * d[ii];  // 1 - t
+            w.push_back(i < q ? (double)(scale * ww[i]) : 0.0);
+            omt2.push_back(dd_split(e * (2 - e)));
+        }
+    };
+    const long double e1 = cuts.empty() ? 0.0L : cuts[0];
+    panel(true, e1, 1 - e1, 1 - e1);
+    for (size_t i = 0; i < cuts.size(); ++i) {
+        const long double hi = cuts[i], lo = i + 1 < cuts.size() ? cuts[i + 1] : 0.0L;
+        const long double h = (hi - lo) / 2;
+        panel(false, lo, h, h);
+    }
+}
 constexpr int kParts = 4;  // pipeline parts of a captured batch execution
 
 struct QuadClass {
@@ -97,7 +179,7 @@ struct BatchState {
     std::vector<FnDesc> fn;
     BatchFn *dfn = nullptr;
     std::map<int64_t, HSet> hs;
-    std::map<int, QSet> qs;
+    std::vector<QSet> qs;              // rules, indexed by FnDesc::w_id
     std::vector<QuadClass> classes;
     std::vector<DstGroup> groups;
     std::vector<int> large;
@@ -110,6 +192,8 @@ struct BatchState {
     hipStream_t side = nullptr;        // second stream of the captured pipeline
     hipEvent_t evq[kParts] = {}, evj = nullptr;
     double *x_arena = nullptr, *phi_arena = nullptr;
+    NodeTile *node_tiles = nullptr;    // node construction blocks (kept for the complements)
+    int64_t n_node_tiles = 0;
     double2 *zA = nullptr, *zB = nullptr;
     int64_t f_bytes = 0, x_elems = 0, c_elems = 0, phi_elems = 0, ws_bytes = 0;
     std::vector<void *> allocs;
@@ -225,6 +309,9 @@ hipError_t launch_pipeline(BatchState *st, const void *f_arena, double *c_arena,
     return hipStreamWaitEvent(s, st->evj, 0);
 }
 
+lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::vector<RuleKey> &keys,
+                      const lc_precision *prec, const char *who, lc_plan_t *out);
+
 }  // namespace
 
 void destroy_batch(lc_plan_s *p) {
@@ -244,6 +331,11 @@ void info_batch(lc_plan_s *p, lc_plan_desc *d) {
     d->samples = samples;
     d->sample_bytes = st->f_bytes;
     d->workspace_bytes = st->ws_bytes;
+}
+
+hipError_t batch_complement(const lc_plan_s *p, double *comp, hipStream_t s) {
+    const BatchState *st = (const BatchState *)p->ext;
+    return launch_bnodes(st->node_tiles, st->n_node_tiles, s, st->x_arena, comp);
 }
 
 lc_status nodes_batch(lc_plan_s *p, const double **x, int64_t *rows, int32_t *Q) {
@@ -270,6 +362,13 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         mix(d.M_eff);
         mix(d.Q);
         mix(d.prec);
+        const RuleKey &k = st->qs[d.w_id].key;
+        mix(k.kind);
+        mix(k.q);
+        int64_t rb = 0;
+        memcpy(&rb, &k.ratio, sizeof rb);
+        mix(rb);
+        mix(k.levels);
     }
     const std::string key = arch_name() + "|batch|" + std::to_string(st->B) + "|" + std::to_string(h);
     std::string val;
@@ -388,13 +487,89 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         lc_status s = validate_request(N[b], M[b], Q[b], (int)prec[b], who);
         if (s != LC_OK) return s;
     }
+    std::vector<RuleKey> keys(B);
+    for (int b = 0; b < B; ++b) {
+        keys[b].kind = 0;
+        keys[b].q = Q[b];
+    }
+    return build_batch(B, N, M, keys, prec, "lc_plan_batch", out);
+}
+
+lc_status lc_plan_batch_rules(int32_t B, const int64_t *N, const int64_t *M, const lc_abel_rule *rules,
+                              const lc_precision *prec, lc_plan_t *out) {
+    if (!out || !N || !M || !rules || !prec) return fail_status(LC_ERR_INVALID, "lc_plan_batch_rules: null argument");
+    if (B < 1) return fail_status(LC_ERR_INVALID, "lc_plan_batch_rules: B must be >= 1");
+    std::vector<RuleKey> keys(B);
+    for (int b = 0; b < B; ++b) {
+        char who[80];
+        snprintf(who, sizeof who, "lc_plan_batch_rules[%d]", b);
+        const lc_abel_rule &r = rules[b];
+        if (r.band != 0.0 || r.nbreak != 0)
+            return fail_status(LC_ERR_UNSUPPORTED, std::string(who) +
+                               ": batch rules take no band or breakpoints (every row must have the same panels)");
+        if (r.q < 1 || r.q > 65536) return fail_status(LC_ERR_INVALID, std::string(who) + ": q must be in [1, 65536]");
+        if (!(r.grade_ratio >= 0 && r.grade_ratio < 1) || r.grade_levels < 0 || r.grade_levels > 64)
+            return fail_status(LC_ERR_INVALID, std::string(who) + ": grade_ratio in [0, 1), grade_levels in [0, 64]");
+        const bool cuts = r.grade_ratio > 0 && r.grade_levels > 0;
+        if (cuts && (r.q % 2))
+            return fail_status(LC_ERR_INVALID, std::string(who) + ": q must be even when the rule has cuts");
+        keys[b].kind = 1;
+        keys[b].q = r.q;
+        keys[b].ratio = cuts ? r.grade_ratio : 0.0;
+        keys[b].levels = cuts ? r.grade_levels : 0;
+        if ((int)grade_cuts(keys[b].ratio, keys[b].levels).size() != keys[b].levels)
+            return fail_status(LC_ERR_INVALID, std::string(who) +
+                               ": grading cuts ratio^k must lie in (1e-15, 1 - 1e-7) and not merge");
+        const int64_t R = (int64_t)(keys[b].levels + 1) * ((r.q + 3) / 4 * 4);
+        if (R > 65536)
+            return fail_status(LC_ERR_UNSUPPORTED, std::string(who) + ": more than 65536 nodes per row");
+        lc_status s = validate_request(N[b], M[b], (int32_t)R, (int)prec[b], who);
+        if (s != LC_OK) return s;
+    }
+    return build_batch(B, N, M, keys, prec, "lc_plan_batch_rules", out);
+}
+
+}  // extern "C"
+
+namespace lc {
+namespace {
+
+lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::vector<RuleKey> &keys,
+                      const lc_precision *prec, const char *who, lc_plan_t *out) {
+    const std::string whos(who);
     BatchState *st = new (std::nothrow) BatchState();
-    if (!st) return fail_status(LC_ERR_NOMEM, "lc_plan_batch: host allocation failed");
+    if (!st) return fail_status(LC_ERR_NOMEM, whos + ": host allocation failed");
     st->B = B;
     st->fn.resize(B);
     const int cu = device_cu_count();
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+
+    // ---- rules (host tables; uploaded with the other shared tables)
+    std::map<RuleKey, int> rule_id;
+    std::vector<std::vector<double>> rw;
+    std::vector<std::vector<double2>> ro;
+    std::vector<int> wid(B);
+    for (int b = 0; b < B; ++b) {
+        auto it = rule_id.find(keys[b]);
+        if (it != rule_id.end()) {
+            wid[b] = it->second;
+            continue;
+        }
+        const int id = (int)st->qs.size();
+        rule_id[keys[b]] = id;
+        wid[b] = id;
+        std::vector<double> w, t;
+        std::vector<double2> o;
+        if (keys[b].kind == 0) gauss_half_rule(keys[b].q, t, w, o);
+        else composite_rule(keys[b], w, o);
+        QSet q;
+        q.key = keys[b];
+        q.Q = (int)w.size();
+        st->qs.push_back(q);
+        rw.push_back(std::move(w));
+        ro.push_back(std::move(o));
+    }
 
     // ---- sizes and offsets
     int64_t foff = 0, xoff = 0, coff = 0, poff = 0;
@@ -407,7 +582,8 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         d.M_eff = Me;
         d.H = Me / 2;
         d.L = d.H / 2;
-        d.Q = Q[b];
+        d.Q = st->qs[wid[b]].Q;
+        d.w_id = wid[b];
         d.prec = (int)prec[b];
         const int esz = d.prec == LC_FP64 ? 8 : 4;
         d.f_off = foff;
@@ -420,7 +596,7 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         poff += d.H;
         if (d.L > kLdsFftMax && four_step_cfg(d.L).L1 == 0) {
             free_state(st);
-            return fail_status(LC_ERR_UNSUPPORTED, "lc_plan_batch: an FFT length has no four-step split");
+            return fail_status(LC_ERR_UNSUPPORTED, whos + ": an FFT length has no four-step split");
         }
     }
     st->f_bytes = foff;
@@ -463,16 +639,10 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
             h.dcfg = four_step_cfg(d.L);
             st->hs[d.H] = h;
         }
-        if (!st->qs.count(d.Q)) {
-            QSet q;
-            q.Q = d.Q;
-            std::vector<double> t, w;
-            std::vector<double2> omt2;
-            gauss_half_rule(d.Q, t, w, omt2);
-            chk(upload(st, &q.w, w));
-            chk(upload(st, &q.omt2, omt2));
-            st->qs[d.Q] = q;
-        }
+    }
+    for (size_t i = 0; i < st->qs.size(); ++i) {
+        chk(upload(st, &st->qs[i].w, rw[i]));
+        chk(upload(st, &st->qs[i].omt2, ro[i]));
     }
     chk(balloc(st, &st->x_arena, (size_t)st->x_elems));
     chk(balloc(st, &st->phi_arena, (size_t)st->phi_elems));
@@ -493,7 +663,7 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
     if (e != hipSuccess) {
         free_state(st);
         return fail_status(e == hipErrorOutOfMemory ? LC_ERR_NOMEM : LC_ERR_HIP,
-                           std::string("lc_plan_batch: allocation/upload failed: ") + hipGetErrorString(e));
+                           whos + ": allocation/upload failed: " + hipGetErrorString(e));
     }
     // ---- nodes: one launch over blocks of 4096 nodes of one function each
     if (e == hipSuccess) {
@@ -501,12 +671,14 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
         for (auto &d : st->fn) {
             const int64_t n = d.H * d.Q;
             for (int64_t a = 0; a < n; a += 4096)
-                nt.push_back({st->x_arena + d.x_off, st->hs[d.H].rowA, st->qs[d.Q].omt2, a,
+                nt.push_back({st->x_arena + d.x_off, st->hs[d.H].rowA, st->qs[d.w_id].omt2, a,
                               std::min<int64_t>(n, a + 4096), d.Q});
         }
         NodeTile *dnt = nullptr;
         chk(upload(st, &dnt, nt));
         if (e == hipSuccess) chk(launch_bnodes(dnt, (int64_t)nt.size(), 0));
+        st->node_tiles = dnt;
+        st->n_node_tiles = (int64_t)nt.size();
     }
     chk(hipDeviceSynchronize());
     // ---- device descriptors
@@ -530,15 +702,15 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
     chk(upload(st, &st->dfn, hfn));
     // ---- quadrature classes and their tiles
     std::map<std::pair<int, int>, std::vector<int>> cls;
-    for (int b = 0; b < B; ++b) cls[{st->fn[b].Q, st->fn[b].prec}].push_back(b);
+    for (int b = 0; b < B; ++b) cls[{st->fn[b].w_id, st->fn[b].prec}].push_back(b);
     for (auto &kv : cls) {
         QuadClass qc;
-        qc.Q = kv.first.first;
+        qc.Q = st->qs[kv.first.first].Q;
         qc.prec = kv.first.second;
         for (int b : kv.second) qc.rows += st->fn[b].H;
         qc.cfg = default_quad_cfg(qc.prec, qc.Q, qc.rows, cu);
         qc.cfg.Qv = qc.Q;
-        qc.w = st->qs[qc.Q].w;
+        qc.w = st->qs[kv.first.first].w;
         qc.fns = kv.second;
         std::vector<BatchTile> tiles = make_tiles(st->fn, st->hs, qc.fns, quad_rows_per_block(qc.cfg));
         qc.ntiles = (int)tiles.size();
@@ -679,19 +851,19 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
     }
     if (e != hipSuccess) {
         free_state(st);
-        return fail_status(LC_ERR_HIP, std::string("lc_plan_batch: setup failed: ") + hipGetErrorString(e));
+        return fail_status(LC_ERR_HIP, whos + ": setup failed: " + hipGetErrorString(e));
     }
     chk(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking));
     for (int k = 0; k < kParts; ++k) chk(hipEventCreateWithFlags(&st->evq[k], hipEventDisableTiming));
     chk(hipEventCreateWithFlags(&st->evj, hipEventDisableTiming));
     if (e != hipSuccess) {
         free_state(st);
-        return fail_status(LC_ERR_HIP, std::string("lc_plan_batch: stream/event setup: ") + hipGetErrorString(e));
+        return fail_status(LC_ERR_HIP, whos + ": stream/event setup: " + hipGetErrorString(e));
     }
     lc_plan_s *p = new (std::nothrow) lc_plan_s();
     if (!p) {
         free_state(st);
-        return fail_status(LC_ERR_NOMEM, "lc_plan_batch: host allocation failed");
+        return fail_status(LC_ERR_NOMEM, whos + ": host allocation failed");
     }
     p->kind = LC_PLAN_BATCH;
     hipGetDevice(&p->device);
@@ -700,6 +872,11 @@ lc_status lc_plan_batch(int32_t B, const int64_t *N, const int64_t *M, const int
     *out = p;
     return LC_OK;
 }
+
+}  // namespace
+}  // namespace lc
+
+extern "C" {
 
 lc_status lc_plan_batch_offsets(lc_plan_t p, int64_t *f_off, int64_t *x_off, int64_t *c_off) {
     if (!p || p->kind != LC_PLAN_BATCH) return fail_status(LC_ERR_INVALID, "lc_plan_batch_offsets: not a batch plan");

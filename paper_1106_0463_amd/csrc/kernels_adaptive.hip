@@ -23,7 +23,8 @@ namespace lc {
 // padding slots repeat the last node.
 __global__ __launch_bounds__(256) void k_anodes(const ASeg *__restrict__ segs, int64_t nseg,
                                                 const double2 *__restrict__ dtab,
-                                                const double2 *__restrict__ rowA, double *__restrict__ x) {
+                                                const double2 *__restrict__ rowA, double *__restrict__ x,
+                                                bool comp) {
     const double2 two = make_double2(2.0, 0.0);
     for (int64_t k = blockIdx.x; k < nseg; k += gridDim.x) {
         const ASeg sg = segs[k];
@@ -32,16 +33,16 @@ __global__ __launch_bounds__(256) void k_anodes(const ASeg *__restrict__ segs, i
             const int ii = i < sg.q ? i : sg.q - 1;
             const double2 e = dd_add(sg.E, dd_mul(sg.h, dtab[sg.woff + ii]));   // 1 - t
             const double2 omt2 = dd_mul(e, dd_add(two, make_double2(-e.x, -e.y)));  // 1 - t^2
-            x[sg.off + i] = node_dd(a, omt2);
+            x[sg.off + i] = comp ? omx_dd(a, omt2) : node_dd(a, omt2);
         }
     }
 }
 
 hipError_t launch_anodes(const ASeg *segs, int64_t nseg, const double2 *dtab, const double2 *rowA, double *x,
-                         hipStream_t s) {
+                         hipStream_t s, bool comp) {
     const int64_t grid = nseg < 65536 ? nseg : 65536;
     if (grid < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_anodes, dim3((unsigned)grid), dim3(256), 0, s, segs, nseg, dtab, rowA, x);
+    hipLaunchKernelGGL(k_anodes, dim3((unsigned)grid), dim3(256), 0, s, segs, nseg, dtab, rowA, x, comp);
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ namespace lc {
 // subtraction are carried out in double-double with FMA, so x is the FP64
 // value nearest the exact node in all but rare half-way cases.
 __global__ __launch_bounds__(256) void k_nodes(int64_t H, int Q, const double2 *__restrict__ A,
-                                               const double2 *__restrict__ B, double *__restrict__ x) {
+                                               const double2 *__restrict__ B, double *__restrict__ x, bool comp) {
     // the error-free transformations below must not be contracted into FMAs
 #pragma clang fp contract(off)
     const int64_t total = H * (int64_t)Q;
@@ -30,6 +30,10 @@ __global__ __launch_bounds__(256) void k_nodes(int64_t H, int Q, const double2 *
         const int64_t r = idx / Q;
         const int q = (int)(idx - r * Q);
         const double2 a = A[r], b = B[q];
+        if (comp) {  // 1 - x = a b
+            x[idx] = omx_dd(a, b);
+            continue;
+        }
         const double p = a.x * b.x;
         double e = fma(a.x, b.x, -p);                 // exact low part of a.x b.x
         e = fma(a.x, b.y, fma(a.y, b.x, e));          // + cross terms
@@ -42,30 +46,36 @@ __global__ __launch_bounds__(256) void k_nodes(int64_t H, int Q, const double2 *
 
 // The same construction for many functions at once (batch plans): block t
 // builds nodes [begin, end) of tiles[t].
-__global__ __launch_bounds__(256) void k_bnodes(const NodeTile *__restrict__ tiles) {
+// With comp set, the complements 1 - x go to comp + (t.x - x_base) + idx
+// instead.
+__global__ __launch_bounds__(256) void k_bnodes(const NodeTile *__restrict__ tiles, const double *x_base,
+                                                double *comp) {
     const NodeTile t = tiles[blockIdx.x];
     for (int64_t idx = t.begin + threadIdx.x; idx < t.end; idx += 256) {
         const int64_t r = idx / t.Q;
         const int q = (int)(idx - r * t.Q);
-        t.x[idx] = node_dd(t.rowA[r], t.omt2[q]);
+        if (comp) comp[(t.x - x_base) + idx] = omx_dd(t.rowA[r], t.omt2[q]);
+        else t.x[idx] = node_dd(t.rowA[r], t.omt2[q]);
     }
 }
 
-hipError_t launch_bnodes(const NodeTile *tiles, int64_t ntiles, hipStream_t s) {
+hipError_t launch_bnodes(const NodeTile *tiles, int64_t ntiles, hipStream_t s, const double *x_base,
+                         double *comp) {
     for (int64_t a = 0; a < ntiles; a += 1 << 20) {
         const int64_t n = ntiles - a < (1 << 20) ? ntiles - a : (1 << 20);
-        hipLaunchKernelGGL(k_bnodes, dim3((unsigned)n), dim3(256), 0, s, tiles + a);
+        hipLaunchKernelGGL(k_bnodes, dim3((unsigned)n), dim3(256), 0, s, tiles + a, x_base, comp);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_nodes(int64_t H, int Q, const double2 *A, const double2 *B, double *x, hipStream_t s) {
+hipError_t launch_nodes(int64_t H, int Q, const double2 *A, const double2 *B, double *x, hipStream_t s,
+                        bool comp) {
     const int64_t total = H * (int64_t)Q;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_nodes, dim3((unsigned)blocks), dim3(256), 0, s, H, Q, A, B, x);
+    hipLaunchKernelGGL(k_nodes, dim3((unsigned)blocks), dim3(256), 0, s, H, Q, A, B, x, comp);
     return hipGetLastError();
 }
 

@@ -180,8 +180,9 @@ struct AflatLaunch {
     int b0[kAflatLanes + 1];
 };
 
+// comp: write the complements 1 - x instead of the nodes
 hipError_t launch_anodes(const ASeg *segs, int64_t nseg, const double2 *dtab, const double2 *rowA, double *x,
-                         hipStream_t s);
+                         hipStream_t s, bool comp = false);
 int aflat_blocks_per_cu(int prec);
 hipError_t launch_aflat(int prec, const AflatLaunch &L, const void *f, const ATab *tab, const double *wtab,
                         const double *s2, double *phi, hipStream_t s);
@@ -194,8 +195,10 @@ hipError_t launch_transpose64(const double *src, int64_t R, int64_t C, double *d
 // dst[r * n + i] = src[i], r < reps
 hipError_t launch_repeat(const double *src, int64_t n, int64_t reps, double *dst, hipStream_t s);
 hipError_t launch_nodes(int64_t H, int Q, const double2 *A, const double2 *B, double *x,
-                        hipStream_t s);
-hipError_t launch_bnodes(const NodeTile *tiles, int64_t ntiles, hipStream_t s);
+                        hipStream_t s, bool comp = false);
+// comp: write 1 - x to comp at each node's offset from x_base instead
+hipError_t launch_bnodes(const NodeTile *tiles, int64_t ntiles, hipStream_t s, const double *x_base = nullptr,
+                         double *comp = nullptr);
 hipError_t launch_quad(const QuadCfg &cfg, int prec, const void *f, const double *w,
                        const double *s2, int64_t rows, int Q, double *phi, hipStream_t s);
 hipError_t launch_dst(const DstCfg &cfg, const double *phi, int64_t H, int64_t L, int64_t N,

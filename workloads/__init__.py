@@ -49,6 +49,13 @@ class GeneratingFunction:
         t = float(self.t)
         return torch.rsqrt((1.0 - t) ** 2 + (2.0 * t) * (1.0 - x))
 
+    def torch_omx(self, omx):
+        """The same from the complement 1 - x of the node (accurate near
+        x = 1, where f is steep for t near 1)."""
+        import torch
+        t = float(self.t)
+        return torch.rsqrt((1.0 - t) ** 2 + (2.0 * t) * omx)
+
 
 @dataclass
 class Exponential:
@@ -256,6 +263,34 @@ def mixed_stream(B: int = 65536, seed: int = 5, alpha: float = 1.2,
     param = np.where(kind == 0, t, a)
     fp64 = (np.arange(B) // 2) % 2 == 0
     return MixedStream(Nb, kind, param, fp64)
+
+
+def stream_grid(ms: MixedStream, b: int) -> int:
+    """M_b of request b: 4 N_b, enlarged for a generating function so that
+    the aliased tail t^{n+M} falls below 1e-13 (M_b >= N_b + ln(1e-13)/ln t
+    + 1); even."""
+    N = int(ms.N[b])
+    M = 4 * N
+    if ms.kind[b] == 0:
+        t = float(ms.param[b])
+        M = max(M, N + int(np.ceil(np.log(1e-13) / np.log(t))) + 1)
+    return M + M % 2
+
+
+def stream_rule(ms: MixedStream, b: int) -> dict:
+    """The caller's choice of Abel rule for request b (an lc_abel_rule with
+    no band and no breakpoints).  Generating function: 16-node panels
+    graded toward x = 1 with ratio 0.2 and K = max(0, ceil(ln(d/4)/ln 0.2))
+    levels, where d = (1-t)^2/(2t) is the distance of its singularity
+    beyond x = 1 (about d/4 beyond t = 1 in the rule's variable at y = pi),
+    so that the last panel is no wider than that distance.  e^{ax}: one
+    panel of q = 16 nodes for |a| <= 8, 24 above."""
+    if ms.kind[b] == 0:
+        t = float(ms.param[b])
+        d = (1.0 - t) ** 2 / (2.0 * t)
+        K = max(0, int(np.ceil(np.log(d / 4.0) / np.log(0.2))))
+        return {"q": 16, "grade_ratio": 0.2 if K else 0.0, "grade_levels": K}
+    return {"q": 16 if abs(float(ms.param[b])) <= 8.0 else 24, "grade_ratio": 0.0, "grade_levels": 0}
 
 
 def stream_function(ms: MixedStream, b: int):

@@ -73,14 +73,18 @@ def series_grid(coef: np.ndarray, x_nodes, device="cuda"):
     return F
 
 
-def fill_closed_form_arena(nodes, f_arena, x_off, f_off, H, Q, funcs, fp32):
+def fill_closed_form_arena(nodes, f_arena, x_off, f_off, H, Q, funcs, fp32, omx=None):
     """Samples closed-form families f_b (objects with a .torch method) at
-    their slices of the node arena into the byte arena (FP32 where fp32[b])."""
+    their slices of the node arena into the byte arena (FP32 where fp32[b]).
+    Given the arena of node complements 1 - x, families with a .torch_omx
+    method are evaluated from it."""
     import torch
     for b, f in enumerate(funcs):
         n = int(H[b]) * int(Q[b])
-        x = nodes[int(x_off[b]):int(x_off[b]) + n]
-        v = f.torch(x)
+        if omx is not None and hasattr(f, "torch_omx"):
+            v = f.torch_omx(omx[int(x_off[b]):int(x_off[b]) + n])
+        else:
+            v = f.torch(nodes[int(x_off[b]):int(x_off[b]) + n])
         if fp32[b]:
             dst = f_arena[int(f_off[b]):int(f_off[b]) + 4 * n].view(torch.float32)
             dst.copy_(v.float())
