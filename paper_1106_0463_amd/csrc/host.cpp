@@ -267,10 +267,21 @@ QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu) {
     return c;
 }
 
+// Workgroup size of an LDS FFT of length L: the smallest of 64 .. 1024
+// threads with at most 8 values per thread (one radix-8 butterfly per thread
+// and pass for L = 8T).
+int dst_threads_for(int64_t L) {
+    int T = 64;
+    while (T < 1024 && L > 8 * T) T *= 2;
+    return T;
+}
+
+bool dst_threads_ok(int T) { return T == 64 || T == 128 || T == 256 || T == 512 || T == 1024; }
+
 DstCfg default_dst_cfg(int64_t L) {
     DstCfg d{};
     if (L <= kLdsFftMax) {
-        d.threads = L <= 512 ? 64 : (L <= 2048 ? 256 : 1024);
+        d.threads = dst_threads_for(L);
         d.sched = make_sched((int)L);
         return d;
     }
@@ -671,7 +682,7 @@ lc_status tune_single(lc_plan_s *p, hipStream_t s) {
             q.vec = v[0]; q.G = v[1]; q.cpl = v[2]; q.unroll = v[3]; q.block = v[4]; q.grid = v[5];
             ok = quad_cfg_supported(q, d.prec, d.Q) && (in >> tag) && tag == "dst" && (in >> threads);
         }
-        if (ok && d.L <= kLdsFftMax) ok = sched_from(in, dc.sched, (int)d.L) && d.L <= 8 * threads;
+        if (ok && d.L <= kLdsFftMax) ok = sched_from(in, dc.sched, (int)d.L) && d.L <= 8 * threads && dst_threads_ok(threads);
         if (ok && d.L > kLdsFftMax) ok = sched_from(in, dc.s1, dc.L1) && sched_from(in, dc.s2, dc.L2);
         if (ok) ok = (in >> tag) && tag == "fused" && (in >> fused);
         if (ok) {
@@ -698,7 +709,7 @@ lc_status tune_single(lc_plan_s *p, hipStream_t s) {
     DstCfg bd = p->dst;
     double bt = 1e30;
     if (d.L <= kLdsFftMax) {
-        for (int T : {64, 256, 1024}) {
+        for (int T : {64, 128, 256, 512, 1024}) {
             if (d.L > 8 * T) continue;
             for (const FftSched &sc : sched_candidates((int)d.L)) {
                 DstCfg c = p->dst;

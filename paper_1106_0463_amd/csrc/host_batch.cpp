@@ -388,7 +388,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         cached = cached && (in >> ng) && ng == st->groups.size();
         for (size_t i = 0; cached && i < ng; ++i) {
             int t = 0;
-            cached = (bool)(in >> t) && st->groups[i].Lmax <= 8 * t;
+            cached = (bool)(in >> t) && st->groups[i].Lmax <= 8 * t && dst_threads_ok(t);
             gthreads.push_back(t);
         }
     }
@@ -426,7 +426,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
                 gthreads.push_back(bt);
                 continue;
             }
-            for (int T : {64, 256, 1024}) {
+            for (int T : {64, 128, 256, 512, 1024}) {
                 if (e != hipSuccess || g.Lmax > 8 * T || prepare_bdst(T, g.Lmax) != hipSuccess) continue;
                 hipError_t er;
                 const double t = time_launch([&](hipStream_t ss) { return launch_bdst(T, g.Lmax, st->phi_arena, st->dfn, g.list, g.n, cbuf, ss); }, s, 3, &er);
@@ -796,7 +796,7 @@ lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::
     }
     for (auto &kv : grp) {
         DstGroup g;
-        g.threads = kv.first <= 512 ? 64 : (kv.first <= 2048 ? 256 : 1024);
+        g.threads = dst_threads_for(kv.first);
         auto v = kv.second;
         std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
             if (st->part_of[a] != st->part_of[b]) return st->part_of[a] < st->part_of[b];

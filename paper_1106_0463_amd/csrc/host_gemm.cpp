@@ -45,6 +45,7 @@ struct GemmState {
     int ks = 0, ns = 0, kch = 0;  // MFMA product shape (0: per-mode defaults)
     int64_t N = 0, M = 0, M_eff = 0, H = 0, L = 0;
     double *xc = nullptr, *lam = nullptr, *A = nullptr;
+    double *Ap = nullptr;  // Abel form: A with the DST pack applied to its rows ([H][P])
     void *Y = nullptr;
     int *rowexp = nullptr;
     double2 *tw_pre = nullptr, *tw_pack = nullptr, *tw_fft = nullptr;
@@ -221,6 +222,10 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
     up(&g->tw_fft, fft);
     chk(galloc(g, &g->A, (size_t)(g->H + 1) * P));
     if (e == hipSuccess) chk(launch_amat((int)g->H, P, g->QA, g->xc, g->lam, d_rowA, d_omt2, d_w, d_s2, g->A, 0));
+    if (e == hipSuccess && !direct) {
+        chk(galloc(g, &g->Ap, (size_t)g->H * P));
+        if (e == hipSuccess) chk(launch_apack(g->A, P, g->H, g->L, g->tw_pre, g->tw_pack, g->Ap, 0));
+    }
     if (e == hipSuccess && direct) {
         // Lmat^T [P][N]: the FP64 twist/DST/rescale of every column of A
         double *AT = nullptr;
@@ -246,8 +251,8 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
             if (direct)  // rows n of Lmat = columns of Lmat^T
                 chk(launch_split_rows(g->h16, g->LT, 0, 1, N, (int)N, P, g->Kp, (int)g->Hpad, g->npc, g->Y,
                                       g->Hpad * g->Kp, g->rowexp, g->scaled, 0));
-            else  // rows 1..H of A
-                chk(launch_split_rows(g->h16, g->A, 1, P, 1, (int)g->H, P, g->Kp, (int)g->Hpad, g->npc, g->Y,
+            else  // rows of Ap (A with the DST pack applied)
+                chk(launch_split_rows(g->h16, g->Ap, 0, P, 1, (int)g->H, P, g->Kp, (int)g->Hpad, g->npc, g->Y,
                                       g->Hpad * g->Kp, g->rowexp, g->scaled, 0));
         }
     }
@@ -318,14 +323,14 @@ lc_status lc_execute_gemm(lc_plan_t p, const double *F_dev, int32_t B, double *C
         if (g->direct)  // column-major: C^T (N x B) = Lmat (N x P, stored as Lmat^T [P][N]) * F (P x B)
             rs = rocblas_dgemm(g->rb, rocblas_operation_none, rocblas_operation_transpose, (int)g->N, B, g->P, &one,
                                g->LT, (int)g->N, F_dev, B, &zero, C_dev, (int)g->N);
-        else  // column-major: Out^T (H x B) = A[1:] (H x P) * F (P x B)
+        else  // column-major: Out^T (H x B) = Ap (H x P) * F (P x B)
             rs = rocblas_dgemm(g->rb, rocblas_operation_transpose, rocblas_operation_transpose, (int)g->H, B, g->P,
-                               &one, g->A + g->P, g->P, F_dev, B, &zero, g->Out64, (int)g->H);
+                               &one, g->Ap, g->P, F_dev, B, &zero, g->Out64, (int)g->H);
         if (rs != rocblas_status_success) return fail_status(LC_ERR_HIP, "lc_execute_gemm: rocblas_dgemm failed");
         if ((e = timing_end(p, stream, slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
         if (g->direct) return LC_OK;
-        e = launch_gdst(0, g->Out64, (int)g->H, nullptr, nullptr, B, g->H, g->L, g->N, g->tw_pre, g->tw_pack,
-                        g->tw_fft, g->sched, C_dev, stream);
+        e = launch_gdst_z(0, g->Out64, (int)g->H, nullptr, nullptr, B, g->H, g->L, g->N, g->tw_fft, g->sched, C_dev,
+                          stream);
         if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: dst: ") + hipGetErrorString(e));
         return LC_OK;
     }
@@ -343,8 +348,8 @@ lc_status lc_execute_gemm(lc_plan_t p, const double *F_dev, int32_t B, double *C
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: mfma: ") + hipGetErrorString(e));
     if ((e = timing_end(p, stream, slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
     if (g->direct) return LC_OK;
-    e = launch_gdst(1, g->Out32, (int)g->H, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, B, g->H,
-                    g->L, g->N, g->tw_pre, g->tw_pack, g->tw_fft, g->sched, C_dev, stream);
+    e = launch_gdst_z(1, g->Out32, (int)g->H, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, B,
+                      g->H, g->L, g->N, g->tw_fft, g->sched, C_dev, stream);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: dst: ") + hipGetErrorString(e));
     return LC_OK;
 }

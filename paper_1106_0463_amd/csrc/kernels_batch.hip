@@ -309,6 +309,8 @@ __global__ __launch_bounds__(T) void k_bdst_lds(const double *__restrict__ phi_a
 hipError_t prepare_bdst(int threads, int Lmax) {
     const size_t lds = (size_t)Lmax * sizeof(double2);
     if (lds <= 65536) return hipSuccess;
+    if (threads == 512)
+        return hipFuncSetAttribute((const void *)k_bdst_lds<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (threads == 256)
         return hipFuncSetAttribute((const void *)k_bdst_lds<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (threads == 1024)
@@ -325,8 +327,14 @@ hipError_t launch_bdst(int threads, int Lmax, const double *phi_arena, const Bat
         case 64:
             hipLaunchKernelGGL(k_bdst_lds<64>, dim3(nlist), dim3(64), lds, s, phi_arena, fns, list, c_arena);
             break;
+        case 128:
+            hipLaunchKernelGGL(k_bdst_lds<128>, dim3(nlist), dim3(128), lds, s, phi_arena, fns, list, c_arena);
+            break;
         case 256:
             hipLaunchKernelGGL(k_bdst_lds<256>, dim3(nlist), dim3(256), lds, s, phi_arena, fns, list, c_arena);
+            break;
+        case 512:
+            hipLaunchKernelGGL(k_bdst_lds<512>, dim3(nlist), dim3(512), lds, s, phi_arena, fns, list, c_arena);
             break;
         case 1024:
             hipLaunchKernelGGL(k_bdst_lds<1024>, dim3(nlist), dim3(1024), lds, s, phi_arena, fns, list, c_arena);

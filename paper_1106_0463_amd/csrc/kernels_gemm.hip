@@ -662,6 +662,111 @@ __global__ __launch_bounds__(T) void k_gdst_lds(const PhiT *__restrict__ Out, in
     for (int64_t n = threadIdx.x; n < N; n += T) c[n] = dst_post(n, lds, H);
 }
 
+// ------------------------------------- twist folded into the Abel matrix ---
+// The DST pack of eq. (2.4) (twist e^{i pi k/(2H)} and the half-length
+// complex recombination of dst_pack) is linear in phi, so applied to the
+// rows of A it gives the matrix whose product with F is the packed input Z
+// of the FFT: rows 2k and 2k+1 of Ap are Re Z_k and Im Z_k (k < L = H/2) as
+// combinations of the rows H-k, k, L-k, L+k of A (row 0, y = 0, is zero:
+// that is phi_0 = 0 of V_0 = phi_H).  Block k, threads over the columns.
+__global__ __launch_bounds__(256) void k_apack(const double *__restrict__ A, int P, int64_t H, int64_t L,
+                                               const double2 *__restrict__ tw_pre,
+                                               const double2 *__restrict__ tw_pack, double *__restrict__ Ap) {
+    const int64_t k = blockIdx.x;
+    const double2 t0 = tw_pre[k], t1 = tw_pre[k + L], tp = tw_pack[k];
+    const double *rHk = A + (H - k) * P, *rk = A + k * P, *rLk = A + (L - k) * P, *rLpk = A + (L + k) * P;
+    double *re = Ap + 2 * k * P, *im = re + P;
+    for (int p = threadIdx.x; p < P; p += 256) {
+        const double2 vk = cmul(t0, make_double2(rHk[p], -rk[p]));
+        const double2 vkl = cmul(t1, make_double2(rLk[p], -rLpk[p]));
+        const double2 sum = cadd(vk, vkl);
+        const double2 r = cmul(tp, csub(vk, vkl));
+        re[p] = sum.x - r.y;
+        im[p] = sum.y + r.x;
+    }
+}
+
+hipError_t launch_apack(const double *A, int P, int64_t H, int64_t L, const double2 *tw_pre, const double2 *tw_pack,
+                        double *Ap, hipStream_t s) {
+    hipLaunchKernelGGL(k_apack, dim3((unsigned)L), dim3(256), 0, s, A, P, H, L, tw_pre, tw_pack, Ap);
+    return hipGetLastError();
+}
+
+// Batched FFT + unpack/rescale of rows that already hold the packed input:
+// function b's Z_k is (Out[b][2k], Out[b][2k+1]) times 2^(rowexp[2k or
+// 2k+1] + colexp[b]) when SC; every thread's loads (up to 8 values) are
+// issued before the first is stored to LDS.
+template <int T, typename PhiT, bool SC>
+__global__ __launch_bounds__(T) void k_gdst_z(const PhiT *__restrict__ Out, int ldo, const int *__restrict__ rowexp,
+                                              const int *__restrict__ colexp, int64_t H, int L, int64_t N,
+                                              const double2 *__restrict__ tw_fft, FftSched sch,
+                                              double *__restrict__ C) {
+    extern __shared__ double2 lds[];
+    using P2 = typename std::conditional<std::is_same<PhiT, float>::value, float2, double2>::type;
+    const int b = blockIdx.x;
+    const P2 *row = reinterpret_cast<const P2 *>(Out + (int64_t)b * ldo);
+    const int ce = colexp ? max(colexp[b], -1000) : 0;
+    P2 v[8];
+    int2 ex[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = min((int)threadIdx.x + i * T, L - 1);
+        v[i] = row[k];
+        if constexpr (SC) ex[i] = reinterpret_cast<const int2 *>(rowexp)[k];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = (int)threadIdx.x + i * T;
+        if (k < L) {
+            if constexpr (SC) lds[k] = make_double2(ldexp((double)v[i].x, ex[i].x + ce), ldexp((double)v[i].y, ex[i].y + ce));
+            else lds[k] = make_double2((double)v[i].x, (double)v[i].y);
+        }
+    }
+    __syncthreads();
+    fft_lds_one<T, 8>(lds, L, sch, tw_fft);
+    double *c = C + (int64_t)b * N;
+    for (int64_t n = threadIdx.x; n < N; n += T) c[n] = dst_post(n, lds, H);
+}
+
+hipError_t launch_gdst_z(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,
+                         int64_t H, int64_t L, int64_t N, const double2 *tw_fft, const FftSched &sch, double *C,
+                         hipStream_t s) {
+    const size_t lds = (size_t)L * sizeof(double2);
+    // one radix-8 butterfly per thread and pass for power-of-two lengths
+    // (compile-time passes); otherwise the length classes of launch_gdst
+    int T = L <= 512 ? 64 : (L <= 2048 ? 256 : 1024);
+    if ((L & (L - 1)) == 0 && L >= 512) T = (int)(L / 8);
+    if (L > 8 * T || (ldo & 1)) return hipErrorInvalidValue;
+#define LC_GZ1(TV, PT, SCV)                                                                            \
+    if (T == TV && (rowexp != nullptr) == SCV) {                                                       \
+        if (lds > 65536) {                                                                             \
+            hipError_t e = hipFuncSetAttribute((const void *)k_gdst_z<TV, PT, SCV>,                    \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
+            if (e != hipSuccess) return e;                                                             \
+        }                                                                                              \
+        hipLaunchKernelGGL((k_gdst_z<TV, PT, SCV>), dim3(B), dim3(TV), lds, s, (const PT *)Out, ldo, rowexp, \
+                           colexp, H, (int)L, N, tw_fft, sch, C);                                      \
+        return hipGetLastError();                                                                      \
+    }
+#define LC_GZ(TV, PT) LC_GZ1(TV, PT, true) LC_GZ1(TV, PT, false)
+    if (phi_is_fp32) {
+        LC_GZ(64, float)
+        LC_GZ(128, float)
+        LC_GZ(256, float)
+        LC_GZ(512, float)
+        LC_GZ(1024, float)
+    } else {
+        LC_GZ(64, double)
+        LC_GZ(128, double)
+        LC_GZ(256, double)
+        LC_GZ(512, double)
+        LC_GZ(1024, double)
+    }
+#undef LC_GZ
+#undef LC_GZ1
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_gdst(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,
                        int64_t H, int64_t L, int64_t N, const double2 *tw_pre, const double2 *tw_pack,
                        const double2 *tw_fft, const FftSched &sch, double *C, hipStream_t s) {

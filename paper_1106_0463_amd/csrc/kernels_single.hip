@@ -475,9 +475,18 @@ hipError_t launch_dst(const DstCfg &cfg, const double *phi, int64_t H, int64_t L
                 hipLaunchKernelGGL(k_dst_lds<64>, dim3(1), dim3(64), lds, s, phi, H, (int)L, N, tw_pre,
                                    tw_pack, tw_fft, cfg.sched, c);
                 break;
+            case 128:
+                hipLaunchKernelGGL(k_dst_lds<128>, dim3(1), dim3(128), lds, s, phi, H, (int)L, N, tw_pre,
+                                   tw_pack, tw_fft, cfg.sched, c);
+                break;
             case 256:
                 if ((e = allow_lds(k_dst_lds<256>, lds)) != hipSuccess) return e;
                 hipLaunchKernelGGL(k_dst_lds<256>, dim3(1), dim3(256), lds, s, phi, H, (int)L, N, tw_pre,
+                                   tw_pack, tw_fft, cfg.sched, c);
+                break;
+            case 512:
+                if ((e = allow_lds(k_dst_lds<512>, lds)) != hipSuccess) return e;
+                hipLaunchKernelGGL(k_dst_lds<512>, dim3(1), dim3(512), lds, s, phi, H, (int)L, N, tw_pre,
                                    tw_pack, tw_fft, cfg.sched, c);
                 break;
             case 1024:

@@ -38,4 +38,13 @@ hipError_t launch_gdst(int phi_is_fp32, const void *Out, int ldo, const int *row
                        int64_t H, int64_t L, int64_t N, const double2 *tw_pre, const double2 *tw_pack,
                        const double2 *tw_fft, const FftSched &sch, double *C, hipStream_t s);
 
+// Ap [H][P]: rows 2k, 2k+1 = Re, Im of the DST pack Z_k applied to the rows
+// of A ([H+1][P], row 0 zero), k < L = H/2
+hipError_t launch_apack(const double *A, int P, int64_t H, int64_t L, const double2 *tw_pre, const double2 *tw_pack,
+                        double *Ap, hipStream_t s);
+// batched FFT + unpack/rescale of packed rows (Out[b][2k], Out[b][2k+1]) = Z_k
+hipError_t launch_gdst_z(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,
+                         int64_t H, int64_t L, int64_t N, const double2 *tw_fft, const FftSched &sch, double *C,
+                         hipStream_t s);
+
 }  // namespace lc

@@ -253,6 +253,8 @@ QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu);
 int quad_blocks_per_cu(const QuadCfg &cfg, int prec);
 int bquad_blocks_per_cu(const QuadCfg &cfg, int prec);
 DstCfg default_dst_cfg(int64_t L);
+int dst_threads_for(int64_t L);   // smallest of 64 .. 1024 with L <= 8 T
+bool dst_threads_ok(int T);       // a built LDS FFT workgroup size
 DstCfg four_step_cfg(int64_t L);
 int device_cu_count();
 

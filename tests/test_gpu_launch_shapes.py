@@ -166,7 +166,7 @@ def test_single_dst_threads(lc, tmp_path, monkeypatch, L):
     key, tok = _last_entry(cache, "single")
     assert tok[7] == "dst" and tok[-2] == "fused"
     tok[-1] = "0"  # the DST kernel, not the fused small path
-    sizes = [T for T in (64, 256, 1024) if L <= 8 * T]
+    sizes = [T for T in (64, 128, 256, 512, 1024) if L <= 8 * T]
     banner(f"[gpu] single DST L={L}: workgroup sizes {sizes}")
     for T in sizes:
         forced = tok[:8] + [str(T)] + tok[9:]
