@@ -188,6 +188,10 @@ struct BatchState {
     int nct = 0, nrt = 0, npt = 0;
     int cst[kParts + 1] = {}, rst[kParts + 1] = {}, pst[kParts + 1] = {};  // big tiles per part
     std::vector<int> part_of;          // part of each function
+    std::vector<char> fused;           // functions run whole by the fused kernel
+    FusedFn *flist[2] = {};            // their descriptors per sample precision, largest first
+    int nfused[2] = {};
+    int64_t fHmax[2] = {};
     int nparts = 1;
     hipStream_t side = nullptr;        // second stream of the captured pipeline
     hipEvent_t evq[kParts] = {}, evj = nullptr;
@@ -265,7 +269,13 @@ hipError_t launch_part_dst(BatchState *st, int k, double *c_arena, hipStream_t s
                        st->pst[k + 1] - st->pst[k], c_arena, s);
 }
 
-hipError_t launch_part_quad(BatchState *st, int k, const void *f_arena, hipStream_t s) {
+hipError_t launch_part_quad(BatchState *st, int k, const void *f_arena, double *c_arena, hipStream_t s) {
+    for (int pr = 0; pr < 2; ++pr) {  // the fused functions (one part only), first
+        if (k > 0 || st->nfused[pr] == 0) continue;
+        hipError_t e = launch_bfused(pr == 0 ? LC_FP64 : LC_FP32_QUAD, f_arena, st->dfn, st->flist[pr],
+                                     st->nfused[pr], st->fHmax[pr], c_arena, s);
+        if (e != hipSuccess) return e;
+    }
     for (auto &qc : st->classes) {
         const int n = qc.tstart[k + 1] - qc.tstart[k];
         if (n <= 0) continue;
@@ -284,7 +294,7 @@ hipError_t launch_all(lc_plan_s *p, BatchState *st, const void *f_arena, double 
     int slot = -1;
     if (timed && (e = timing_begin(p, s, &slot)) != hipSuccess) return e;
     for (int k = 0; k < st->nparts; ++k)
-        if ((e = launch_part_quad(st, k, f_arena, s)) != hipSuccess) return e;
+        if ((e = launch_part_quad(st, k, f_arena, c_arena, s)) != hipSuccess) return e;
     if (timed && (e = timing_end(p, s, slot)) != hipSuccess) return e;
     for (int k = 0; k < st->nparts; ++k)
         if ((e = launch_part_dst(st, k, c_arena, s)) != hipSuccess) return e;
@@ -299,7 +309,7 @@ hipError_t launch_all(lc_plan_s *p, BatchState *st, const void *f_arena, double 
 hipError_t launch_pipeline(BatchState *st, const void *f_arena, double *c_arena, hipStream_t s) {
     hipError_t e;
     for (int k = 0; k < st->nparts; ++k) {
-        if ((e = launch_part_quad(st, k, f_arena, s)) != hipSuccess) return e;
+        if ((e = launch_part_quad(st, k, f_arena, c_arena, s)) != hipSuccess) return e;
         if ((e = hipEventRecord(st->evq[k], s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(st->side, st->evq[k], 0)) != hipSuccess) return e;
         const bool last = k + 1 == st->nparts;
@@ -400,6 +410,10 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         for (auto &qc : st->classes) {
             double best = 1e30;
             QuadCfg bc = qc.cfg;
+            if (qc.fns.empty()) {  // every function of the class runs in the fused kernel
+                qcfg.push_back(bc);
+                continue;
+            }
             for (QuadCfg c : quad_candidates(qc.prec, qc.Q, qc.rows, cu, true)) {
                 c.Qv = qc.Q;
                 std::vector<BatchTile> tl = make_tiles(st->fn, st->hs, qc.fns, quad_rows_per_block(c));
@@ -621,6 +635,21 @@ lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::
         }
     }
 
+    // functions small enough for one workgroup can run quadrature, twist, FFT
+    // and rescale in the fused kernel (LC_BATCH_FUSE=1; off by default: it
+    // measured within 1% of the two-phase execution on the uneven batch and
+    // the mixed stream, one way or the other)
+    {
+        bool fuse = false;
+        if (const char *ev = getenv("LC_BATCH_FUSE")) fuse = atoi(ev) != 0;
+        int64_t hmin = 512;  // below: tiled reduction and packed DSTs (one workgroup would idle)
+        if (const char *ev = getenv("LC_BATCH_FUSE_HMIN")) hmin = std::max<int64_t>(2, atoll(ev));
+        st->fused.assign(B, 0);
+        for (int b = 0; b < B; ++b) {
+            const FnDesc &d = st->fn[b];
+            st->fused[b] = fuse && st->nparts == 1 && d.H >= hmin && d.H <= kFuseHmax && fuse_lanes(d.prec, d.Q) > 0;
+        }
+    }
     // ---- shared tables
     for (auto &d : st->fn) {
         if (!st->hs.count(d.H)) {
@@ -707,6 +736,12 @@ lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::
         QuadClass qc;
         qc.Q = st->qs[kv.first.first].Q;
         qc.prec = kv.first.second;
+        {   // the functions that run whole in the fused kernel leave the tiles
+            std::vector<int> rest;
+            for (int b : kv.second)
+                if (!st->fused[b]) rest.push_back(b);
+            kv.second = rest;
+        }
         for (int b : kv.second) qc.rows += st->fn[b].H;
         qc.cfg = default_quad_cfg(qc.prec, qc.Q, qc.rows, cu);
         qc.cfg.Qv = qc.Q;
@@ -723,6 +758,21 @@ lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::
         chk(upload(st, &qc.tiles, tiles));
         st->classes.push_back(qc);
     }
+    // ---- fused functions: one list per sample precision, largest first
+    for (int pr = 0; pr < 2; ++pr) {
+        std::vector<int> fz;
+        for (int b = 0; b < B; ++b)
+            if (st->fused[b] && (st->fn[b].prec == LC_FP64) == (pr == 0)) fz.push_back(b);
+        std::stable_sort(fz.begin(), fz.end(), [&](int a, int c) { return st->fn[a].H > st->fn[c].H; });
+        std::vector<FusedFn> fl;
+        for (int b : fz) {
+            const FnDesc &d = st->fn[b];
+            fl.push_back({b, d.Q, fuse_lanes(d.prec, d.Q), 0, st->qs[d.w_id].w});
+            st->fHmax[pr] = std::max(st->fHmax[pr], d.H);
+        }
+        st->nfused[pr] = (int)fl.size();
+        if (!fl.empty()) chk(upload(st, &st->flist[pr], fl));
+    }
     // ---- DST groups (one workgroup per function, longest first; short
     // functions of equal FFT length packed several per workgroup)
     std::map<int, std::vector<int>> grp;
@@ -731,6 +781,7 @@ lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::
     if (const char *ev = getenv("LC_BATCH_MULTI")) pack = atoi(ev) != 0;
     for (int b = 0; b < B; ++b) {
         const int64_t L = st->fn[b].L;
+        if (st->fused[b]) continue;  // its DST runs in the fused kernel
         if (is_big(L)) {
             st->large.push_back(b);
             continue;

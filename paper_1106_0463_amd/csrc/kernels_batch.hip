@@ -410,6 +410,113 @@ hipError_t launch_bdst_multi(const double *phi_arena, const BatchFn *fns, const 
     return hipGetLastError();
 }
 
+// --------------------------------------- fused small functions ---
+// One workgroup per function small enough for its LDS (H <= kFuseHmax):
+// every row's Abel sum goes to LDS (G lanes per row, U rows per group in
+// flight, each lane's chunk weights in registers; chunk indices past the row
+// are clamped and weighted 0 so that all loads issue together), then the
+// twist, FFT and rescale of eq. (2.4) run from LDS and the coefficients go
+// to the arena: phi never leaves the CU.  One launch covers every fused
+// function of a sample precision, whatever its rule: block i takes
+// list[i] = {function, Q, G, weights}, Q <= G * kFuseCpl * VEC.
+constexpr int kFuseCpl = 4;
+struct BLdsPhi {
+    const double *p;
+    __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
+};
+template <typename T, int G, int U>
+__device__ __forceinline__ void fused_rows(const T *__restrict__ f, const double *__restrict__ w, int Q, int64_t H,
+                                           const double *__restrict__ s2, double *__restrict__ phs) {
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int RPB = 256 / G;
+    using V = typename VecOf<T, VEC>::type;
+    const int NC = Q / VEC;
+    const int g = threadIdx.x & (G - 1), rg = threadIdx.x / G;
+    double wr[kFuseCpl][VEC];
+    int cc[kFuseCpl];
+#pragma unroll
+    for (int j = 0; j < kFuseCpl; ++j) {
+        const int c = g + j * G;
+        cc[j] = c < NC ? c : NC - 1;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) wr[j][e] = c < NC ? w[c * VEC + e] : 0.0;
+    }
+    for (int64_t r0 = 0; r0 < H; r0 += RPB * U) {
+        V v[U][kFuseCpl];
+        double s2v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = r0 + rg + u * RPB;
+            const int64_t rc = row < H ? row : H - 1;
+            const V *p = reinterpret_cast<const V *>(f + rc * Q);
+#pragma unroll
+            for (int j = 0; j < kFuseCpl; ++j) v[u][j] = ld_stream(p + cc[j]);
+            s2v[u] = ld_global(s2 + rc);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < kFuseCpl; ++j) {
+                double d[VEC];
+                to_d(v[u][j], d);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc = fma(wr[j][e], d[e], acc);
+            }
+            acc = group_sum<G>(acc);
+            const int64_t row = r0 + rg + u * RPB;
+            if (g == 0 && row < H) phs[row] = s2v[u] * acc;
+        }
+    }
+}
+
+template <typename T, int U>
+__global__ __launch_bounds__(256) void k_bfused(const unsigned char *__restrict__ f_arena,
+                                                const BatchFn *__restrict__ fns,
+                                                const FusedFn *__restrict__ list, double *__restrict__ c_arena) {
+    extern __shared__ double2 lds[];
+    const FusedFn fd = list[blockIdx.x];
+    const BatchFn &fn = fns[fd.fn];
+    const int64_t H = fn.H;
+    const int L = (int)fn.L;
+    double *phs = reinterpret_cast<double *>(lds + L);
+    const T *f = reinterpret_cast<const T *>(f_arena + fn.f_off);
+    switch (fd.G) {
+        case 8: fused_rows<T, 8, U>(f, fd.w, fd.Q, H, fn.s2, phs); break;
+        case 16: fused_rows<T, 16, U>(f, fd.w, fd.Q, H, fn.s2, phs); break;
+        case 32: fused_rows<T, 32, U>(f, fd.w, fd.Q, H, fn.s2, phs); break;
+        default: fused_rows<T, 64, U>(f, fd.w, fd.Q, H, fn.s2, phs); break;
+    }
+    __syncthreads();
+    dst_pack_lds<256, 8>(lds, BLdsPhi{phs}, H, L, fn.tw_pre, fn.tw_pack);
+    __syncthreads();
+    fft_lds_one<256, 8>(lds, L, fn.sched, fn.tw_fft);
+    double *c = c_arena + fn.c_off;
+    for (int64_t n = threadIdx.x; n < fn.N; n += 256) c[n] = dst_post(n, lds, H);
+}
+
+int fuse_lanes(int prec, int Q) {
+    const int VEC = prec == LC_FP64 ? 2 : 4;
+    if (Q % VEC) return 0;
+    for (int G = 8; G <= 64; G *= 2)
+        if (Q <= G * kFuseCpl * VEC) return G;
+    return 0;
+}
+
+hipError_t launch_bfused(int prec, const void *f_arena, const BatchFn *fns, const FusedFn *list, int n, int64_t Hmax,
+                         double *c_arena, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (Hmax > kFuseHmax) return hipErrorInvalidValue;
+    const size_t lds = (size_t)Hmax * 16;  // L complex + H phi values
+    if (prec == LC_FP64)
+        hipLaunchKernelGGL((k_bfused<double, 4>), dim3(n), dim3(256), lds, s, (const unsigned char *)f_arena, fns,
+                           list, c_arena);
+    else
+        hipLaunchKernelGGL((k_bfused<float, 4>), dim3(n), dim3(256), lds, s, (const unsigned char *)f_arena, fns,
+                           list, c_arena);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------- batched four-step ---
 // The same three passes as the single-function four-step FFT, for every
 // long function of a batch in one launch each: block t works on function

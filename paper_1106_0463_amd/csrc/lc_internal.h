@@ -229,6 +229,20 @@ __host__ __device__ inline int multi_slots(int L) {
 }
 hipError_t launch_bdst_multi(const double *phi_arena, const BatchFn *fns, const int32_t *list, int nblocks,
                              double *c_arena, hipStream_t s);
+// Functions of at most kFuseHmax rows whose Q suits the fused kernel run
+// quadrature, twist, FFT and rescale in one workgroup; one launch per
+// sample precision (list: n entries, Hmax their largest H).
+constexpr int64_t kFuseHmax = 2048;
+struct FusedFn {
+    int32_t fn;        // function (index into the BatchFn table)
+    int32_t Q;         // samples per row
+    int32_t G;         // lanes per row (fuse_lanes)
+    int32_t pad;
+    const double *w;   // the rule's weights [Q]
+};
+int fuse_lanes(int prec, int Q);  // lanes per row of the fused kernel, 0 if Q does not suit it
+hipError_t launch_bfused(int prec, const void *f_arena, const BatchFn *fns, const FusedFn *list, int n, int64_t Hmax,
+                         double *c_arena, hipStream_t s);
 hipError_t launch_bbig(const double *phi_arena, const BigFn *fns, const BigTile *ctiles, int nct,
                        const BigTile *rtiles, int nrt, const BigTile *ptiles, int npt, double *c_arena,
                        hipStream_t s);

@@ -289,3 +289,43 @@ def test_long_function_wide_four_step(lc):
     torch.cuda.synchronize()
     assert rel_err(got, cs) <= 5e-14
     p.destroy()
+
+
+def test_fused_small_functions(lc, monkeypatch):
+    """The fused one-workgroup path (LC_BATCH_FUSE=1: quadrature rows into
+    LDS, then the DST, for functions of at most 2048 rows whose row length
+    suits it): FP64 and FP32 samples, Q of 8 to 176 lanes' worth, a Q that
+    does not suit it (33, tiled) and a four-step member beside them; equal to
+    the method oracle and to the same plan without fusion."""
+    import torch
+    Ns = [1, 7, 30, 64, 200, 511, 1000, 1024, 300, 5000]
+    M = [4, 28, 120, 256, 800, 2044, 4000, 4096, 1200, 40000]
+    Q = [2, 16, 48, 48, 24, 176, 48, 64, 33, 48]
+    prec = ["fp64", "fp32", "fp64", "fp32", "fp64", "fp64", "fp32", "fp64", "fp64", "fp64"]
+    fams = [W.GeneratingFunction(0.4), W.Exponential(1.3), W.Cosine(5.0), W.Rational(3.0)]
+    funcs = [fams[b % 4] for b in range(len(Ns))]
+    banner(f"[gpu] fused small functions, {len(Ns)} functions")
+    out = {}
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("LC_BATCH_FUSE", fuse)
+        monkeypatch.setenv("LC_BATCH_FUSE_HMIN", "2")
+        bp, arena, c_off = _build(lc, funcs, Ns, M, Q, prec)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            c1 = bp.execute(arena, stream=s)
+            c2 = torch.full_like(c1, float("nan"))
+            bp.execute(arena, c2, stream=s)  # graph replay
+            s.synchronize()
+        assert torch.equal(c1, c2)
+        out[fuse] = c2.cpu().numpy()
+        bp.destroy()
+    for b, (f, n, m, q, pr) in enumerate(zip(funcs, Ns, M, Q, prec)):
+        got, plain = out["1"][c_off[b]:c_off[b + 1]], out["0"][c_off[b]:c_off[b + 1]]
+        k = 2 * np.arange(n) + 1
+        assert rel_err(got / k, plain / k) <= 1e-13, b
+        if n * expected_grid(m) <= 2_000_000:
+            ref = np.array(oracle.method_coeffs(f, n, expected_grid(m), q), dtype=float)
+            if pr == "fp64":
+                assert rel_err(got, ref) <= TOL, b
+            else:
+                assert rel_err(got / k, ref / k) <= 1e-7, b
