@@ -99,7 +99,7 @@ std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu, bool
     };
     const int vfit = prec == LC_FP64 ? 2 : 4;
     for (int G : {4, 8, 16})
-        for (int cpl : {1, 2, 3, 4, 6, 8})
+        for (int cpl : {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11})
             for (int u : {1, 2, 4}) {
                 QuadCfg c{};
                 c.vec = vfit;

@@ -215,7 +215,7 @@ void row_factors(int64_t H, std::vector<double2> &A, std::vector<double> &s2) {
 // -------------------------------------------------- launch configs ---
 static bool fit_key_ok(int cpl, int u) {
     const int key = cpl * 16 + u;
-    const int ok[] = {17, 18, 20, 33, 34, 36, 49, 50, 65, 66, 97, 129};
+    const int ok[] = {17, 18, 20, 33, 34, 36, 49, 50, 65, 66, 81, 97, 113, 129, 145, 161, 177};
     for (int k : ok)
         if (k == key) return true;
     return false;

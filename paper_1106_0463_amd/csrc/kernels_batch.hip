@@ -211,6 +211,11 @@ static hipError_t bgen(const QuadCfg &c, const void *f, const double *w, int Q, 
             case 4 * 16 + 2: return bfit<TT, VV, GG, 4, 2>(c, f, w, tiles, ntiles, phi, s); \
             case 6 * 16 + 1: return bfit<TT, VV, GG, 6, 1>(c, f, w, tiles, ntiles, phi, s); \
             case 8 * 16 + 1: return bfit<TT, VV, GG, 8, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 5 * 16 + 1: return bfit<TT, VV, GG, 5, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 7 * 16 + 1: return bfit<TT, VV, GG, 7, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 9 * 16 + 1: return bfit<TT, VV, GG, 9, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 10 * 16 + 1: return bfit<TT, VV, GG, 10, 1>(c, f, w, tiles, ntiles, phi, s);\
+            case 11 * 16 + 1: return bfit<TT, VV, GG, 11, 1>(c, f, w, tiles, ntiles, phi, s);\
             default: break;                                                                       \
         }                                                                                         \
     }

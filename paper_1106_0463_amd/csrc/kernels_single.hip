@@ -259,6 +259,11 @@ static hipError_t go_gen(const QuadCfg &c, const void *f, const double *w, const
             case 4 * 16 + 2: return go_fit<TT, VV, GG, 4, 2>(c, f, w, s2, rows, phi, s);          \
             case 6 * 16 + 1: return go_fit<TT, VV, GG, 6, 1>(c, f, w, s2, rows, phi, s);          \
             case 8 * 16 + 1: return go_fit<TT, VV, GG, 8, 1>(c, f, w, s2, rows, phi, s);          \
+            case 5 * 16 + 1: return go_fit<TT, VV, GG, 5, 1>(c, f, w, s2, rows, phi, s);         \
+            case 7 * 16 + 1: return go_fit<TT, VV, GG, 7, 1>(c, f, w, s2, rows, phi, s);         \
+            case 9 * 16 + 1: return go_fit<TT, VV, GG, 9, 1>(c, f, w, s2, rows, phi, s);         \
+            case 10 * 16 + 1: return go_fit<TT, VV, GG, 10, 1>(c, f, w, s2, rows, phi, s);        \
+            case 11 * 16 + 1: return go_fit<TT, VV, GG, 11, 1>(c, f, w, s2, rows, phi, s);        \
             default: break;                                                                      \
         }                                                                                        \
     }
@@ -339,7 +344,7 @@ bool quad_cfg_supported(const QuadCfg &c, int prec, int Q) {
         if (!(c.G == 4 || c.G == 8 || c.G == 16)) return false;
         if (c.G * c.cpl * c.vec != Q) return false;
         const int key = c.cpl * 16 + c.unroll;
-        const int ok[] = {17, 18, 20, 33, 34, 36, 49, 50, 65, 66, 97, 129};
+        const int ok[] = {17, 18, 20, 33, 34, 36, 49, 50, 65, 66, 81, 97, 113, 129, 145, 161, 177};
         for (int k : ok)
             if (k == key) return true;
         return false;

@@ -166,3 +166,29 @@ def test_table1_abs_pow(lc):
     assert rel_err(got, ref) <= TOL
     err = max(abs(got[n] - float(v)) for n, v in zip(ns, vals))
     assert err < 2e-8
+
+
+@pytest.mark.parametrize("Q,precision", [(80, "fp64"), (112, "fp64"), (144, "fp64"), (160, "fp64"), (176, "fp64"),
+                                         (80, "fp32"), (112, "fp32"), (176, "fp32")])
+def test_long_row_fit_shapes(lc, Q, precision):
+    # rows of 5, 7, 9, 10 and 11 chunks per lane (the row lengths of graded
+    # composite rules with 16-node panels) take the exact-fit reduction, in a
+    # single plan and in a batch, against the method oracle
+    import torch
+    f = W.Exponential(2.5)
+    N, M = 300, 1200
+    banner(f"[gpu] fit reduction Q={Q} {precision}")
+    got, info = run_gpu(lc, f, N, M, Q, precision)
+    ref = np.array(oracle.method_coeffs(f, N, expected_grid(M), Q), dtype=float)
+    k = 2 * np.arange(N) + 1
+    tol = TOL if precision == "fp64" else 1e-7
+    assert rel_err(got / k, ref / k) <= tol
+    bp = lc.plan_batch([N, 40], [M, 160], [Q, Q], precision)
+    f_off, x_off, c_off = bp.offsets()
+    arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
+    from workloads.gpu import fill_closed_form_arena
+    H = [expected_grid(M) // 2, expected_grid(160) // 2]
+    fill_closed_form_arena(bp.nodes, arena, x_off, f_off, H, [Q, Q], [f, f], [precision == "fp32"] * 2)
+    c = bp.execute(arena).cpu().numpy()
+    bp.destroy()
+    assert rel_err(c[c_off[0]:c_off[1]] / k, got / k) <= 1e-13
