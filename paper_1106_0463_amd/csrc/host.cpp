@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -23,6 +24,21 @@ namespace lc {
 static thread_local std::string g_err;
 
 void set_error(const std::string &msg) { g_err = msg; }
+
+// Every device allocation of the library.  LC_ALLOC_LIMIT (bytes, read once)
+// makes any single allocation larger than the limit fail as out of memory:
+// a hook that lets a test drive the LC_ERR_NOMEM paths deterministically.
+hipError_t device_alloc(void **p, size_t bytes) {
+    static const long long limit = [] {
+        const char *ev = getenv("LC_ALLOC_LIMIT");
+        return ev ? atoll(ev) : -1LL;
+    }();
+    if (limit >= 0 && bytes > (size_t)limit) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
 
 static lc_status fail(lc_status s, const char *fmt, ...) {
     char buf[512];
@@ -358,7 +374,7 @@ template <typename T>
 static hipError_t dalloc(T **ptr, size_t count, int64_t *acc) {
     *ptr = nullptr;
     if (count == 0) return hipSuccess;
-    hipError_t e = hipMalloc((void **)ptr, count * sizeof(T));
+    hipError_t e = device_alloc((void **)ptr, count * sizeof(T));
     if (e == hipSuccess && acc) *acc += (int64_t)(count * sizeof(T));
     return e;
 }
@@ -695,7 +711,7 @@ lc_status tune_single(lc_plan_s *p, hipStream_t s) {
     }
     hipError_t e = hipSuccess;
     double *cbuf = nullptr;
-    if ((e = hipMalloc((void **)&cbuf, (size_t)d.N * sizeof(double))) != hipSuccess)
+    if ((e = device_alloc((void **)&cbuf, (size_t)d.N * sizeof(double))) != hipSuccess)
         return fail_status(LC_ERR_NOMEM, "lc_autotune: workspace");
     const void *fsrc = p->x;  // same shape as the samples (FP64) or larger (FP32)
     double best = 1e30;

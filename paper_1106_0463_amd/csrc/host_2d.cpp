@@ -48,7 +48,7 @@ void free_2d(Plan2D *t) {
 template <typename T>
 hipError_t talloc(Plan2D *t, T **p, size_t n) {
     *p = nullptr;
-    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    hipError_t e = device_alloc((void **)p, n * sizeof(T));
     if (e == hipSuccess) {
         t->allocs.push_back(*p);
         t->ws += (int64_t)(n * sizeof(T));

@@ -75,7 +75,7 @@ template <typename T>
 hipError_t aalloc(AdaptiveState *a, T **p, size_t n, int64_t *ws) {
     *p = nullptr;
     if (n == 0) return hipSuccess;
-    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    hipError_t e = device_alloc((void **)p, n * sizeof(T));
     if (e == hipSuccess) {
         a->allocs.push_back(*p);
         *ws += (int64_t)(n * sizeof(T));

@@ -212,7 +212,7 @@ template <typename T>
 hipError_t balloc(BatchState *st, T **p, size_t n) {
     *p = nullptr;
     if (n == 0) return hipSuccess;
-    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    hipError_t e = device_alloc((void **)p, n * sizeof(T));
     if (e == hipSuccess) {
         st->allocs.push_back(*p);
         st->ws_bytes += (int64_t)(n * sizeof(T));
@@ -418,7 +418,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
                 c.Qv = qc.Q;
                 std::vector<BatchTile> tl = make_tiles(st->fn, st->hs, qc.fns, quad_rows_per_block(c));
                 BatchTile *dt = nullptr;
-                if ((e = hipMalloc((void **)&dt, tl.size() * sizeof(BatchTile))) != hipSuccess) break;
+                if ((e = device_alloc((void **)&dt, tl.size() * sizeof(BatchTile))) != hipSuccess) break;
                 e = hipMemcpy(dt, tl.data(), tl.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
                 c.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)tl.size(), c.grid * 1));
                 if (e == hipSuccess) {
@@ -432,7 +432,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
             qcfg.push_back(bc);
         }
         double *cbuf = nullptr;
-        if (e == hipSuccess) e = hipMalloc((void **)&cbuf, (size_t)std::max<int64_t>(1, st->c_elems) * sizeof(double));
+        if (e == hipSuccess) e = device_alloc((void **)&cbuf, (size_t)std::max<int64_t>(1, st->c_elems) * sizeof(double));
         for (auto &g : st->groups) {
             double best = 1e30;
             int bt = g.threads;

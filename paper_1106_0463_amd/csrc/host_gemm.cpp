@@ -65,7 +65,7 @@ template <typename T>
 hipError_t galloc(GemmState *g, T **p, size_t n, bool perB = false) {
     *p = nullptr;
     if (n == 0) return hipSuccess;
-    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    hipError_t e = device_alloc((void **)p, n * sizeof(T));
     if (e == hipSuccess) {
         (perB ? g->ballocs : g->allocs).push_back(*p);
         (perB ? g->b_bytes : g->ws_bytes) += (int64_t)(n * sizeof(T));
@@ -229,7 +229,7 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
     if (e == hipSuccess && direct) {
         // Lmat^T [P][N]: the FP64 twist/DST/rescale of every column of A
         double *AT = nullptr;
-        chk(hipMalloc((void **)&AT, (size_t)P * g->H * sizeof(double)));
+        chk(device_alloc((void **)&AT, (size_t)P * g->H * sizeof(double)));
         chk(galloc(g, &g->LT, (size_t)P * N));
         if (e == hipSuccess) chk(launch_transpose_a(g->A, (int)g->H, P, AT, 0));
         if (e == hipSuccess)

@@ -166,3 +166,38 @@ def test_output_buffers_validated_before_launch(lc):
             g.execute(F, out)
         assert int(torch.count_nonzero(out)) == 0
     g.destroy()
+
+
+def test_out_of_memory_status():
+    """LC_ERR_NOMEM through the LC_ALLOC_LIMIT hook (any device allocation
+    above the limit fails), in a child process so that the limit holds from
+    the library's first allocation: every plan kind reports LC_ERR_NOMEM,
+    leaves *out untouched and says what failed; a plan below the limit still
+    builds and runs."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = r'''
+import ctypes as C, sys
+sys.path.insert(0, %r)
+import paper_1106_0463_amd as lc
+from paper_1106_0463_amd._lib import AbelRule
+lib = lc.load()
+def check(st, h, what):
+    assert st == 2 and h.value == 777, (what, st, h.value, lib.lc_last_error())
+    assert lib.lc_last_error().decode() != "", what
+h = C.c_void_p(777)
+check(lib.lc_plan(1000, 4000, 48, 0, C.byref(h)), h, "lc_plan")
+rule = AbelRule(16, 0, 0.0, 0, None, 0.2, 3)
+check(lib.lc_plan_adaptive(1000, 4000, C.byref(rule), 0, C.byref(h)), h, "lc_plan_adaptive")
+N = (C.c_int64 * 2)(500, 40); M = (C.c_int64 * 2)(2000, 160); Q = (C.c_int32 * 2)(48, 48); P = (C.c_int * 2)(0, 1)
+check(lib.lc_plan_batch(2, N, M, Q, P, C.byref(h)), h, "lc_plan_batch")
+check(lib.lc_plan_gemm(512, 2048, 1000, 3, C.byref(h)), h, "lc_plan_gemm")
+assert lib.lc_plan(8, 16, 2, 0, C.byref(h)) == 0
+assert lib.lc_plan_destroy(h) == 0
+print("NOMEM_OK")
+''' % root
+    env = dict(os.environ, LC_ALLOC_LIMIT="65536")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "NOMEM_OK" in r.stdout, r.stdout + r.stderr
