@@ -174,7 +174,7 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
         case LC_GEMM_FP16X1: g->h16 = kF16; g->npc = 1; g->kmode = 1; g->scaled = 1; break;
         default: g->npc = 0; break;
     }
-    if (g->kmode && g->npc && !mgemm_shape_supported(g->kmode, g->ks, g->ns, g->kch)) {
+    if (g->kmode && g->npc && !mgemm_shape_supported(g->kmode, g->ks, g->ns, g->kch, direct != 0)) {
         free_gemm(g);
         return fail_status(LC_ERR_INVALID, who + "LC_MGEMM_STAGES / LC_MGEMM_KCH name no built product kernel");
     }

@@ -577,11 +577,15 @@ static void mgemm_defaults(int mode, int h16, bool d64, int &ks, int &ns, int &k
     // (at 8 their E_a reaches 1.0e-7 and 1.25e-7), 8 for bf16x3 and fp16x1,
     // whose 16-bit representation limits them above that anyway
     const bool long_chunks = mode == 1 || (mode == 3 && h16 == kBF16);
-    kch = d64 ? (kch ? kch : (long_chunks ? 8 : 4)) : 8;
+    // FP32 chunk length of the Abel form: 16 K-steps for the three-product
+    // modes (their fold into the second total every 8 steps cost 5%; E_a at
+    // full size 1.1e-8 either way), 8 for the six-product mode (no faster at
+    // 16, E_a 1.8e-8 -> 2.9e-8) and for one product
+    kch = d64 ? (kch ? kch : (long_chunks ? 8 : 4)) : (kch ? kch : (mode == 3 ? 16 : 8));
 }
 
-bool mgemm_shape_supported(int mode, int ks, int ns, int kch) {
-    if (kch != 0 && kch != 2 && kch != 4 && kch != 8) return false;
+bool mgemm_shape_supported(int mode, int ks, int ns, int kch, bool direct) {
+    if (direct ? (kch != 0 && kch != 2 && kch != 4 && kch != 8) : (kch != 0 && kch != 8 && kch != 16)) return false;
     if (ks == 0 && ns == 0) return true;
     static const int built[][3] = {{1, 32, 2}, {1, 32, 4}, {1, 16, 4}, {3, 32, 2}, {3, 16, 2},
                                    {3, 16, 3}, {3, 16, 4}, {6, 16, 2}, {6, 16, 3}};
@@ -613,7 +617,8 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
         return hipGetLastError();                                                                               \
     }
 #define LC_MG(T, MV, KSV, NSV)                                                                                  \
-    LC_MG1(T, MV, KSV, NSV, false, 8) LC_MG1(T, MV, KSV, NSV, true, 2) LC_MG1(T, MV, KSV, NSV, true, 4)         \
+    LC_MG1(T, MV, KSV, NSV, false, 8) LC_MG1(T, MV, KSV, NSV, false, 16)                                        \
+    LC_MG1(T, MV, KSV, NSV, true, 2) LC_MG1(T, MV, KSV, NSV, true, 4)                                           \
     LC_MG1(T, MV, KSV, NSV, true, 8)
 #define LC_MG_ALL(T)                                                                                            \
     LC_MG(T, 1, 32, 2) LC_MG(T, 1, 32, 4) LC_MG(T, 1, 16, 4)                                                    \

@@ -15,10 +15,11 @@ constexpr int kBF16 = 0, kF16 = 1;
 constexpr int kGemmBM = 128;
 
 // MFMA product shape of a plan: k per LDS stage and ring length (ks, ns;
-// 0: the per-mode default), and K-steps of 16 per FP64 flush of the direct
-// form's accumulators (kch: 2, 4 or 8; 0: per mode).  True when the library
-// holds a kernel for it.
-bool mgemm_shape_supported(int mode, int ks, int ns, int kch);
+// 0: the per-mode default), and K-steps of 16 per flush of the FP32 MFMA
+// accumulators into the second total (kch: 2, 4 or 8 for the direct form's
+// FP64 totals, 8 or 16 for the Abel form's FP32 totals; 0: per mode).  True
+// when the library holds a kernel for it.
+bool mgemm_shape_supported(int mode, int ks, int ns, int kch, bool direct);
 
 hipError_t launch_amat(int H, int P, int QA, const double *xc, const double *lam, const double2 *rowA,
                        const double2 *omt2, const double *wq, const double *s2, double *A, hipStream_t s);

@@ -275,3 +275,17 @@ def test_direct_chunk_lengths(lc, monkeypatch, mode, kch):
     E_c, E_a = _errors(C, coef, 777)
     banner(f"    E_c {E_c:.2e} E_a {E_a:.2e}")
     assert E_a <= BOUND[mode] * (1 if kch <= DEFAULT_KCH[mode] else 2)
+
+
+@pytest.mark.parametrize("kch", [8, 16])
+@pytest.mark.parametrize("mode", ["fp16x3", "bf16x3", "bf16x6", "fp16x1"])
+def test_abel_chunk_lengths(lc, monkeypatch, mode, kch):
+    # both FP32 chunk lengths of the Abel product (8 and 16 K-steps per fold
+    # into the second total; 16 is the three-product modes' default) on
+    # ragged sizes, within each mode's bound
+    monkeypatch.setenv("LC_MGEMM_KCH", str(kch))
+    banner(f"[gpu] gemm {mode} Abel KCH={kch}")
+    C, coef = _run(lc, mode, 1000, 1600, 777, 77, 500, seed=9)
+    E_c, E_a = _errors(C, coef, 777)
+    banner(f"    E_c {E_c:.2e} E_a {E_a:.2e}")
+    assert E_a <= BOUND[mode]
