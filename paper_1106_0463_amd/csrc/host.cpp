@@ -40,6 +40,32 @@ hipError_t device_alloc(void **p, size_t bytes) {
     return hipMalloc(p, bytes);
 }
 
+// LC_LOG=1 (read once): one stderr line per plan decision (grid size,
+// launch shapes, radix schedules, batch classes and DST groups).
+bool log_on() {
+    static const bool on = [] {
+        const char *ev = getenv("LC_LOG");
+        return ev && atoi(ev) != 0;
+    }();
+    return on;
+}
+
+void log_line(const char *fmt, ...) {
+    if (!log_on()) return;
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[lc] %s\n", buf);
+}
+
+std::string sched_str(const FftSched &s) {
+    std::string r;
+    for (int i = 0; i < s.npass; ++i) r += (i ? "x" : "") + std::to_string(s.radix[i]);
+    return r.empty() ? "-" : r;
+}
+
 static lc_status fail(lc_status s, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -469,6 +495,14 @@ lc_status lc_plan(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan_t 
     const double bytes = (double)H * Q * esz;
     p->fused_small = (bytes <= 256.0 * 1024 && H <= 4096 && fused_small_lds_bytes(H, Q) <= 65536);
     p->fused_threads = L <= 2048 ? 256 : 1024;
+    log_line("lc_plan: N=%lld M=%lld M_eff=%lld H=%lld Q=%d %s; quad vec=%d G=%d cpl=%d unroll=%d grid=%d; %s",
+             (long long)N, (long long)M, (long long)M_eff, (long long)H, Q, prec == LC_FP64 ? "fp64" : "fp32",
+             p->quad.vec, p->quad.G, p->quad.cpl, p->quad.unroll, p->quad.grid,
+             p->fused_small ? "one fused kernel" :
+             (L > kLdsFftMax ? ("four-step " + std::to_string(dcfg.L1) + "x" + std::to_string(dcfg.L2) + " (" +
+                                sched_str(dcfg.s1) + ", " + sched_str(dcfg.s2) + ")").c_str()
+                             : ("LDS FFT L=" + std::to_string(L) + " T=" + std::to_string(dcfg.threads) + " radix " +
+                                sched_str(dcfg.sched)).c_str()));
     *out = p;
     return LC_OK;
 }

@@ -555,6 +555,10 @@ extern "C" lc_status lc_plan_adaptive(int64_t N, int64_t M, const lc_abel_rule *
                            std::string("lc_plan_adaptive: ") + hipGetErrorString(e));
     }
     p->workspace_bytes = ws;
+    log_line("lc_plan_adaptive: N=%lld M_eff=%lld H=%lld samples=%lld panels=%lld (%.2f per row) max q=%d "
+             "rules=%zu lane cap G=%d %s", (long long)N, (long long)M_eff, (long long)H, (long long)nnz,
+             (long long)a->nseg, (double)a->nseg / (double)H, qmax, rules.size(), 4 << gcap,
+             L > kLdsFftMax ? "four-step FFT" : "LDS FFT");
     *out = p;
     return LC_OK;
 }

@@ -920,6 +920,18 @@ lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::
     hipGetDevice(&p->device);
     p->ext = st;
     p->workspace_bytes = st->ws_bytes;
+    if (log_on()) {
+        log_line("%s: B=%d sample bytes=%lld rules=%zu classes=%zu fused=%d+%d four-step=%zu parts=%d", who, B,
+                 (long long)st->f_bytes, st->qs.size(), st->classes.size(), st->nfused[0], st->nfused[1],
+                 st->large.size(), st->nparts);
+        for (auto &qc : st->classes)
+            log_line("  class R=%d %s: %zu functions, %lld rows, %d tiles; vec=%d G=%d cpl=%d unroll=%d grid=%d", qc.Q,
+                     qc.prec == LC_FP64 ? "fp64" : "fp32", qc.fns.size(), (long long)qc.rows, qc.ntiles, qc.cfg.vec,
+                     qc.cfg.G, qc.cfg.cpl, qc.cfg.unroll, qc.cfg.grid);
+        for (auto &g : st->groups)
+            log_line("  DST group: %s T=%d Lmax=%d, %d %s", g.multi ? "packed" : "LDS", g.threads, g.Lmax, g.n,
+                     g.multi ? "workgroups" : "functions");
+    }
     *out = p;
     return LC_OK;
 }

@@ -273,6 +273,11 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
     p->kind = LC_PLAN_GEMM;
     hipGetDevice(&p->device);
     p->ext = g;
+    log_line("%sP=%d M_eff=%lld H=%lld N=%lld mode=%d (%d pieces, %d products) rows=%lld padded=%lld "
+             "stages=%s chunk=%s", who.c_str(), P, (long long)g->M_eff, (long long)g->H, (long long)N, g->mode, g->npc,
+             g->kmode, (long long)g->R, (long long)g->Hpad,
+             g->ks ? (std::to_string(g->ks) + "," + std::to_string(g->ns)).c_str() : "default",
+             g->kch ? std::to_string(g->kch).c_str() : "default");
     *out = p;
     return LC_OK;
 }

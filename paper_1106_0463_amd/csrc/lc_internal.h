@@ -252,6 +252,9 @@ size_t fused_small_lds_bytes(int64_t H, int Q);
 // --- host helpers (host.cpp) ---------------------------------------------
 void set_error(const std::string &msg);
 hipError_t device_alloc(void **p, size_t bytes);  // hipMalloc behind the LC_ALLOC_LIMIT test hook
+bool log_on();                                   // LC_LOG=1
+void log_line(const char *fmt, ...);             // one "[lc] ..." line on stderr when LC_LOG=1
+std::string sched_str(const FftSched &s);        // "8x8x4" 
 int64_t smooth_len_at_least(int64_t L);           // smallest 2^a 3^b >= L
 FftSched make_sched(int L, const int *order = nullptr);
 void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w,

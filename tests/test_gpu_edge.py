@@ -201,3 +201,36 @@ print("NOMEM_OK")
     env = dict(os.environ, LC_ALLOC_LIMIT="65536")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and "NOMEM_OK" in r.stdout, r.stdout + r.stderr
+
+
+def test_plan_log():
+    """LC_LOG=1 prints one line per plan decision on stderr (grid size, launch
+    shapes, radix schedules, batch classes and DST groups); without it the
+    library prints nothing."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = r'''
+import sys
+sys.path.insert(0, %r)
+import paper_1106_0463_amd as lc
+lc.plan(100, 300, 17).destroy()
+lc.plan(700, 82000, 12).destroy()
+lc.plan(1000, 8192, 48).destroy()
+lc.plan_adaptive(64, 512, q=16, grade_ratio=0.2, grade_levels=3).destroy()
+lc.plan_batch([30, 300], [120, 1200], [48, 24], ["fp64", "fp32"]).destroy()
+lc.plan_gemm(64, 256, 100, "fp16x3").destroy()
+''' % root
+    for log in ("1", "0"):
+        env = dict(os.environ, LC_LOG=log)
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        lines = [s for s in r.stderr.splitlines() if s.startswith("[lc]")]
+        if log == "0":
+            assert not lines, lines
+            continue
+        text = "\n".join(lines)
+        for want in ("lc_plan: N=100 M=300 M_eff=", "one fused kernel", "four-step", "LDS FFT L=2048", "lc_plan_adaptive: N=64",
+                     "lc_plan_batch: B=2", "class R=48 fp64", "class R=24 fp32", "DST group", "lc_plan_gemm: P=64"):
+            assert want in text, (want, text)
