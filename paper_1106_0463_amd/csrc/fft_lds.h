@@ -286,13 +286,46 @@ __device__ __forceinline__ void dst_pack_lds(double2 *__restrict__ lds, PhiAt ph
 
 // DST-III unpack and rescale: c_n = (2n+1) a_n with
 //   a_n = (1/H) [ sum_{j<H} phi_j sin(pi (2n+1) j / (2H)) + (1/2)(-1)^n phi_H ]
-//       = (-1)^n X_n / H,  X_{2m} = v_m / 2,  X_{2m+1} = v_{H-1-m} / 2.
+//       = (-1)^n X_n / H,  X_{2m} = v_m / 2,  X_{2m+1} = v_{H-1-m} / 2,
+// evaluated as ((2n+1) (-1)^n v) * r with r = 1/(2H) rounded (exact, so
+// the same as dividing by 2H, when H is a power of two); r is loop-invariant
+// in the callers' loops, so its division is done once.
 __device__ __forceinline__ double dst_post(int64_t n, const double2 *z, int64_t H) {
     const int64_t q = (n & 1) ? (H - 1 - (n >> 1)) : (n >> 1);
     const double2 zz = z[q >> 1];
     const double v = (q & 1) ? zz.y : zz.x;
     const double sgn = (n & 1) ? -1.0 : 1.0;
-    return (double)(2 * n + 1) * sgn * v / (double)(2 * H);
+    return (double)(2 * n + 1) * sgn * v * (1.0 / (double)(2 * H));
+}
+
+// dst_post for every n < N by the T threads of a block, four coefficients
+// per thread and step: with H even, n = 4j .. 4j+3 read only z[j] and
+// z[H/2 - 1 - j] (q = 2j, 2j+1 and H-1-2j, H-2-2j), so a step is two LDS
+// reads, eight multiplications and, where c + 4j is 16-byte aligned, two
+// 16-byte stores.  The values are dst_post's bit for bit.  N <= H.
+template <int T>
+__device__ __forceinline__ void dst_post_block(double *__restrict__ c, int N, const double2 *__restrict__ z, int H) {
+    const double r = 1.0 / (double)(2 * H);
+    const bool vec = ((uintptr_t)c & 15) == 0;
+    const int nq = N >> 2;
+#pragma unroll 2
+    for (int j = threadIdx.x; j < nq; j += T) {
+        const double2 a = z[j], b = z[(H >> 1) - 1 - j];
+        const double f = (double)(8 * j + 1);
+        const double c0 = f * a.x * r, c1 = -(f + 2.0) * b.y * r;
+        const double c2 = (f + 4.0) * a.y * r, c3 = -(f + 6.0) * b.x * r;
+        if (vec) {
+            reinterpret_cast<double2 *>(c)[2 * j] = make_double2(c0, c1);
+            reinterpret_cast<double2 *>(c)[2 * j + 1] = make_double2(c2, c3);
+        } else {
+            c[4 * j] = c0;
+            c[4 * j + 1] = c1;
+            c[4 * j + 2] = c2;
+            c[4 * j + 3] = c3;
+        }
+    }
+    const int n = 4 * nq + (int)threadIdx.x;
+    if (n < N) c[n] = dst_post(n, z, H);
 }
 
 }  // namespace lc

@@ -53,6 +53,8 @@ struct GemmState {
     int Bmax = 0;
     void *X = nullptr;
     int *colexp = nullptr;
+    int *cexp = nullptr;              // FP16: chunk exponents [nch][Bpad]
+    unsigned char *cscale = nullptr;  // FP16: chunk factors [Bpad/128][nchp][128]
     float *Out32 = nullptr;
     double *Out64 = nullptr;
     rocblas_handle rb = nullptr;
@@ -78,6 +80,8 @@ void free_b(GemmState *g) {
     g->ballocs.clear();
     g->X = nullptr;
     g->colexp = nullptr;
+    g->cexp = nullptr;
+    g->cscale = nullptr;
     g->Out32 = nullptr;
     g->Out64 = nullptr;
     g->Bmax = 0;
@@ -105,6 +109,11 @@ hipError_t reserve(GemmState *g, int B) {
         chk(galloc(g, &x, (size_t)g->npc * g->Bpad * g->Kp, true));
         g->X = x;
         chk(galloc(g, &g->colexp, (size_t)B, true));
+        if (g->scaled) {
+            const int nchp = mgemm_scale_chunks(g->Kp);
+            chk(galloc(g, &g->cexp, (size_t)(g->Kp / 16 + kExpChunk16 - 1) / kExpChunk16 * g->Bpad, true));
+            chk(galloc(g, &g->cscale, (size_t)nchp * g->Bpad, true));
+        }
         if (!g->direct) chk(galloc(g, &g->Out32, (size_t)B * g->H, true));
     }
     if (e == hipSuccess) g->Bmax = B;
@@ -340,16 +349,17 @@ lc_status lc_execute_gemm(lc_plan_t p, const double *F_dev, int32_t B, double *C
         return LC_OK;
     }
     const int64_t xps = g->Bpad * g->Kp;
-    e = launch_split_cols(g->h16, F_dev, g->P, B, g->Kp, g->npc, g->X, xps, g->colexp, g->scaled, stream);
+    e = launch_split_cols(g->h16, F_dev, g->P, B, g->Kp, g->npc, g->X, xps, g->Bpad, g->cexp, g->colexp, g->cscale,
+                          stream);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: split: ") + hipGetErrorString(e));
     if ((e = timing_begin(p, stream, &slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
     if (g->direct)
         e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->N, g->Kp, nullptr, (int)g->N,
-                         C_dev, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, g->ks, g->ns,
-                         g->kch, stream);
+                         C_dev, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, g->cscale, g->ks,
+                         g->ns, g->kch, stream);
     else
         e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->H, g->Kp, g->Out32,
-                         (int)g->H, nullptr, nullptr, nullptr, g->ks, g->ns, g->kch, stream);
+                         (int)g->H, nullptr, nullptr, nullptr, g->cscale, g->ks, g->ns, g->kch, stream);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: mfma: ") + hipGetErrorString(e));
     if ((e = timing_end(p, stream, slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
     if (g->direct) return LC_OK;

@@ -308,7 +308,7 @@ __global__ __launch_bounds__(T) void k_bdst_lds(const double *__restrict__ phi_a
     __syncthreads();
     fft_lds_one<T, 8>(lds, L, sch, fn.tw_fft);
     double *c = c_arena + fn.c_off;
-    for (int64_t n = threadIdx.x; n < fn.N; n += T) c[n] = dst_post(n, lds, H);
+    dst_post_block<T>(c, (int)fn.N, lds, (int)H);
 }
 
 hipError_t prepare_bdst(int threads, int Lmax) {
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void k_bfused(const unsigned char *__restrict_
     __syncthreads();
     fft_lds_one<256, 8>(lds, L, fn.sched, fn.tw_fft);
     double *c = c_arena + fn.c_off;
-    for (int64_t n = threadIdx.x; n < fn.N; n += 256) c[n] = dst_post(n, lds, H);
+    dst_post_block<256>(c, (int)fn.N, lds, (int)H);
 }
 
 int fuse_lanes(int prec, int Q) {

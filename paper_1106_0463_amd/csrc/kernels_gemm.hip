@@ -9,7 +9,9 @@
 //   k_amat        A in FP64, one workgroup per row j
 //   k_split_rows  A -> 16-bit pieces (bf16, or fp16 with a power-of-two row
 //                 scale, k_rowexp), in MFMA fragment order
-//   k_colmax / k_split_cols  F [P][B] FP64 -> pieces of F^T, fragment order
+//   k_split_cols  F [P][B] FP64 -> pieces of F^T, fragment order (FP16:
+//                 one power-of-two scale per function and chunk of 256 p)
+//   k_colscale    per-function exponent and chunk factors of the FP16 split
 //   k_mgemm       Out[b][j] = sum_{(u,v)} sum_p X_u[b][p] Y_v[j][p] on MFMA
 //                 (32x32x16, FP32 accumulation), fused over the piece
 //                 products of the precision mode
@@ -134,6 +136,8 @@ hipError_t launch_amat(int H, int P, int QA, const double *xc, const double *lam
 // bytes per lane, which no bank or channel pattern can split.  Rows are
 // padded to the block tile and k to Kp with zeros.
 constexpr int kSplitKW = 4;  // k fragments per wave in the column split
+// K-steps of 16 per FP16 column-exponent chunk: one column-split block
+static_assert(4 * kSplitKW == kExpChunk16, "a split block covers one exponent chunk");
 
 __device__ __forceinline__ int64_t fo_offset(int64_t r, int k, int K16) {
     return ((r >> 5) * K16 + (k >> 4)) * 512 + (((r & 31) + ((k >> 3) & 1) * 32) << 3) + (k & 7);
@@ -250,41 +254,22 @@ hipError_t launch_transpose_a(const double *A, int H, int P, double *AT, hipStre
     return hipGetLastError();
 }
 
-// per-function exponent colexp[b] = ilogb(max_p |F[p][b]|) + 1: a fill, then
-// blocks of 256 functions x 64 rows fold their partial maxima in with an
-// integer atomic max (the exponent is monotone in the magnitude).
-__global__ __launch_bounds__(256) void k_colexp_init(int B, int *__restrict__ colexp) {
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    if (b < B) colexp[b] = -2000;
-}
-
-__global__ __launch_bounds__(256) void k_colmax(const double *__restrict__ F, int P, int B,
-                                                int *__restrict__ colexp) {
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    const int p0 = blockIdx.y * 64;
-    if (b >= B) return;
-    const int p1 = p0 + 64 < P ? p0 + 64 : P;
-    double m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int p = p0;
-    for (; p + 8 <= p1; p += 8) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) m[e] = fmax(m[e], fabs(__builtin_nontemporal_load(F + (int64_t)(p + e) * B + b)));
-    }
-    for (; p < p1; ++p) m[0] = fmax(m[0], fabs(F[(int64_t)p * B + b]));
-    double mm = 0.0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) mm = fmax(mm, m[e]);
-    if (mm > 0.0) atomicMax(colexp + b, ilogb(mm) + 1);
-}
-
 // F [P][B] -> pieces X_i in fragment order over Bpad rows (function b is
 // row b); one thread per (b, 8 consecutive p).  Fragments are numbered with
 // the row block fastest, so that the waves resident together read long
 // contiguous stretches of the same rows of F.
-template <typename H16, int NPC>
+//
+// FP16 (SC): block (rb, kg) covers exactly the 256 samples p of exponent
+// chunk kg for its 32 functions, so it scales them by 2^-e with its own
+// chunk exponent e = ilogb(max |F|) + 1 (at least -1000) and stores e in
+// cexp[kg][b]: one read of F instead of a maximum pass over all of it
+// before the split.  The product rescales each chunk's FP32 sums by
+// 2^(e - E_b) at the fold of its accumulators, E_b the function's largest
+// chunk exponent (k_colscale).
+template <typename H16, int NPC, bool SC>
 __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F, int P, int B, int K16, int RB,
                                                     H16 *__restrict__ X, int64_t piece_stride,
-                                                    const int *__restrict__ colexp) {
+                                                    int *__restrict__ cexp, int64_t Bpad) {
     // block (rb, kg): wave w writes the kSplitKW consecutive k fragments from
     // (4 kg + w) kSplitKW on, so a block's fragments of one piece are one
     // contiguous 4 kSplitKW KiB run; consecutive blocks take consecutive rb,
@@ -292,7 +277,6 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F
     const int rb = (int)(blockIdx.x % (unsigned)RB), kg = (int)(blockIdx.x / (unsigned)RB);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int b = rb * 32 + (lane & 31);
-    const double sc = (colexp && b < B) ? ldexp(1.0, -max(colexp[b], -1000)) : 1.0;
     // every load of the wave's kSplitKW fragments first, branch-free (indices
     // past F clamped, their values zeroed below), so that all are in flight
     // together; masked loads would each wait for the one before
@@ -307,12 +291,35 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F
     }
     // (the pieces of fragments past K16 are computed and dropped: only their
     // stores are conditional, so the loads above stay ahead of every use)
+    double m = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSplitKW; ++j) {
+        const int k = ((kg * 4 + w) * kSplitKW + j) * 16 + (lane >> 5) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            v[j][e] = (b < B && k + e < P) ? v[j][e] : 0.0;
+            m = fmax(m, fabs(v[j][e]));
+        }
+    }
+    if constexpr (SC) {
+        __shared__ double red[4][32];
+        m = fmax(m, __shfl_xor(m, 32, 64));  // lanes l and l + 32 hold the same function
+        if (lane < 32) red[w][lane] = m;
+        __syncthreads();
+        const int l = lane & 31;
+        m = fmax(fmax(red[0][l], red[1][l]), fmax(red[2][l], red[3][l]));
+        const int ex = m > 0.0 ? max(ilogb(m) + 1, -1000) : -1000;
+        if (w == 0 && lane < 32) cexp[(int64_t)kg * Bpad + b] = ex;
+        const double sc = ldexp(1.0, -ex);
+#pragma unroll
+        for (int j = 0; j < kSplitKW; ++j)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[j][e] *= sc;
+    }
 #pragma unroll
     for (int j = 0; j < kSplitKW; ++j) {
         const int k16 = (kg * 4 + w) * kSplitKW + j;
         const int k = k16 * 16 + (lane >> 5) * 8;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[j][e] = (b < B && k + e < P) ? v[j][e] * sc : 0.0;
         u32x4 out[NPC];
         split8<H16, NPC>(v[j], out);
         if (k16 < K16) {
@@ -321,6 +328,30 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F
                 *reinterpret_cast<u32x4 *>(X + i * piece_stride + fo_offset(b, k, K16)) = out[i];
         }
     }
+}
+
+// Per function b < Bt (the rows of the call's block tiles; cexp's row
+// stride is Bpad): E_b = max over chunks of cexp[c][b] (the exponent
+// of max_p |F[p][b]|, applied by the DST or the direct form's epilogue), and
+// the chunk factors 2^(cexp[c][b] - E_b) as biased exponent bytes
+// u = max(cexp - E_b + 127, 0) (the FP32 bit pattern u << 23; 0, a zero
+// factor, for chunks 2^127 or more below the function's largest, whose share
+// is far below FP32's rounding) in cs[b / 128][c][b % 128] for c < nchp (the
+// product's block tile of 128 functions reads its nchp * 128 bytes as one
+// run; chunks c >= nch are zero).
+__global__ __launch_bounds__(256) void k_colscale(const int *__restrict__ cexp, int nch, int nchp, int64_t Bpad,
+                                                  int64_t Bt, int B, int *__restrict__ colexp,
+                                                  unsigned char *__restrict__ cs) {
+    // thread (b, c): blockIdx.y = c < nchp; every thread takes E_b over all
+    // chunks itself (nch independent, cached loads)
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (b >= Bt) return;
+    int E = -1000;
+    for (int i = 0; i < nch; ++i) E = max(E, cexp[i * Bpad + b]);
+    if (c == 0 && b < B) colexp[b] = E;
+    cs[(b >> 7) * nchp * 128 + c * 128 + (b & 127)] =
+        c < nch ? (unsigned char)max(0, cexp[c * Bpad + b] - E + 127) : (unsigned char)0;
 }
 
 hipError_t launch_split_rows(int h16, const double *S, int64_t roff, int64_t rs, int64_t cs, int H, int P, int Kp,
@@ -352,32 +383,33 @@ hipError_t launch_split_rows(int h16, const double *S, int64_t roff, int64_t rs,
 }
 
 hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int npc, void *X,
-                             int64_t piece_stride, int *colexp, int scaled, hipStream_t s) {
-    if (scaled) {
-        hipLaunchKernelGGL(k_colexp_init, dim3((B + 255) / 256), dim3(256), 0, s, B, colexp);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_colmax, dim3((B + 255) / 256, (P + 63) / 64), dim3(256), 0, s, F, P, B, colexp);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+                             int64_t piece_stride, int64_t Bpad, int *cexp, int *colexp, unsigned char *cscale,
+                             hipStream_t s) {
     const int K16 = Kp / 16;
-    const int RB = (B + kGemmBM - 1) / kGemmBM * (kGemmBM / 32);  // row blocks up to the padded B
-    const dim3 grid((unsigned)((int64_t)RB * ((K16 + 4 * kSplitKW - 1) / (4 * kSplitKW))));
-    const int *ce = scaled ? colexp : nullptr;
-#define LC_SC(T, NP)                                                                                     \
+    const int64_t Bt = ((int64_t)B + kGemmBM - 1) / kGemmBM * kGemmBM;  // rows of the call's block tiles
+    const int RB = (int)(Bt / 32);
+    const int nch = (K16 + kExpChunk16 - 1) / kExpChunk16;
+    const dim3 grid((unsigned)((int64_t)RB * nch));
+    const bool sc = h16 == kF16;
+    if (sc && (!cexp || !colexp || !cscale)) return hipErrorInvalidValue;
+#define LC_SC(T, NP, SCV)                                                                                \
     if (npc == NP) {                                                                                     \
-        hipLaunchKernelGGL((k_split_cols<T, NP>), grid, dim3(256), 0, s, F, P, B, K16, RB, (T *)X,      \
-                           piece_stride, ce);                                                            \
-        return hipGetLastError();                                                                        \
+        hipLaunchKernelGGL((k_split_cols<T, NP, SCV>), grid, dim3(256), 0, s, F, P, B, K16, RB, (T *)X, \
+                           piece_stride, cexp, Bpad);                                                    \
+        e = hipGetLastError();                                                                           \
+    } else
+    hipError_t e = hipErrorInvalidValue;
+    if (!sc) {
+        LC_SC(__bf16, 1, false) LC_SC(__bf16, 2, false) LC_SC(__bf16, 3, false) {}
+        return e;
     }
-    if (h16 == kBF16) {
-        LC_SC(__bf16, 1) LC_SC(__bf16, 2) LC_SC(__bf16, 3)
-    } else {
-        LC_SC(_Float16, 1) LC_SC(_Float16, 2) LC_SC(_Float16, 3)
-    }
+    LC_SC(_Float16, 1, true) LC_SC(_Float16, 2, true) LC_SC(_Float16, 3, true) {}
 #undef LC_SC
-    return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+    const int nchp = mgemm_scale_chunks(Kp);
+    hipLaunchKernelGGL(k_colscale, dim3((unsigned)((Bt + 255) / 256), (unsigned)nchp), dim3(256), 0, s, cexp, nch,
+                       nchp, Bpad, Bt, B, colexp, cscale);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ MFMA GEMM ---
@@ -439,8 +471,9 @@ template <typename H16, int MODE, int KS, int NS, bool D64, int KCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mgemm(
     const H16 *__restrict__ X, int64_t xps, const H16 *__restrict__ Y, int64_t yps, int Bn, int Hn, int K16,
     float *__restrict__ Out, int ldo, double *__restrict__ C64, const int *__restrict__ rowexp,
-    const int *__restrict__ colexp) {
+    const int *__restrict__ colexp, const unsigned char *__restrict__ cscale, int nchp) {
     using PR = Prods<MODE>;
+    constexpr bool CS = std::is_same<H16, _Float16>::value;  // FP16: per-chunk column factors
     constexpr int NX = PR::nx, NY = PR::ny;
     constexpr int KF = KS / 16;                        // fragments along k per stage
     constexpr int FX = NX * 4 * KF, FY = NY * 4 * KF;  // fragments per stage (4 row blocks of 32)
@@ -476,6 +509,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
     };
 
+    static_assert(kExpChunk16 % KCH == 0, "a fold must not span two exponent chunks");
     // Two-level accumulation: the MFMA accumulator covers KCH K-steps of 16
     // and is then added into a second total and cleared, so that no FP32
     // chain runs over more than KCH MFMA steps per product (each step
@@ -495,6 +529,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 acc[a][b][v] = 0.f;
                 tot[a][b][v] = 0;
             }
+
+    // FP16: the chunk factors of the block's 128 functions, [nchp][128] bytes
+    // after the ring, copied before the first stage so that the first
+    // stage's wait covers them
+    const unsigned *scl = reinterpret_cast<const unsigned *>(ring + NS * FST * 64);
+    if constexpr (CS) {
+        const unsigned char *src = cscale + (int64_t)(rbx / 4) * nchp * 128;
+        for (int i = wave; i < nchp / 8; i += 4)
+            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(src + i * 1024 + lane * 16),
+                                             (__attribute__((address_space(3))) void *)(ring + NS * FST * 64 + i * 64),
+                                             16, 0, 0);
+    }
+    // fold of the accumulators into the totals; FP16 scales chunk c's sums of
+    // row r by 2^(u - 127), u its factor byte (D rows of lane l, register v:
+    // 8 (v/4) + 4 (l/32) + v%4, so four consecutive bytes per v/4)
+    auto fold = [&](int c) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                unsigned wd = 0;
+                if constexpr (CS) wd = scl[(c * 128 + (wm + a) * 32 + 8 * g + 4 * (lane >> 5)) >> 2];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float f = CS ? __builtin_bit_cast(float, ((wd >> (8 * i)) & 0xffu) << 23) : 1.f;
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const int v = 4 * g + i;
+                        tot[a][b][v] += CS ? (TotT)(acc[a][b][v] * f) : (TotT)acc[a][b][v];
+                        acc[a][b][v] = 0.f;
+                    }
+                }
+            }
+    };
 
     const int nk = K16 / KF;  // stages
 #pragma unroll
@@ -526,26 +594,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
                     for (int b = 0; b < 2; ++b)
                         acc[a][b] = Mfma<H16>::run(fx[PR::u[pi]][a], fy[PR::v[pi]][b], acc[a][b]);
-            if (++kstep == KCH) {
+            if (++kstep == KCH) {  // KCH divides kExpChunk16: a fold never spans two chunks
                 kstep = 0;
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-#pragma unroll
-                        for (int v = 0; v < 16; ++v) {
-                            tot[a][b][v] += (TotT)acc[a][b][v];
-                            acc[a][b][v] = 0.f;
-                        }
+                fold((kt * KF + kf) / kExpChunk16);
             }
         }
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) tot[a][b][v] += (TotT)acc[a][b][v];
+    fold((K16 - 1) / kExpChunk16);
     // D layout: lane l, register v -> row 8 (v/4) + 4 (l/32) + (v%4), col l%32
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -567,7 +622,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 }
 
 // stage depth (k per stage, ring length) of each mode: LDS per block is
-// NS * (NX + NY) * 4 * KS/16 KiB, at most 80 KiB so that two blocks share a CU
+// NS * (NX + NY) * 4 * KS/16 KiB (+ nchp / 8 KiB of FP16 chunk factors, at
+// most 8 KiB for P <= 16384), at most 80 KiB so that two blocks share a CU
 static void mgemm_defaults(int mode, int h16, bool d64, int &ks, int &ns, int &kch) {
     if (!ks) {
         ks = mode == 1 ? 32 : 16;
@@ -595,16 +651,18 @@ bool mgemm_shape_supported(int mode, int ks, int ns, int kch, bool direct) {
 }
 
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
-                        int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp, int ks,
-                        int ns, int kch, hipStream_t s) {
+                        int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
+                        const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s) {
     if (Kp % 32) return hipErrorInvalidValue;
+    if (h16 == kF16 && !cscale) return hipErrorInvalidValue;
+    const int nchp = mgemm_scale_chunks(Kp);
     const int K16 = Kp / 16;
     const bool d64 = C64 != nullptr;
     int KS = ks, NS = ns;
     mgemm_defaults(mode, h16, d64, KS, NS, kch);
     const int grid = ((Bn + kGemmBM - 1) / kGemmBM) * ((Hn + 127) / 128);
     const int npx = mode == 1 ? 1 : (mode == 3 ? 2 : 3);
-    const size_t lds = (size_t)NS * 2 * npx * 4 * (KS / 16) * 1024;
+    const size_t lds = (size_t)NS * 2 * npx * 4 * (KS / 16) * 1024 + (h16 == kF16 ? (size_t)nchp * 128 : 0);
 #define LC_MG1(T, MV, KSV, NSV, DV, KV)                                                                         \
     if (mode == MV && KS == KSV && NS == NSV && d64 == DV && kch == KV) {                                       \
         if (lds > 65536) {                                                                                      \
@@ -613,7 +671,7 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
             if (e != hipSuccess) return e;                                                                      \
         }                                                                                                       \
         hipLaunchKernelGGL((k_mgemm<T, MV, KSV, NSV, DV, KV>), dim3(grid), dim3(256), lds, s, (const T *)X,    \
-                           xps, (const T *)Y, yps, Bn, Hn, K16, Out, ldo, C64, rowexp, colexp);                \
+                           xps, (const T *)Y, yps, Bn, Hn, K16, Out, ldo, C64, rowexp, colexp, cscale, nchp);  \
         return hipGetLastError();                                                                               \
     }
 #define LC_MG(T, MV, KSV, NSV)                                                                                  \
@@ -663,8 +721,7 @@ __global__ __launch_bounds__(T) void k_gdst_lds(const PhiT *__restrict__ Out, in
     dst_pack_lds<T, 8>(lds, ph, H, L, tw_pre, tw_pack);
     __syncthreads();
     fft_lds_one<T, 8>(lds, L, sch, tw_fft);
-    double *c = C + (int64_t)b * N;
-    for (int64_t n = threadIdx.x; n < N; n += T) c[n] = dst_post(n, lds, H);
+    dst_post_block<T>(C + (int64_t)b * N, (int)N, lds, (int)H);
 }
 
 // ------------------------------------- twist folded into the Abel matrix ---
@@ -729,8 +786,7 @@ __global__ __launch_bounds__(T) void k_gdst_z(const PhiT *__restrict__ Out, int 
     }
     __syncthreads();
     fft_lds_one<T, 8>(lds, L, sch, tw_fft);
-    double *c = C + (int64_t)b * N;
-    for (int64_t n = threadIdx.x; n < N; n += T) c[n] = dst_post(n, lds, H);
+    dst_post_block<T>(C + (int64_t)b * N, (int)N, lds, (int)H);
 }
 
 hipError_t launch_gdst_z(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,

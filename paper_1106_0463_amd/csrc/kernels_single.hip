@@ -391,7 +391,7 @@ __global__ __launch_bounds__(T) void k_dst_lds(const double *__restrict__ phi, i
     dst_pack_lds<T, 8>(lds, ph, H, L, tw_pre, tw_pack);
     __syncthreads();
     fft_lds_one<T, 8>(lds, L, sch, tw_fft);
-    for (int64_t n = threadIdx.x; n < N; n += T) c[n] = dst_post(n, lds, H);
+    dst_post_block<T>(c, (int)N, lds, (int)H);
 }
 
 // Four-step FFT of length L = L1 * L2 (k = L2 k1 + k2, p = p1 + L1 p2):
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(TH) void k_fused_small(const T *__restrict__ f, con
     for (int k = threadIdx.x; k < L; k += TH) lds[k] = dst_pack(k, ph, H, L, tw_pre, tw_pack);
     __syncthreads();
     fft_lds<TH, 8>(lds, L, 1, sch, tw_fft, 1);
-    for (int64_t n = threadIdx.x; n < N; n += TH) c[n] = dst_post(n, lds, H);
+    dst_post_block<TH>(c, (int)N, lds, (int)H);
 }
 
 hipError_t launch_fused_small(int threads, int prec, const void *f, const double *w, const double *s2,

@@ -289,3 +289,80 @@ def test_abel_chunk_lengths(lc, monkeypatch, mode, kch):
     E_c, E_a = _errors(C, coef, 777)
     banner(f"    E_c {E_c:.2e} E_a {E_a:.2e}")
     assert E_a <= BOUND[mode]
+
+
+def _wide_range_columns(x, B, seed):
+    """F [P][B] whose columns span many binary orders across the grid and
+    between functions: x^200 (samples near x = 0 underflow to zero while
+    those near the ends are O(1)), e^{+-300 x}, a zero column, one series
+    and its copies scaled by 2^600 and 2^-600, e^{300 x} scaled by 2^-400,
+    and series scaled by 10^U(-30, 30)."""
+    rng = np.random.default_rng(seed)
+    F = np.empty((x.size, B))
+    F[:, 0] = x ** 200
+    F[:, 1] = np.exp(300 * x)
+    F[:, 2] = np.exp(-300 * x)
+    F[:, 3] = 0.0
+    coef = W.gemm_batch_coeffs(B, 400, seed=seed)
+    for b in range(4, B):
+        F[:, b] = npleg.legval(x, coef[b])
+    F[:, 5] = np.ldexp(F[:, 4], 600)
+    F[:, 6] = np.ldexp(F[:, 4], -600)
+    F[:, 7] = np.ldexp(F[:, 1], -400)
+    F[:, 8:] *= 10.0 ** rng.uniform(-30, 30, B - 8)
+    return F
+
+
+# (column, copy of, power of two) in _wide_range_columns
+SCALED_COPIES = ((5, 4, 600), (6, 4, -600), (7, 1, -400))
+
+
+@pytest.mark.parametrize("mode,bound", [_mode_param("fp16x3", 1e-7), _mode_param("fp16x1", 1e-3)])
+@pytest.mark.parametrize("direct", [False, True], ids=["abel", "direct"])
+def test_fp16_chunk_exponents(lc, mode, bound, direct):
+    # FP16 pieces carry one power-of-two exponent per function and chunk of
+    # 256 samples, and the product folds each chunk's FP32 sums back in with
+    # its factor.  On columns spanning hundreds of binary orders (across the
+    # grid and between functions):
+    # * a column scaled by 2^k gives its copy's coefficients times 2^k bit
+    #   for bit (every exponent shifts by k; nothing else changes);
+    # * every function keeps max|da_n| <= bound max|f| against the FP64
+    #   product of the same matrix (the FP32 sums round relative to the
+    #   samples: x^200 and e^{300 x} have coefficients 11 and 28 times below
+    #   their largest samples), and the plain series max|da_n| <= bound max|a_n|;
+    # * a zero column gives zeros.
+    # Two calls in a row on one plan, the second with fewer functions (fewer
+    # block tiles than reserved).
+    import torch
+    banner(f"[gpu] {mode} {'direct' if direct else 'abel'}: per-chunk column exponents")
+    P, M, N, B = 1000, 2048, 777, 77
+    plan = lc.plan_legendre_matrix if direct else lc.plan_gemm
+    g64, g16 = plan(P, M, N, "fp64"), plan(P, M, N, mode)
+    x = g16.nodes.cpu().numpy()
+    F = _wide_range_columns(x, B, 13)
+    n = np.arange(N)
+    for nb in (B, 33):
+        Fd = torch.from_numpy(np.ascontiguousarray(F[:, :nb])).cuda()
+        C16 = g16.execute(Fd)
+        C64 = g64.execute(Fd)
+        torch.cuda.synchronize()
+        c16 = C16.cpu().numpy()
+        a16, a64 = c16 / (2 * n + 1), C64.cpu().numpy() / (2 * n + 1)
+        assert np.all(c16[3] == 0.0)
+        for b, src, k in SCALED_COPIES:
+            assert np.array_equal(c16[b], np.ldexp(c16[src], k)), (b, src, k)
+        worst_f = worst_a = 0.0
+        for b in range(nb):
+            if b == 3:
+                continue
+            fmax, amax = np.max(np.abs(F[:, b])), np.max(np.abs(a64[b]))
+            assert np.isfinite(fmax) and amax > 0.0, b
+            d = np.max(np.abs(a16[b] - a64[b]))
+            assert d <= bound * fmax, (nb, b, d / fmax)
+            worst_f = max(worst_f, d / fmax)
+            if b >= 8:
+                assert d <= bound * amax, (nb, b, d / amax)
+                worst_a = max(worst_a, d / amax)
+        banner(f"    B={nb}: worst max|da|/max|f| {worst_f:.2e}, series max|da|/max|a| {worst_a:.2e}")
+    g16.destroy()
+    g64.destroy()
