@@ -167,13 +167,56 @@ __device__ void fft_lds(double2 *__restrict__ lds, int Lsub, int nsub, const Fft
     else fft_passes<T, EPT, false>(lds, Lsub, nsub, sch, tw, (int)tw_stride);
 }
 
+// ------------------------------------------------ octant twiddles ---
+// The FFT twiddles tw[m] = e^{2 pi i m / L} (m < L, L divisible by 8) follow
+// from the first octant tab[j] = tw[j], j <= L/8, by the exact quarter-turn
+// and octant symmetries.  The host builds its table with the same reduction
+// (quadrant, then the angle or its complement to a quarter turn, at most
+// pi/4), so these are its values bit for bit.  The compile-time passes read
+// an LDS copy of the octant (L/8 + 1 entries after the transform's L values)
+// instead of the global table: global twiddle reads wait behind the
+// streaming loads and stores of the kernels around the FFT.
+template <int LS>
+__device__ __forceinline__ double2 tw_octant(const double2 *__restrict__ tab, int m) {
+    constexpr int Q = LS / 4, O = LS / 8;
+    const int q = (m / Q) & 3, r = m % Q;
+    const bool hi = r > O;  // angle past pi/4 in its quadrant: the complement's sine and cosine
+    const double2 t = tab[hi ? Q - r : r];
+    const double c = hi ? t.y : t.x, sn = hi ? t.x : t.y;
+    return q == 0 ? make_double2(c, sn) : q == 1 ? make_double2(-sn, c) : q == 2 ? make_double2(-c, -sn)
+                                                                             : make_double2(sn, -c);
+}
+
+// LDS bytes of a one-transform DST workgroup: L values and the octant.
+__host__ __device__ constexpr size_t fft_lds_bytes(int64_t L) { return (size_t)(L + L / 8 + 1) * 16; }
+
+// The octant of tw (L/8 + 1 <= 2T values: at most two per thread for
+// L <= 8T), read at clamped indices so that both reads are issued at once
+// with the caller's first loads; octant_store puts them in LDS, before the
+// barrier that precedes the FFT.
+struct OctantRegs {
+    double2 a, b;
+};
+template <int T>
+__device__ __forceinline__ OctantRegs octant_load(const double2 *__restrict__ tw, int L) {
+    const int n = L / 8 + 1;
+    return {tw[min((int)threadIdx.x, n - 1)], tw[min((int)threadIdx.x + T, n - 1)]};
+}
+template <int T>
+__device__ __forceinline__ void octant_store(double2 *__restrict__ tab, const OctantRegs &o, int L) {
+    const int n = L / 8 + 1;
+    if ((int)threadIdx.x < n) tab[threadIdx.x] = o.a;
+    if ((int)threadIdx.x + T < n) tab[threadIdx.x + T] = o.b;
+}
+
 // One transform of power-of-two length LS whose pass stride NS is a
 // compile-time constant: the butterfly's quotient and remainder by NS and
 // its twiddle offsets are shifts, masks and constants, where the run-time
 // pass divides.  Each pass computes what stockham_pass computes for the same
 // radix and stride.
-template <int R, int T, int LS, int NS>
-__device__ __forceinline__ void stockham_fixed(double2 *__restrict__ lds, const double2 *__restrict__ tw) {
+template <int R, int T, int LS, int NS, bool OCT>
+__device__ __forceinline__ void stockham_fixed(double2 *__restrict__ lds, const double2 *__restrict__ tw,
+                                               const double2 *__restrict__ tab) {
     constexpr int nbs = LS / R, span = NS * R, twstep = LS / span;
     constexpr int MAXB = (nbs + T - 1) / T;
     const int tid = threadIdx.x;
@@ -189,7 +232,8 @@ __device__ __forceinline__ void stockham_fixed(double2 *__restrict__ lds, const 
             const int k = b % NS, q = b / NS;
             if constexpr (NS > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) w[i][r - 1] = tw[k * r * twstep];
+                for (int r = 1; r < R; ++r)
+                    w[i][r - 1] = OCT ? tw_octant<LS>(tab, k * r * twstep) : tw[k * r * twstep];
             }
             base[i] = q * span + k;
         }
@@ -211,14 +255,16 @@ __device__ __forceinline__ void stockham_fixed(double2 *__restrict__ lds, const 
     __syncthreads();
 }
 
-// Radix-8 passes, then one radix-4 or radix-2 pass for what is left.
-template <int T, int LS, int NS>
-__device__ __forceinline__ void fixed_passes(double2 *__restrict__ lds, const double2 *__restrict__ tw) {
+// Radix-8 passes, then one radix-4 or radix-2 pass for what is left;
+// twiddles from the LDS octant tab when OCT.
+template <int T, int LS, int NS, bool OCT>
+__device__ __forceinline__ void fixed_passes(double2 *__restrict__ lds, const double2 *__restrict__ tw,
+                                             const double2 *__restrict__ tab) {
     if constexpr (NS < LS) {
         constexpr int rest = LS / NS;
         constexpr int R = rest % 8 == 0 ? 8 : (rest % 4 == 0 ? 4 : 2);
-        stockham_fixed<R, T, LS, NS>(lds, tw);
-        fixed_passes<T, LS, NS * R>(lds, tw);
+        stockham_fixed<R, T, LS, NS, OCT>(lds, tw, tab);
+        fixed_passes<T, LS, NS * R, OCT>(lds, tw, tab);
     }
 }
 
@@ -226,13 +272,20 @@ __device__ __forceinline__ void fixed_passes(double2 *__restrict__ lds, const do
 // the power-of-two lengths 2T, 4T and 8T take compile-time passes (radix 8
 // first, whatever radix order the schedule names: the results differ from
 // the schedule's by rounding only), every other length the run-time
-// schedule.
+// schedule.  tab: the LDS octant of tw, stored (octant_store) before a
+// barrier that precedes this call, or null for global twiddle reads.
 template <int T, int EPT>
-__device__ void fft_lds_one(double2 *__restrict__ lds, int L, const FftSched &sch, const double2 *__restrict__ tw) {
+__device__ __forceinline__ void fft_lds_one(double2 *__restrict__ lds, int L, const FftSched &sch, const double2 *__restrict__ tw,
+                            const double2 *__restrict__ tab = nullptr) {
     static_assert(EPT == 8, "compile-time lengths assume 8 values per thread");
-    if (L == 8 * T) fixed_passes<T, 8 * T, 1>(lds, tw);
-    else if (L == 4 * T) fixed_passes<T, 4 * T, 1>(lds, tw);
-    else if (L == 2 * T) fixed_passes<T, 2 * T, 1>(lds, tw);
+    if (tab) {
+        if (L == 8 * T) return fixed_passes<T, 8 * T, 1, true>(lds, tw, tab);
+        if (L == 4 * T) return fixed_passes<T, 4 * T, 1, true>(lds, tw, tab);
+        if (L == 2 * T && T >= 4) return fixed_passes<T, 2 * T, 1, true>(lds, tw, tab);
+    }
+    if (L == 8 * T) fixed_passes<T, 8 * T, 1, false>(lds, tw, tab);
+    else if (L == 4 * T) fixed_passes<T, 4 * T, 1, false>(lds, tw, tab);
+    else if (L == 2 * T) fixed_passes<T, 2 * T, 1, false>(lds, tw, tab);
     else fft_passes<T, EPT, true>(lds, L, 1, sch, tw, 1);
 }
 
@@ -302,8 +355,11 @@ __device__ __forceinline__ double dst_post(int64_t n, const double2 *z, int64_t 
 // per thread and step: with H even, n = 4j .. 4j+3 read only z[j] and
 // z[H/2 - 1 - j] (q = 2j, 2j+1 and H-1-2j, H-2-2j), so a step is two LDS
 // reads, eight multiplications and, where c + 4j is 16-byte aligned, two
-// 16-byte stores.  The values are dst_post's bit for bit.  N <= H.
-template <int T>
+// 16-byte stores.  The values are dst_post's bit for bit.  N <= H.  NT:
+// non-temporal stores, for coefficients that nothing in the library reads
+// back (they leave the caches to the loads around them).
+typedef double lc_f64x2 __attribute__((ext_vector_type(2)));
+template <int T, bool NT = false>
 __device__ __forceinline__ void dst_post_block(double *__restrict__ c, int N, const double2 *__restrict__ z, int H) {
     const double r = 1.0 / (double)(2 * H);
     const bool vec = ((uintptr_t)c & 15) == 0;
@@ -315,8 +371,20 @@ __device__ __forceinline__ void dst_post_block(double *__restrict__ c, int N, co
         const double c0 = f * a.x * r, c1 = -(f + 2.0) * b.y * r;
         const double c2 = (f + 4.0) * a.y * r, c3 = -(f + 6.0) * b.x * r;
         if (vec) {
-            reinterpret_cast<double2 *>(c)[2 * j] = make_double2(c0, c1);
-            reinterpret_cast<double2 *>(c)[2 * j + 1] = make_double2(c2, c3);
+            const lc_f64x2 u0 = {c0, c1}, u1 = {c2, c3};
+            lc_f64x2 *p = reinterpret_cast<lc_f64x2 *>(c) + 2 * j;
+            if constexpr (NT) {
+                __builtin_nontemporal_store(u0, p);
+                __builtin_nontemporal_store(u1, p + 1);
+            } else {
+                p[0] = u0;
+                p[1] = u1;
+            }
+        } else if constexpr (NT) {
+            __builtin_nontemporal_store(c0, c + 4 * j);
+            __builtin_nontemporal_store(c1, c + 4 * j + 1);
+            __builtin_nontemporal_store(c2, c + 4 * j + 2);
+            __builtin_nontemporal_store(c3, c + 4 * j + 3);
         } else {
             c[4 * j] = c0;
             c[4 * j + 1] = c1;

@@ -299,20 +299,22 @@ __global__ __launch_bounds__(T) void k_bdst_lds(const double *__restrict__ phi_a
     const BatchFn &fn = fns[list[blockIdx.x]];
     const int64_t H = fn.H;
     const int L = (int)fn.L;
-    const FftSched sch = fn.sched;
+    const FftSched &sch = fn.sched;  // uniform reads of the table, not a private copy
     struct Phi {
         const double *p;
         __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
     } ph{phi_arena + fn.phi_off};
+    const OctantRegs oc = octant_load<T>(fn.tw_fft, L);
     dst_pack_lds<T, 8>(lds, ph, H, L, fn.tw_pre, fn.tw_pack);
+    octant_store<T>(lds + L, oc, L);
     __syncthreads();
-    fft_lds_one<T, 8>(lds, L, sch, fn.tw_fft);
+    fft_lds_one<T, 8>(lds, L, sch, fn.tw_fft, lds + L);
     double *c = c_arena + fn.c_off;
-    dst_post_block<T>(c, (int)fn.N, lds, (int)H);
+    dst_post_block<T, true>(c, (int)fn.N, lds, (int)H);
 }
 
 hipError_t prepare_bdst(int threads, int Lmax) {
-    const size_t lds = (size_t)Lmax * sizeof(double2);
+    const size_t lds = fft_lds_bytes(Lmax);
     if (lds <= 65536) return hipSuccess;
     if (threads == 512)
         return hipFuncSetAttribute((const void *)k_bdst_lds<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -327,7 +329,7 @@ hipError_t launch_bdst(int threads, int Lmax, const double *phi_arena, const Bat
                        int nlist, double *c_arena, hipStream_t s) {
     if (nlist <= 0) return hipSuccess;
     if (Lmax > 8 * threads) return hipErrorInvalidValue;
-    const size_t lds = (size_t)Lmax * sizeof(double2);
+    const size_t lds = fft_lds_bytes(Lmax);
     switch (threads) {
         case 64:
             hipLaunchKernelGGL(k_bdst_lds<64>, dim3(nlist), dim3(64), lds, s, phi_arena, fns, list, c_arena);

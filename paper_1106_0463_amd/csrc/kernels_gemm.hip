@@ -718,9 +718,11 @@ __global__ __launch_bounds__(T) void k_gdst_lds(const PhiT *__restrict__ Out, in
             return v;
         }
     } ph{row, rowexp, ce};
+    const OctantRegs oc = octant_load<T>(tw_fft, L);
     dst_pack_lds<T, 8>(lds, ph, H, L, tw_pre, tw_pack);
+    octant_store<T>(lds + L, oc, L);
     __syncthreads();
-    fft_lds_one<T, 8>(lds, L, sch, tw_fft);
+    fft_lds_one<T, 8>(lds, L, sch, tw_fft, lds + L);
     dst_post_block<T>(C + (int64_t)b * N, (int)N, lds, (int)H);
 }
 
@@ -768,6 +770,7 @@ __global__ __launch_bounds__(T) void k_gdst_z(const PhiT *__restrict__ Out, int 
     const int b = blockIdx.x;
     const P2 *row = reinterpret_cast<const P2 *>(Out + (int64_t)b * ldo);
     const int ce = colexp ? max(colexp[b], -1000) : 0;
+    const OctantRegs oc = octant_load<T>(tw_fft, L);
     P2 v[8];
     int2 ex[8];
 #pragma unroll
@@ -784,15 +787,16 @@ __global__ __launch_bounds__(T) void k_gdst_z(const PhiT *__restrict__ Out, int 
             else lds[k] = make_double2((double)v[i].x, (double)v[i].y);
         }
     }
+    octant_store<T>(lds + L, oc, L);
     __syncthreads();
-    fft_lds_one<T, 8>(lds, L, sch, tw_fft);
-    dst_post_block<T>(C + (int64_t)b * N, (int)N, lds, (int)H);
+    fft_lds_one<T, 8>(lds, L, sch, tw_fft, lds + L);
+    dst_post_block<T, true>(C + (int64_t)b * N, (int)N, lds, (int)H);
 }
 
 hipError_t launch_gdst_z(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,
                          int64_t H, int64_t L, int64_t N, const double2 *tw_fft, const FftSched &sch, double *C,
                          hipStream_t s) {
-    const size_t lds = (size_t)L * sizeof(double2);
+    const size_t lds = fft_lds_bytes(L);
     // one radix-8 butterfly per thread and pass for power-of-two lengths
     // (compile-time passes); otherwise the length classes of launch_gdst
     int T = L <= 512 ? 64 : (L <= 2048 ? 256 : 1024);
@@ -831,7 +835,7 @@ hipError_t launch_gdst_z(int phi_is_fp32, const void *Out, int ldo, const int *r
 hipError_t launch_gdst(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,
                        int64_t H, int64_t L, int64_t N, const double2 *tw_pre, const double2 *tw_pack,
                        const double2 *tw_fft, const FftSched &sch, double *C, hipStream_t s) {
-    const size_t lds = (size_t)L * sizeof(double2);
+    const size_t lds = fft_lds_bytes(L);
     int T = L <= 512 ? 64 : (L <= 2048 ? 256 : 1024);
     if (L > 8 * T) return hipErrorInvalidValue;
 #define LC_GD1(TV, PT, SCV)                                                                            \

@@ -388,10 +388,12 @@ __global__ __launch_bounds__(T) void k_dst_lds(const double *__restrict__ phi, i
                                                double *__restrict__ c) {
     extern __shared__ double2 lds[];
     GlobalPhi ph{phi};
+    const OctantRegs oc = octant_load<T>(tw_fft, L);
     dst_pack_lds<T, 8>(lds, ph, H, L, tw_pre, tw_pack);
+    octant_store<T>(lds + L, oc, L);
     __syncthreads();
-    fft_lds_one<T, 8>(lds, L, sch, tw_fft);
-    dst_post_block<T>(c, (int)N, lds, (int)H);
+    fft_lds_one<T, 8>(lds, L, sch, tw_fft, lds + L);
+    dst_post_block<T, true>(c, (int)N, lds, (int)H);
 }
 
 // Four-step FFT of length L = L1 * L2 (k = L2 k1 + k2, p = p1 + L1 p2):
@@ -473,7 +475,7 @@ hipError_t launch_dst(const DstCfg &cfg, const double *phi, int64_t H, int64_t L
                       double2 *zB, double *c, hipStream_t s) {
     hipError_t e;
     if (L <= kLdsFftMax) {
-        const size_t lds = (size_t)L * sizeof(double2);
+        const size_t lds = fft_lds_bytes(L);
         if (L > 8 * cfg.threads) return hipErrorInvalidValue;
         switch (cfg.threads) {
             case 64:
