@@ -760,12 +760,14 @@ hipError_t launch_apack(const double *A, int P, int64_t H, int64_t L, const doub
 // function b's Z_k is (Out[b][2k], Out[b][2k+1]) times 2^(rowexp[2k or
 // 2k+1] + colexp[b]) when SC; every thread's loads (up to 8 values) are
 // issued before the first is stored to LDS.
-template <int T, typename PhiT, bool SC>
+// FIX: L == 8T, the kernel holds only that length's compile-time passes.
+template <int T, typename PhiT, bool SC, bool FIX>
 __global__ __launch_bounds__(T) void k_gdst_z(const PhiT *__restrict__ Out, int ldo, const int *__restrict__ rowexp,
-                                              const int *__restrict__ colexp, int64_t H, int L, int64_t N,
+                                              const int *__restrict__ colexp, int64_t H, int Lr, int64_t N,
                                               const double2 *__restrict__ tw_fft, FftSched sch,
                                               double *__restrict__ C) {
     extern __shared__ double2 lds[];
+    const int L = FIX ? 8 * T : Lr;
     using P2 = typename std::conditional<std::is_same<PhiT, float>::value, float2, double2>::type;
     const int b = blockIdx.x;
     const P2 *row = reinterpret_cast<const P2 *>(Out + (int64_t)b * ldo);
@@ -789,7 +791,8 @@ __global__ __launch_bounds__(T) void k_gdst_z(const PhiT *__restrict__ Out, int 
     }
     octant_store<T>(lds + L, oc, L);
     __syncthreads();
-    fft_lds_one<T, 8>(lds, L, sch, tw_fft, lds + L);
+    if constexpr (FIX) fixed_passes<T, 8 * T, 1, true>(lds, tw_fft, lds + L);
+    else fft_lds_one<T, 8>(lds, L, sch, tw_fft, lds + L);
     dst_post_block<T, true>(C + (int64_t)b * N, (int)N, lds, (int)H);
 }
 
@@ -802,18 +805,20 @@ hipError_t launch_gdst_z(int phi_is_fp32, const void *Out, int ldo, const int *r
     int T = L <= 512 ? 64 : (L <= 2048 ? 256 : 1024);
     if ((L & (L - 1)) == 0 && L >= 512) T = (int)(L / 8);
     if (L > 8 * T || (ldo & 1)) return hipErrorInvalidValue;
-#define LC_GZ1(TV, PT, SCV)                                                                            \
-    if (T == TV && (rowexp != nullptr) == SCV) {                                                       \
+    const bool fix = L == 8 * T;
+#define LC_GZ1(TV, PT, SCV, FV)                                                                        \
+    if (T == TV && (rowexp != nullptr) == SCV && fix == FV) {                                          \
         if (lds > 65536) {                                                                             \
-            hipError_t e = hipFuncSetAttribute((const void *)k_gdst_z<TV, PT, SCV>,                    \
+            hipError_t e = hipFuncSetAttribute((const void *)k_gdst_z<TV, PT, SCV, FV>,                \
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
             if (e != hipSuccess) return e;                                                             \
         }                                                                                              \
-        hipLaunchKernelGGL((k_gdst_z<TV, PT, SCV>), dim3(B), dim3(TV), lds, s, (const PT *)Out, ldo, rowexp, \
-                           colexp, H, (int)L, N, tw_fft, sch, C);                                      \
+        hipLaunchKernelGGL((k_gdst_z<TV, PT, SCV, FV>), dim3(B), dim3(TV), lds, s, (const PT *)Out, ldo, \
+                           rowexp, colexp, H, (int)L, N, tw_fft, sch, C);                              \
         return hipGetLastError();                                                                      \
     }
-#define LC_GZ(TV, PT) LC_GZ1(TV, PT, true) LC_GZ1(TV, PT, false)
+#define LC_GZ(TV, PT) LC_GZ1(TV, PT, true, true) LC_GZ1(TV, PT, false, true) \
+    LC_GZ1(TV, PT, true, false) LC_GZ1(TV, PT, false, false)
     if (phi_is_fp32) {
         LC_GZ(64, float)
         LC_GZ(128, float)
