@@ -366,3 +366,17 @@ def test_fp16_chunk_exponents(lc, mode, bound, direct):
         banner(f"    B={nb}: worst max|da|/max|f| {worst_f:.2e}, series max|da|/max|a| {worst_a:.2e}")
     g16.destroy()
     g64.destroy()
+
+
+@pytest.mark.parametrize("mode,bound", [("fp64", 1e-12), _mode_param("fp16x3", 1e-7)])
+def test_abel_dst_lengths(lc, mode, bound):
+    # the batched DST of the Abel form at every power-of-two FFT length
+    # L = M/4 = 512 ... 8192, i.e. every workgroup size T = L/8 = 64 ... 1024
+    # of its compile-time-pass instances, with FP64 (fp64 mode) and FP32
+    # (split mode) products; exact coefficients of degree-200 series
+    banner(f"[gpu] gemm {mode}: DST lengths 512..8192")
+    for M in (2048, 4096, 8192, 16384, 32768):
+        C, coef = _run(lc, mode, 256, M, 256, 8, 200, seed=M)
+        E_c, E_a = _errors(C, coef, 256)
+        banner(f"    M={M}: E_c {E_c:.2e} E_a {E_a:.2e}")
+        assert (E_c if mode == "fp64" else E_a) <= bound, M
