@@ -139,7 +139,8 @@ typedef struct {
 
 /* Size rule for the y-grid (host only, no device work).  The FFT of eq. (2.4)
  * is computed as a complex FFT of length H/2; this library supports lengths
- * 2^a 3^b.  M_eff is the smallest M' >= max(M, 4) with M' = 4 * 2^a 3^b.
+ * 2^a 3^b 5^c.  M_eff is the smallest M' >= max(M, 4) with M' = 4 * 2^a 3^b 5^c
+ * and c <= 1 (at most one radix-5 pass, whose rounding exceeds the others').
  * Using M_eff >= M only refines the trapezoid grid of eq. (2.4).
  * Errors: LC_ERR_INVALID if M < 2 or M_eff is null or the size overflows. */
 lc_status lc_grid_size(int64_t M, int64_t *M_eff);

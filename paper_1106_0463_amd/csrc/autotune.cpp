@@ -170,12 +170,14 @@ std::vector<FftSched> sched_candidates(int L) {
     FftSched r = d;
     for (int i = 0; i < d.npass; ++i) r.radix[i] = d.radix[d.npass - 1 - i];
     out.push_back(r);
-    int n = L, c2 = 0, c3 = 0;
+    int n = L, c2 = 0, c3 = 0, c5 = 0;
+    while (n % 5 == 0) { n /= 5; ++c5; }
     while (n % 3 == 0) { n /= 3; ++c3; }
     while (n % 2 == 0) { n /= 2; ++c2; }
     std::vector<int> v;
     for (int i = 0; i + 1 < c2; i += 2) v.push_back(4);
     if (c2 % 2) v.push_back(2);
+    for (int i = 0; i < c5; ++i) v.push_back(5);
     for (int i = 0; i < c3; ++i) v.push_back(3);
     v.push_back(0);
     out.push_back(make_sched(L, v.data()));

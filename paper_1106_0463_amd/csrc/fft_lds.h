@@ -54,6 +54,30 @@ template <> struct Dft<4> {
     }
 };
 
+// X_k = sum_j x_j w^{jk}, w = e^{+2 pi i/5}: with s1 = x1 + x4, d1 = x1 - x4,
+// s2 = x2 + x3, d2 = x2 - x3, X_1,4 = x0 + c1 s1 + c2 s2 +- i (n1 d1 + n2 d2)
+// and X_2,3 = x0 + c2 s1 + c1 s2 +- i (n2 d1 - n1 d2), with c1, c2 = cos(2 pi/5),
+// cos(4 pi/5) = (sqrt 5 - 1)/4, -(sqrt 5 + 1)/4 and n1, n2 = sin(2 pi/5),
+// sin(4 pi/5) = sqrt(10 + 2 sqrt 5)/4, sqrt(10 - 2 sqrt 5)/4.
+template <> struct Dft<5> {
+    static __device__ __forceinline__ void run(double2 *v) {
+        const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+        const double n1 = 0.95105651629515357212, n2 = 0.58778525229247312917;
+        const double2 s1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+        const double2 s2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+        const double2 a1 = make_double2(v[0].x + c1 * s1.x + c2 * s2.x, v[0].y + c1 * s1.y + c2 * s2.y);
+        const double2 a2 = make_double2(v[0].x + c2 * s1.x + c1 * s2.x, v[0].y + c2 * s1.y + c1 * s2.y);
+        // b1 = i (n1 d1 + n2 d2), b2 = i (n2 d1 - n1 d2)
+        const double2 b1 = make_double2(-(n1 * d1.y + n2 * d2.y), n1 * d1.x + n2 * d2.x);
+        const double2 b2 = make_double2(-(n2 * d1.y - n1 * d2.y), n2 * d1.x - n1 * d2.x);
+        v[0] = cadd(v[0], cadd(s1, s2));
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
+    }
+};
+
 template <> struct Dft<8> {
     static __device__ __forceinline__ void run(double2 *v) {
         const double c = 0.70710678118654752440;  // sqrt(1/2)
@@ -151,6 +175,7 @@ __device__ __forceinline__ void fft_passes(double2 *__restrict__ lds, int Lsub, 
         switch (R) {
             case 8: stockham_pass<8, T, EPT, ONE>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
             case 4: stockham_pass<4, T, EPT, ONE>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
+            case 5: stockham_pass<5, T, EPT, ONE>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
             case 3: stockham_pass<3, T, EPT, ONE>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
             default: stockham_pass<2, T, EPT, ONE>(lds, Lsub, nsub, Ns, tw, tw_stride); break;
         }

@@ -255,7 +255,7 @@ hipError_t device_alloc(void **p, size_t bytes);  // hipMalloc behind the LC_ALL
 bool log_on();                                   // LC_LOG=1
 void log_line(const char *fmt, ...);             // one "[lc] ..." line on stderr when LC_LOG=1
 std::string sched_str(const FftSched &s);        // "8x8x4" 
-int64_t smooth_len_at_least(int64_t L);           // smallest 2^a 3^b >= L
+int64_t smooth_len_at_least(int64_t L);           // smallest 2^a 3^b 5^c >= L, c <= 1
 FftSched make_sched(int L, const int *order = nullptr);
 void gauss_half_rule(int Q, std::vector<double> &t, std::vector<double> &w,
                      std::vector<double2> &omt2);

@@ -3,18 +3,17 @@ import numpy as np
 
 
 def smooth_at_least(L: int) -> int:
-    """Smallest 2^a 3^b >= L (the documented grid-size rule of lc.h)."""
-    best = None
-    p3 = 1
+    """Smallest 2^a 3^b 5^c >= L with c <= 1 (the documented grid-size rule of
+    lc.h), by counting up from L."""
+    n = max(int(L), 1)
     while True:
-        v = p3
-        while v < L:
-            v *= 2
-        best = v if best is None else min(best, v)
-        if p3 > L:
-            break
-        p3 *= 3
-    return best
+        m = n
+        for p in (2, 3):
+            while m % p == 0:
+                m //= p
+        if m in (1, 5):
+            return n
+        n += 1
 
 
 def expected_grid(M: int) -> int:

@@ -41,20 +41,18 @@ def test_status_strings(lib):
 
 
 def _smooth_at_least(L):
-    best = None
-    p3 = 1
+    n = max(L, 1)
     while True:
-        v = p3
-        while v < L:
-            v *= 2
-        best = v if best is None else min(best, v)
-        if p3 > L:
-            break
-        p3 *= 3
-    return best
+        m = n
+        for p in (2, 3):
+            while m % p == 0:
+                m //= p
+        if m in (1, 5):
+            return n
+        n += 1
 
 
-@pytest.mark.parametrize("M", [2, 4, 6, 256, 300, 1200, 4 * 257, 4 * 8191, 262144, 4 * 3001, 10**6])
+@pytest.mark.parametrize("M", [2, 4, 6, 256, 300, 1200, 4 * 257, 4 * 8191, 262144, 4 * 3001, 10**6, 4 * 15625, 4 * 3126])
 def test_grid_size_rule(M):
     import paper_1106_0463_amd as lc
     Me = lc.grid_size(M)
@@ -62,11 +60,10 @@ def test_grid_size_rule(M):
     assert Me >= M and Me % 4 == 0
     assert L == _smooth_at_least(max(1, -(-max(M, 4) // 4)))
     n = L
-    while n % 2 == 0:
-        n //= 2
-    while n % 3 == 0:
-        n //= 3
-    assert n == 1
+    for p in (2, 3):
+        while n % p == 0:
+            n //= p
+    assert n in (1, 5)
 
 
 @pytest.mark.parametrize("args", [(0, 256, 32), (200, 256, 32), (8, 255, 32), (8, 256, 0),
