@@ -145,12 +145,14 @@ def test_batch_shapes(lc, tmp_path, monkeypatch, prec, Q):
     bp.destroy()
 
 
-@pytest.mark.parametrize("L", [64, 128, 256, 512, 1024, 2048, 4096, 8192])
+@pytest.mark.parametrize("L", [64, 128, 256, 512, 1024, 2048, 4096, 8192, 80, 240, 640, 1920, 5120, 7680])
 def test_single_dst_threads(lc, tmp_path, monkeypatch, L):
     """Every DST workgroup size T with L <= 8 T, forced through the cache, on
-    an FFT of power-of-two length L = H/2: the lengths 2T, 4T and 8T take the
-    compile-time Stockham passes, the others the run-time schedule.  All must
-    give the default shape's coefficients up to rounding order."""
+    an FFT of length L = H/2: power-of-two lengths 2T, 4T and 8T take the
+    compile-time Stockham passes, the others (and the lengths 5 2^a and
+    15 2^a, with their radix-5 pass) the run-time schedule.  All must give
+    the default shape's coefficients up to rounding order, and the method
+    oracle's."""
     import torch
     cache = str(tmp_path / "tune.txt")
     monkeypatch.setenv("LC_AUTOTUNE_CACHE", cache)
