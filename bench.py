@@ -51,7 +51,7 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from the 4 GiB copy calibration),
 # with the kernel they were taken on
 TRAFFIC = {"single_large_band": (4.9517e9, "k_aflat<double>"),
-           "batch_fp64": (7.7919e9, "k_bquad_fit<double, 2, 8, 3, 2>")}
+           "batch_fp64": (7.6855e9, "k_bquad_fit<double, 2, 8, 3, 2>")}
 METRIC = "Legendre coeffs/sec at 1 GPU (FP64 ≤1e-12 vs split-BF16 ≤1e-7 rel.)"
 Q_RESOLVING = 8384
 FP64_CLASS = 1e-12   # E_c = max|dc| / max|c|
