@@ -109,7 +109,7 @@ hipError_t reserve(GemmState *g, int B) {
         chk(galloc(g, &x, (size_t)g->npc * g->Bpad * g->Kp, true));
         g->X = x;
         chk(galloc(g, &g->colexp, (size_t)B, true));
-        if (g->scaled) {
+        if (g->scaled && !g->direct) {  // the Abel form's chunk exponents
             const int nchp = mgemm_scale_chunks(g->Kp);
             chk(galloc(g, &g->cexp, (size_t)(g->Kp / 16 + kExpChunk16 - 1) / kExpChunk16 * g->Bpad, true));
             chk(galloc(g, &g->cscale, (size_t)nchp * g->Bpad, true));
@@ -349,13 +349,15 @@ lc_status lc_execute_gemm(lc_plan_t p, const double *F_dev, int32_t B, double *C
         return LC_OK;
     }
     const int64_t xps = g->Bpad * g->Kp;
-    e = launch_split_cols(g->h16, F_dev, g->P, B, g->Kp, g->npc, g->X, xps, g->Bpad, g->cexp, g->colexp, g->cscale,
-                          stream);
+    // the Abel form's FP16 split takes chunk exponents (cscale), the direct
+    // form's one exponent per function (cscale null)
+    e = launch_split_cols(g->h16, F_dev, g->P, B, g->Kp, g->npc, g->X, xps, g->Bpad, g->cexp, g->colexp,
+                          g->direct ? nullptr : g->cscale, stream);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: split: ") + hipGetErrorString(e));
     if ((e = timing_begin(p, stream, &slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
     if (g->direct)
         e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->N, g->Kp, nullptr, (int)g->N,
-                         C_dev, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, g->cscale, g->ks,
+                         C_dev, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, nullptr, g->ks,
                          g->ns, g->kch, stream);
     else
         e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->H, g->Kp, g->Out32,

@@ -254,19 +254,50 @@ hipError_t launch_transpose_a(const double *A, int H, int P, double *AT, hipStre
     return hipGetLastError();
 }
 
+// Direct form (FP16): one exponent per function, colexp[b] = ilogb(max_p
+// |F[p][b]|) + 1, before the split: a fill, then blocks of 256 functions x 64
+// rows fold their partial maxima in with an integer atomic max (the exponent
+// is monotone in the magnitude).  Its product folds FP64 totals every few
+// K-steps, where a factor per chunk would double the fold's work.
+__global__ __launch_bounds__(256) void k_colexp_init(int B, int *__restrict__ colexp) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b < B) colexp[b] = -2000;
+}
+
+__global__ __launch_bounds__(256) void k_colmax(const double *__restrict__ F, int P, int B,
+                                                int *__restrict__ colexp) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int p0 = blockIdx.y * 64;
+    if (b >= B) return;
+    const int p1 = p0 + 64 < P ? p0 + 64 : P;
+    double m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int p = p0;
+    for (; p + 8 <= p1; p += 8) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) m[e] = fmax(m[e], fabs(__builtin_nontemporal_load(F + (int64_t)(p + e) * B + b)));
+    }
+    for (; p < p1; ++p) m[0] = fmax(m[0], fabs(F[(int64_t)p * B + b]));
+    double mm = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) mm = fmax(mm, m[e]);
+    if (mm > 0.0) atomicMax(colexp + b, ilogb(mm) + 1);
+}
+
 // F [P][B] -> pieces X_i in fragment order over Bpad rows (function b is
 // row b); one thread per (b, 8 consecutive p).  Fragments are numbered with
 // the row block fastest, so that the waves resident together read long
 // contiguous stretches of the same rows of F.
 //
-// FP16 (SC): block (rb, kg) covers exactly the 256 samples p of exponent
+// FP16 (SCM 1): block (rb, kg) covers exactly the 256 samples p of exponent
 // chunk kg for its 32 functions, so it scales them by 2^-e with its own
 // chunk exponent e = ilogb(max |F|) + 1 (at least -1000) and stores e in
 // cexp[kg][b]: one read of F instead of a maximum pass over all of it
 // before the split.  The product rescales each chunk's FP32 sums by
 // 2^(e - E_b) at the fold of its accumulators, E_b the function's largest
 // chunk exponent (k_colscale).
-template <typename H16, int NPC, bool SC>
+// SCM 0: no scale (BF16); 1: chunk exponents (above); 2: the function's
+// exponent colexp[b] from k_colmax (direct form).
+template <typename H16, int NPC, int SCM>
 __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F, int P, int B, int K16, int RB,
                                                     H16 *__restrict__ X, int64_t piece_stride,
                                                     int *__restrict__ cexp, int64_t Bpad) {
@@ -301,7 +332,14 @@ __global__ __launch_bounds__(256) void k_split_cols(const double *__restrict__ F
             m = fmax(m, fabs(v[j][e]));
         }
     }
-    if constexpr (SC) {
+    if constexpr (SCM == 2) {
+        const double sc = b < B ? ldexp(1.0, -max(cexp[b], -1000)) : 1.0;
+#pragma unroll
+        for (int j = 0; j < kSplitKW; ++j)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[j][e] *= sc;
+    }
+    if constexpr (SCM == 1) {
         __shared__ double red[4][32];
         m = fmax(m, __shfl_xor(m, 32, 64));  // lanes l and l + 32 hold the same function
         if (lane < 32) red[w][lane] = m;
@@ -390,20 +428,35 @@ hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int
     const int RB = (int)(Bt / 32);
     const int nch = (K16 + kExpChunk16 - 1) / kExpChunk16;
     const dim3 grid((unsigned)((int64_t)RB * nch));
-    const bool sc = h16 == kF16;
-    if (sc && (!cexp || !colexp || !cscale)) return hipErrorInvalidValue;
+    // FP16: chunk exponents when cscale is given (Abel form), else one
+    // exponent per function (direct form)
+    const int mode = h16 != kF16 ? 0 : (cscale ? 1 : 2);
+    if (mode && !colexp) return hipErrorInvalidValue;
+    if (mode == 1 && !cexp) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    if (mode == 2) {
+        hipLaunchKernelGGL(k_colexp_init, dim3((B + 255) / 256), dim3(256), 0, s, B, colexp);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_colmax, dim3((B + 255) / 256, (P + 63) / 64), dim3(256), 0, s, F, P, B, colexp);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    int *ce = mode == 1 ? cexp : colexp;
 #define LC_SC(T, NP, SCV)                                                                                \
     if (npc == NP) {                                                                                     \
         hipLaunchKernelGGL((k_split_cols<T, NP, SCV>), grid, dim3(256), 0, s, F, P, B, K16, RB, (T *)X, \
-                           piece_stride, cexp, Bpad);                                                    \
+                           piece_stride, ce, Bpad);                                                      \
         e = hipGetLastError();                                                                           \
     } else
-    hipError_t e = hipErrorInvalidValue;
-    if (!sc) {
-        LC_SC(__bf16, 1, false) LC_SC(__bf16, 2, false) LC_SC(__bf16, 3, false) {}
+    e = hipErrorInvalidValue;
+    if (mode == 0) {
+        LC_SC(__bf16, 1, 0) LC_SC(__bf16, 2, 0) LC_SC(__bf16, 3, 0) {}
         return e;
     }
-    LC_SC(_Float16, 1, true) LC_SC(_Float16, 2, true) LC_SC(_Float16, 3, true) {}
+    if (mode == 2) {
+        LC_SC(_Float16, 1, 2) LC_SC(_Float16, 2, 2) LC_SC(_Float16, 3, 2) {}
+        return e;
+    }
+    LC_SC(_Float16, 1, 1) LC_SC(_Float16, 2, 1) LC_SC(_Float16, 3, 1) {}
 #undef LC_SC
     if (e != hipSuccess) return e;
     const int nchp = mgemm_scale_chunks(Kp);
@@ -473,7 +526,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     float *__restrict__ Out, int ldo, double *__restrict__ C64, const int *__restrict__ rowexp,
     const int *__restrict__ colexp, const unsigned char *__restrict__ cscale, int nchp) {
     using PR = Prods<MODE>;
-    constexpr bool CS = std::is_same<H16, _Float16>::value;  // FP16: per-chunk column factors
+    // FP16 Abel form: per-chunk column factors (the direct form's FP16 pieces
+    // carry one exponent per function, applied by the epilogue)
+    constexpr bool CS = std::is_same<H16, _Float16>::value && !D64;
     constexpr int NX = PR::nx, NY = PR::ny;
     constexpr int KF = KS / 16;                        // fragments along k per stage
     constexpr int FX = NX * 4 * KF, FY = NY * 4 * KF;  // fragments per stage (4 row blocks of 32)
@@ -654,15 +709,15 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
                         int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
                         const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s) {
     if (Kp % 32) return hipErrorInvalidValue;
-    if (h16 == kF16 && !cscale) return hipErrorInvalidValue;
+    const bool d64 = C64 != nullptr;
+    if (h16 == kF16 && !d64 && !cscale) return hipErrorInvalidValue;
     const int nchp = mgemm_scale_chunks(Kp);
     const int K16 = Kp / 16;
-    const bool d64 = C64 != nullptr;
     int KS = ks, NS = ns;
     mgemm_defaults(mode, h16, d64, KS, NS, kch);
     const int grid = ((Bn + kGemmBM - 1) / kGemmBM) * ((Hn + 127) / 128);
     const int npx = mode == 1 ? 1 : (mode == 3 ? 2 : 3);
-    const size_t lds = (size_t)NS * 2 * npx * 4 * (KS / 16) * 1024 + (h16 == kF16 ? (size_t)nchp * 128 : 0);
+    const size_t lds = (size_t)NS * 2 * npx * 4 * (KS / 16) * 1024 + (h16 == kF16 && !d64 ? (size_t)nchp * 128 : 0);
 #define LC_MG1(T, MV, KSV, NSV, DV, KV)                                                                         \
     if (mode == MV && KS == KSV && NS == NSV && d64 == DV && kch == KV) {                                       \
         if (lds > 65536) {                                                                                      \

@@ -38,15 +38,18 @@ hipError_t launch_split_rows(int h16, const double *S, int64_t roff, int64_t rs,
                              int Hpad, int npc, void *Y, int64_t piece_stride, int *rowexp, int scaled,
                              hipStream_t s);
 hipError_t launch_transpose_a(const double *A, int H, int P, double *AT, hipStream_t s);
-// F [P][B] -> X pieces over Bpad rows; FP16 also writes the chunk exponents
-// cexp [nch][Bpad], the function exponents colexp [B] and the chunk factors
-// cscale [Bpad/128][nchp][128] (all three required for FP16, unused for BF16)
+// F [P][B] -> X pieces over Bpad rows.  FP16 with cscale (Abel form): the
+// chunk exponents cexp [nch][Bpad], the function exponents colexp [B] and
+// the chunk factors cscale [Bpad/128][nchp][128]; FP16 without cscale
+// (direct form): one exponent per function in colexp (a maximum pass over F
+// first); BF16: no scale
 hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int npc, void *X,
                              int64_t piece_stride, int64_t Bpad, int *cexp, int *colexp, unsigned char *cscale,
                              hipStream_t s);
 // C64 == nullptr: FP32 sums into Out[Bn][ldo]; otherwise finished FP64
-// values into C64[Bn][ldo] scaled by 2^(rowexp[j] + colexp[b]); FP16 folds
-// each chunk's sums in with the factors cscale of the column split
+// values into C64[Bn][ldo] scaled by 2^(rowexp[j] + colexp[b]); FP16 with
+// FP32 output folds each chunk's sums in with the factors cscale of the
+// column split (required there; unused with C64)
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
                         int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
                         const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s);

@@ -320,10 +320,11 @@ SCALED_COPIES = ((5, 4, 600), (6, 4, -600), (7, 1, -400))
 @pytest.mark.parametrize("mode,bound", [_mode_param("fp16x3", 1e-7), _mode_param("fp16x1", 1e-3)])
 @pytest.mark.parametrize("direct", [False, True], ids=["abel", "direct"])
 def test_fp16_chunk_exponents(lc, mode, bound, direct):
-    # FP16 pieces carry one power-of-two exponent per function and chunk of
-    # 256 samples, and the product folds each chunk's FP32 sums back in with
-    # its factor.  On columns spanning hundreds of binary orders (across the
-    # grid and between functions):
+    # FP16 pieces carry a power-of-two exponent: per function and chunk of 256
+    # samples in the Abel form (the product folds each chunk's FP32 sums back
+    # in with its factor), per function in the direct form (applied by its
+    # FP64 epilogue).  On columns spanning hundreds of binary orders (across
+    # the grid and between functions):
     # * a column scaled by 2^k gives its copy's coefficients times 2^k bit
     #   for bit (every exponent shifts by k; nothing else changes);
     # * every function keeps max|da_n| <= bound max|f| against the FP64
