@@ -43,6 +43,7 @@ struct GemmState {
     int64_t Hpad = 0, Bpad = 0;  // operand rows padded to the MFMA block tile
     int h16 = kBF16, npc = 1, kmode = 1, scaled = 0;
     int ks = 0, ns = 0, kch = 0;  // MFMA product shape (0: per-mode defaults)
+    int wr = 2;                   // rows of waves per product block (2: 128 functions, 4: 256)
     int64_t N = 0, M = 0, M_eff = 0, H = 0, L = 0;
     double *xc = nullptr, *lam = nullptr, *A = nullptr;
     double *Ap = nullptr;  // Abel form: A with the DST pack applied to its rows ([H][P])
@@ -105,7 +106,8 @@ hipError_t reserve(GemmState *g, int B) {
     } else {
         // the split writes every padded row and k of the pieces it uses
         unsigned short *x = nullptr;
-        g->Bpad = ((int64_t)B + kGemmBM - 1) / kGemmBM * kGemmBM;
+        const int bm = 64 * g->wr;  // rows of the product's block tile
+        g->Bpad = ((int64_t)B + bm - 1) / bm * bm;
         chk(galloc(g, &x, (size_t)g->npc * g->Bpad * g->Kp, true));
         g->X = x;
         chk(galloc(g, &g->colexp, (size_t)B, true));
@@ -169,6 +171,8 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
     g->direct = direct;
     // tuning overrides, fixed for the plan's lifetime
     if (const char *kc = getenv("LC_MGEMM_KCH")) g->kch = atoi(kc);
+    int rows = 256;
+    if (const char *br = getenv("LC_MGEMM_BLOCK_ROWS")) rows = atoi(br);
     if (const char *st = getenv("LC_MGEMM_STAGES")) {
         if (sscanf(st, "%d,%d", &g->ks, &g->ns) != 2) g->ks = g->ns = -1;
     }
@@ -183,6 +187,10 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
         case LC_GEMM_FP16X1: g->h16 = kF16; g->npc = 1; g->kmode = 1; g->scaled = 1; break;
         default: g->npc = 0; break;
     }
+    // product block of 256 functions (8 waves) for the three-product modes
+    // at the default stage shape, 2-3% faster there than 128 (one ring stage
+    // feeds twice the products); 128 (4 waves) for the others
+    g->wr = rows == 256 && g->kmode == 3 && g->ks <= 0 && !g->kch ? 4 : 2;
     if (g->kmode && g->npc && !mgemm_shape_supported(g->kmode, g->ks, g->ns, g->kch, direct != 0)) {
         free_gemm(g);
         return fail_status(LC_ERR_INVALID, who + "LC_MGEMM_STAGES / LC_MGEMM_KCH name no built product kernel");
@@ -352,16 +360,16 @@ lc_status lc_execute_gemm(lc_plan_t p, const double *F_dev, int32_t B, double *C
     // the Abel form's FP16 split takes chunk exponents (cscale), the direct
     // form's one exponent per function (cscale null)
     e = launch_split_cols(g->h16, F_dev, g->P, B, g->Kp, g->npc, g->X, xps, g->Bpad, g->cexp, g->colexp,
-                          g->direct ? nullptr : g->cscale, stream);
+                          g->direct ? nullptr : g->cscale, stream, 64 * g->wr);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: split: ") + hipGetErrorString(e));
     if ((e = timing_begin(p, stream, &slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
     if (g->direct)
         e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->N, g->Kp, nullptr, (int)g->N,
                          C_dev, g->scaled ? g->rowexp : nullptr, g->scaled ? g->colexp : nullptr, nullptr, g->ks,
-                         g->ns, g->kch, stream);
+                         g->ns, g->kch, stream, g->wr);
     else
         e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->H, g->Kp, g->Out32,
-                         (int)g->H, nullptr, nullptr, nullptr, g->cscale, g->ks, g->ns, g->kch, stream);
+                         (int)g->H, nullptr, nullptr, nullptr, g->cscale, g->ks, g->ns, g->kch, stream, g->wr);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: mfma: ") + hipGetErrorString(e));
     if ((e = timing_end(p, stream, slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
     if (g->direct) return LC_OK;

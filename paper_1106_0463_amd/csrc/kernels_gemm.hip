@@ -422,9 +422,10 @@ hipError_t launch_split_rows(int h16, const double *S, int64_t roff, int64_t rs,
 
 hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int npc, void *X,
                              int64_t piece_stride, int64_t Bpad, int *cexp, int *colexp, unsigned char *cscale,
-                             hipStream_t s) {
+                             hipStream_t s, int bm) {
     const int K16 = Kp / 16;
-    const int64_t Bt = ((int64_t)B + kGemmBM - 1) / kGemmBM * kGemmBM;  // rows of the call's block tiles
+    if (bm <= 0 || bm % kGemmBM) return hipErrorInvalidValue;
+    const int64_t Bt = ((int64_t)B + bm - 1) / bm * bm;  // rows of the call's block tiles
     const int RB = (int)(Bt / 32);
     const int nch = (K16 + kExpChunk16 - 1) / kExpChunk16;
     const dim3 grid((unsigned)((int64_t)RB * nch));
@@ -466,8 +467,10 @@ hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int
 }
 
 // ------------------------------------------------------------ MFMA GEMM ---
-// Block tile 128 (b) x 128 (j), 4 waves in 2 x 2, each wave 64 x 64 = 2 x 2
-// MFMA 32x32x16 tiles.  K advances KS per stage through a ring of NS LDS
+// Block tile 64 WR (b) x 128 (j), 2 WR waves in WR x 2 (WR = 2: 128 x 128,
+// WR = 4: 256 x 128), each wave 64 x 64 = 2 x 2 MFMA 32x32x16 tiles; the
+// 256-row block has twice the products per stage copy at the same two waves
+// per SIMD.  K advances KS per stage through a ring of NS LDS
 // stages filled by direct global->LDS copies (16 bytes per lane, one 1 KiB
 // fragment per wave instruction): the copy of stage kt + NS - 1 is issued
 // while stage kt is multiplied, and each wave waits only for the copies of
@@ -520,8 +523,8 @@ __device__ __forceinline__ void lds_barrier() {
 // Epilogue: D64 = false writes the FP32 sums to Out[b][j]; D64 = true writes
 // FP64 C[b][j] = sum * 2^(rowexp[j] + colexp[b]) (exponent arrays may be
 // null), the finished coefficients of the direct Legendre-matrix form.
-template <typename H16, int MODE, int KS, int NS, bool D64, int KCH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mgemm(
+template <typename H16, int MODE, int KS, int NS, bool D64, int KCH, int WR = 2>
+__global__ __launch_bounds__(128 * WR) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mgemm(
     const H16 *__restrict__ X, int64_t xps, const H16 *__restrict__ Y, int64_t yps, int Bn, int Hn, int K16,
     float *__restrict__ Out, int ldo, double *__restrict__ C64, const int *__restrict__ rowexp,
     const int *__restrict__ colexp, const unsigned char *__restrict__ cscale, int nchp) {
@@ -530,18 +533,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // carry one exponent per function, applied by the epilogue)
     constexpr bool CS = std::is_same<H16, _Float16>::value && !D64;
     constexpr int NX = PR::nx, NY = PR::ny;
-    constexpr int KF = KS / 16;                        // fragments along k per stage
-    constexpr int FX = NX * 4 * KF, FY = NY * 4 * KF;  // fragments per stage (4 row blocks of 32)
+    constexpr int KF = KS / 16;                         // fragments along k per stage
+    constexpr int NW = 2 * WR, RX = 2 * WR;             // waves; row blocks of 32 of X per block
+    constexpr int FX = NX * RX * KF, FY = NY * 4 * KF;  // fragments per stage
     constexpr int FST = FX + FY;
-    static_assert(FST % 4 == 0, "stage fragments must split over 4 waves");
-    constexpr int DPW = FST / 4;  // copies per wave per stage
+    static_assert(FST % NW == 0, "stage fragments must split over the waves");
+    constexpr int DPW = FST / NW;  // copies per wave per stage
     static_assert(DPW * (NS - 2) < 64, "vmcnt range");
     extern __shared__ __attribute__((aligned(1024))) u32x4 ring[];  // [NS][FST][64]
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: the copies' LDS base
     const int wm = (wave >> 1) * 2, wn = (wave & 1) * 2;  // row blocks of 32 owned by the wave
     const int ntn = (Hn + 127) / 128;
-    const int rbx = (blockIdx.x / ntn) * 4, rby = (blockIdx.x % ntn) * 4;  // first row blocks of X and Y
+    const int rbx = (blockIdx.x / ntn) * RX, rby = (blockIdx.x % ntn) * 4;  // first row blocks of X and Y
 
     // copy d of a stage (d = wave + 4 i): X fragments first (piece, row
     // block, k fragment), then Y fragments
@@ -549,10 +553,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         u32x4 *st = ring + (kt % NS) * FST * 64;
 #pragma unroll
         for (int i = 0; i < DPW; ++i) {
-            const int d = wave + 4 * i;
+            const int d = wave + NW * i;
             const H16 *src;
             if (d < FX) {
-                const int u = d / (4 * KF), r = (d / KF) % 4, kf = d % KF;
+                const int u = d / (RX * KF), r = (d / KF) % RX, kf = d % KF;
                 src = X + u * xps + ((int64_t)(rbx + r) * K16 + kt * KF + kf) * 512;
             } else {
                 const int e = d - FX;
@@ -589,9 +593,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // after the ring, copied before the first stage so that the first
     // stage's wait covers them
     const unsigned *scl = reinterpret_cast<const unsigned *>(ring + NS * FST * 64);
-    if constexpr (CS) {
+    if constexpr (CS) {  // RX/4 tiles of 128 functions, consecutive in cscale
         const unsigned char *src = cscale + (int64_t)(rbx / 4) * nchp * 128;
-        for (int i = wave; i < nchp / 8; i += 4)
+        for (int i = wave; i < (RX / 4) * nchp / 8; i += NW)
             __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(src + i * 1024 + lane * 16),
                                              (__attribute__((address_space(3))) void *)(ring + NS * FST * 64 + i * 64),
                                              16, 0, 0);
@@ -605,7 +609,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 unsigned wd = 0;
-                if constexpr (CS) wd = scl[(c * 128 + (wm + a) * 32 + 8 * g + 4 * (lane >> 5)) >> 2];
+                if constexpr (CS)
+                    wd = scl[(((wm + a) >> 2) * nchp * 128 + c * 128 + ((wm + a) & 3) * 32 + 8 * g + 4 * (lane >> 5)) >> 2];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float f = CS ? __builtin_bit_cast(float, ((wd >> (8 * i)) & 0xffu) << 23) : 1.f;
@@ -637,7 +642,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
             for (int u = 0; u < NX; ++u)
 #pragma unroll
-                for (int a = 0; a < 2; ++a) fx[u][a] = st[((u * 4 + wm + a) * KF + kf) * 64 + lane];
+                for (int a = 0; a < 2; ++a) fx[u][a] = st[((u * RX + wm + a) * KF + kf) * 64 + lane];
 #pragma unroll
             for (int v = 0; v < NY; ++v)
 #pragma unroll
@@ -707,7 +712,7 @@ bool mgemm_shape_supported(int mode, int ks, int ns, int kch, bool direct) {
 
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
                         int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
-                        const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s) {
+                        const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s, int wr) {
     if (Kp % 32) return hipErrorInvalidValue;
     const bool d64 = C64 != nullptr;
     if (h16 == kF16 && !d64 && !cscale) return hipErrorInvalidValue;
@@ -715,20 +720,24 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
     const int K16 = Kp / 16;
     int KS = ks, NS = ns;
     mgemm_defaults(mode, h16, d64, KS, NS, kch);
-    const int grid = ((Bn + kGemmBM - 1) / kGemmBM) * ((Hn + 127) / 128);
+    if (wr != 2 && wr != 4) return hipErrorInvalidValue;
+    const int grid = ((Bn + 64 * wr - 1) / (64 * wr)) * ((Hn + 127) / 128);
     const int npx = mode == 1 ? 1 : (mode == 3 ? 2 : 3);
-    const size_t lds = (size_t)NS * 2 * npx * 4 * (KS / 16) * 1024 + (h16 == kF16 && !d64 ? (size_t)nchp * 128 : 0);
-#define LC_MG1(T, MV, KSV, NSV, DV, KV)                                                                         \
-    if (mode == MV && KS == KSV && NS == NSV && d64 == DV && kch == KV) {                                       \
+    const size_t lds = (size_t)NS * npx * (2 * wr + 4) * (KS / 16) * 1024 +
+                       (h16 == kF16 && !d64 ? (size_t)(wr / 2) * nchp * 128 : 0);
+#define LC_MG2(T, MV, KSV, NSV, DV, KV, WV)                                                                     \
+    if (mode == MV && KS == KSV && NS == NSV && d64 == DV && kch == KV && wr == WV) {                           \
         if (lds > 65536) {                                                                                      \
-            hipError_t e = hipFuncSetAttribute((const void *)k_mgemm<T, MV, KSV, NSV, DV, KV>,                  \
+            hipError_t e = hipFuncSetAttribute((const void *)k_mgemm<T, MV, KSV, NSV, DV, KV, WV>,              \
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
             if (e != hipSuccess) return e;                                                                      \
         }                                                                                                       \
-        hipLaunchKernelGGL((k_mgemm<T, MV, KSV, NSV, DV, KV>), dim3(grid), dim3(256), lds, s, (const T *)X,    \
-                           xps, (const T *)Y, yps, Bn, Hn, K16, Out, ldo, C64, rowexp, colexp, cscale, nchp);  \
+        hipLaunchKernelGGL((k_mgemm<T, MV, KSV, NSV, DV, KV, WV>), dim3(grid), dim3(128 * WV), lds, s,          \
+                           (const T *)X, xps, (const T *)Y, yps, Bn, Hn, K16, Out, ldo, C64, rowexp, colexp,    \
+                           cscale, nchp);                                                                       \
         return hipGetLastError();                                                                               \
     }
+#define LC_MG1(T, MV, KSV, NSV, DV, KV) LC_MG2(T, MV, KSV, NSV, DV, KV, 2)
 #define LC_MG(T, MV, KSV, NSV)                                                                                  \
     LC_MG1(T, MV, KSV, NSV, false, 8) LC_MG1(T, MV, KSV, NSV, false, 16)                                        \
     LC_MG1(T, MV, KSV, NSV, true, 2) LC_MG1(T, MV, KSV, NSV, true, 4)                                           \
@@ -739,9 +748,12 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
     LC_MG(T, 6, 16, 2) LC_MG(T, 6, 16, 3)
     if (h16 == kBF16) {
         LC_MG_ALL(__bf16)
+        LC_MG2(__bf16, 3, 16, 4, false, 16, 4) LC_MG2(__bf16, 3, 16, 4, true, 8, 4)
     } else {
         LC_MG_ALL(_Float16)
+        LC_MG2(_Float16, 3, 16, 4, false, 16, 4) LC_MG2(_Float16, 3, 16, 4, true, 4, 4)
     }
+#undef LC_MG2
 #undef LC_MG_ALL
 #undef LC_MG
 #undef LC_MG1

@@ -45,14 +45,14 @@ hipError_t launch_transpose_a(const double *A, int H, int P, double *AT, hipStre
 // first); BF16: no scale
 hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int npc, void *X,
                              int64_t piece_stride, int64_t Bpad, int *cexp, int *colexp, unsigned char *cscale,
-                             hipStream_t s);
+                             hipStream_t s, int bm = kGemmBM);
 // C64 == nullptr: FP32 sums into Out[Bn][ldo]; otherwise finished FP64
 // values into C64[Bn][ldo] scaled by 2^(rowexp[j] + colexp[b]); FP16 with
 // FP32 output folds each chunk's sums in with the factors cscale of the
 // column split (required there; unused with C64)
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
                         int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
-                        const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s);
+                        const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s, int wr = 2);
 hipError_t launch_gdst(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,
                        int64_t H, int64_t L, int64_t N, const double2 *tw_pre, const double2 *tw_pack,
                        const double2 *tw_fft, const FftSched &sch, double *C, hipStream_t s);

@@ -259,6 +259,26 @@ def test_product_stage_shapes(lc, monkeypatch, mode, ks, ns):
         assert E_a <= BOUND[mode]
 
 
+@pytest.mark.parametrize("mode", ["fp16x3", "bf16x3"])
+def test_product_block_rows(lc, monkeypatch, mode):
+    # the three-product modes' two product block heights (256 functions, the
+    # default, and 128) on B below one block, between blocks and above two,
+    # with P not a multiple of 32, Abel and direct forms: each output element
+    # is the same sum in the same order either way, so the results agree bit
+    # for bit, and both meet the mode's bound
+    for B in (77, 300, 600):
+        for run in (_run, _run_direct):
+            out = {}
+            for rows in (128, 256):
+                monkeypatch.setenv("LC_MGEMM_BLOCK_ROWS", str(rows))
+                C, coef = run(lc, mode, 1000, 1600, 777, B, 500, seed=B)
+                E_c, E_a = _errors(C, coef, 777)
+                banner(f"[gpu] gemm {mode} {run.__name__} B={B} block rows {rows}: E_c {E_c:.2e} E_a {E_a:.2e}")
+                assert E_a <= BOUND[mode]
+                out[rows] = C
+            assert np.array_equal(out[128], out[256])
+
+
 DEFAULT_KCH = {"fp16x3": 4, "bf16x6": 4, "bf16x3": 8, "fp16x1": 8}
 
 
