@@ -747,7 +747,8 @@ def _sub(line):
             "library_gemm_point", "stated_q_point")
     out = {k: line[k] for k in keep if k in line}
     rf = line["roofline"]
-    out["roofline"] = {k: rf[k] for k in ("bound", "kernel", "kernel_ms", "achieved", "unit", "peak", "frac")}
+    out["roofline"] = {k: rf[k] for k in ("bound", "kernel", "kernel_ms", "achieved", "unit", "peak", "frac",
+                                          "traffic", "traffic_kernel") if k in rf}
     return out
 
 
