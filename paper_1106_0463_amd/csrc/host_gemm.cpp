@@ -173,6 +173,10 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
     if (const char *kc = getenv("LC_MGEMM_KCH")) g->kch = atoi(kc);
     int rows = 256;
     if (const char *br = getenv("LC_MGEMM_BLOCK_ROWS")) rows = atoi(br);
+    if (rows != 128 && rows != 256) {
+        free_gemm(g);
+        return fail_status(LC_ERR_INVALID, who + "LC_MGEMM_BLOCK_ROWS must be 128 or 256");
+    }
     if (const char *st = getenv("LC_MGEMM_STAGES")) {
         if (sscanf(st, "%d,%d", &g->ks, &g->ns) != 2) g->ks = g->ns = -1;
     }

@@ -117,7 +117,8 @@ def test_execute_2d_rejects_null(lib):
     assert lib.lc_execute_2d(None, None, None, None) == 1
 
 
-@pytest.mark.parametrize("env", [("LC_MGEMM_STAGES", "64,7"), ("LC_MGEMM_STAGES", "16"), ("LC_MGEMM_KCH", "3")])
+@pytest.mark.parametrize("env", [("LC_MGEMM_STAGES", "64,7"), ("LC_MGEMM_STAGES", "16"), ("LC_MGEMM_KCH", "3"),
+                                 ("LC_MGEMM_BLOCK_ROWS", "192")])
 def test_gemm_overrides_without_kernel_rejected(monkeypatch, env):
     # a product shape the library holds no kernel for fails at plan time,
     # before any device work
