@@ -316,6 +316,31 @@ QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu) {
     return c;
 }
 
+bool pair_quad_cfg(int prec, int Q, QuadCfg &out) {
+    const int vfit = prec == LC_FP64 ? 2 : 4;
+    if (Q % vfit) return false;
+    const int nc = 2 * Q / vfit;  // chunks of a row pair
+    for (int G : {8, 16, 4}) {
+        if (nc % G) continue;
+        const int cpl = nc / G;
+        int u = cpl <= 2 ? 4 : (cpl <= 4 ? 2 : 1);
+        while (u > 1 && !fit_key_ok(cpl, u)) u /= 2;
+        if (!fit_key_ok(cpl, u)) continue;
+        QuadCfg c = out;
+        c.vec = vfit;
+        c.G = G;
+        c.cpl = cpl;
+        c.unroll = u;
+        c.block = 256;
+        c.grid = std::max(1, c.grid);
+        c.Qv = Q;
+        c.rpg = 2;
+        out = c;
+        return true;
+    }
+    return false;
+}
+
 // Workgroup size of an LDS FFT of length L: the smallest of 64 .. 1024
 // threads with at most 8 values per thread (one radix-8 butterfly per thread
 // and pass for L = 8T).
@@ -734,11 +759,14 @@ lc_status tune_single(lc_plan_s *p, hipStream_t s) {
         int fused = 0, threads = 0;
         std::string qs;
         in >> tag;
-        int v[6];
+        int v[7];
         bool ok = tag == "quad";
-        for (int k = 0; ok && k < 6; ++k) ok = (bool)(in >> v[k]);
+        for (int k = 0; ok && k < 7; ++k) ok = (bool)(in >> v[k]);
         if (ok) {
-            q.vec = v[0]; q.G = v[1]; q.cpl = v[2]; q.unroll = v[3]; q.block = v[4]; q.grid = v[5];
+            q.vec = v[0]; q.G = v[1]; q.cpl = v[2]; q.unroll = v[3]; q.block = v[4]; q.grid = v[5]; q.rpg = v[6];
+            ok = q.rpg == 1;  // single plans use one row per lane group
+        }
+        if (ok) {
             ok = quad_cfg_supported(q, d.prec, d.Q) && (in >> tag) && tag == "dst" && (in >> threads);
         }
         if (ok && d.L <= kLdsFftMax) ok = sched_from(in, dc.sched, (int)d.L) && d.L <= 8 * threads && dst_threads_ok(threads);

@@ -380,7 +380,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         mix(rb);
         mix(k.levels);
     }
-    const std::string key = arch_name() + "|batch|" + std::to_string(st->B) + "|" + std::to_string(h);
+    const std::string key = arch_name() + "|batch2|" + std::to_string(st->B) + "|" + std::to_string(h);
     std::string val;
     std::vector<QuadCfg> qcfg;
     std::vector<int> gthreads;
@@ -391,7 +391,7 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         cached = (bool)(in >> nc) && nc == st->classes.size();
         for (size_t i = 0; cached && i < nc; ++i) {
             QuadCfg c = st->classes[i].cfg;
-            cached = (bool)(in >> c.vec >> c.G >> c.cpl >> c.unroll >> c.block >> c.grid) &&
+            cached = (bool)(in >> c.vec >> c.G >> c.cpl >> c.unroll >> c.block >> c.grid >> c.rpg) &&
                      quad_cfg_supported(c, st->classes[i].prec, st->classes[i].Q);
             qcfg.push_back(c);
         }
@@ -469,6 +469,9 @@ lc_status tune_batch(lc_plan_s *p, hipStream_t s) {
         part_starts(tl, st->part_of, st->nparts, qc.tstart);
         qc.cfg = c;
         qc.cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>(qc.ntiles, c.grid));
+        log_line("lc_autotune: class R=%d %s: vec=%d G=%d cpl=%d unroll=%d grid=%d%s%s", qc.Q,
+                 qc.prec == LC_FP64 ? "fp64" : "fp32", qc.cfg.vec, qc.cfg.G, qc.cfg.cpl, qc.cfg.unroll, qc.cfg.grid,
+                 qc.cfg.rpg == 2 ? " (row pairs)" : "", cached ? " (cached)" : "");
     }
     for (size_t i = 0; i < st->groups.size(); ++i) {
         if (st->groups[i].multi) continue;  // 64 threads by construction
@@ -730,6 +733,12 @@ lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::
     }
     chk(upload(st, &st->dfn, hfn));
     // ---- quadrature classes and their tiles
+    // two rows per lane group wherever 2Q fits: by default for FP32 samples
+    // (the uneven batch's 192-byte rows: 0.98 against 1.08 ms per step),
+    // not for FP64 (1.64 against 1.63 ms); LC_BATCH_ROW_PAIRS=0 or 1 sets
+    // it for both.  The autotuner weighs both shapes either way.
+    int row_pairs = -1;
+    if (const char *ev = getenv("LC_BATCH_ROW_PAIRS")) row_pairs = atoi(ev) != 0;
     std::map<std::pair<int, int>, std::vector<int>> cls;
     for (int b = 0; b < B; ++b) cls[{st->fn[b].w_id, st->fn[b].prec}].push_back(b);
     for (auto &kv : cls) {
@@ -744,6 +753,8 @@ lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::
         }
         for (int b : kv.second) qc.rows += st->fn[b].H;
         qc.cfg = default_quad_cfg(qc.prec, qc.Q, qc.rows, cu);
+        if (row_pairs == 1 || (row_pairs < 0 && qc.prec != LC_FP64))
+            pair_quad_cfg(qc.prec, qc.Q, qc.cfg);  // keeps the default where it does not fit
         qc.cfg.Qv = qc.Q;
         qc.w = st->qs[kv.first.first].w;
         qc.fns = kv.second;
@@ -925,9 +936,9 @@ lc_status build_batch(int32_t B, const int64_t *N, const int64_t *M, const std::
                  (long long)st->f_bytes, st->qs.size(), st->classes.size(), st->nfused[0], st->nfused[1],
                  st->large.size(), st->nparts);
         for (auto &qc : st->classes)
-            log_line("  class R=%d %s: %zu functions, %lld rows, %d tiles; vec=%d G=%d cpl=%d unroll=%d grid=%d", qc.Q,
+            log_line("  class R=%d %s: %zu functions, %lld rows, %d tiles; vec=%d G=%d cpl=%d unroll=%d grid=%d%s", qc.Q,
                      qc.prec == LC_FP64 ? "fp64" : "fp32", qc.fns.size(), (long long)qc.rows, qc.ntiles, qc.cfg.vec,
-                     qc.cfg.G, qc.cfg.cpl, qc.cfg.unroll, qc.cfg.grid);
+                     qc.cfg.G, qc.cfg.cpl, qc.cfg.unroll, qc.cfg.grid, qc.cfg.rpg == 2 ? " (row pairs)" : "");
         for (auto &g : st->groups)
             log_line("  DST group: %s T=%d Lmax=%d, %d %s", g.multi ? "packed" : "LDS", g.threads, g.Lmax, g.n,
                      g.multi ? "workgroups" : "functions");

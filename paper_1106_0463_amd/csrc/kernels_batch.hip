@@ -78,6 +78,84 @@ __global__ __launch_bounds__(256) void k_bquad_fit(const unsigned char *__restri
     }
 }
 
+// Two rows per lane group for short rows: the G lanes of a group read the 2Q
+// contiguous samples of rows 2p and 2p+1 in the exact-fit pattern of one row
+// of 2Q (G * CPL chunks of VEC, lane g taking chunks g, g + G, ...), so that
+// a row of 48 FP32 samples is read as a row of 48 FP64 samples is, and the
+// per-row work (reduction, s2, phi store) is spread over twice the bytes.
+// Q is a multiple of VEC, so each chunk lies in one row; each lane keeps
+// one sum per row, in chunk order.
+template <typename T, int VEC, int G, int CPL, int U>
+__global__ __launch_bounds__(256) void k_bquad_pair(const unsigned char *__restrict__ f_arena,
+                                                    const double *__restrict__ w,
+                                                    const BatchTile *__restrict__ tiles, int ntiles,
+                                                    double *__restrict__ phi_arena) {
+    using V = typename VecOf<T, VEC>::type;
+    constexpr int HALF = G * CPL / 2;  // chunks per row
+    static_assert((G * CPL) % 2 == 0, "a row pair splits into two rows of whole chunks");
+    constexpr int Q = HALF * VEC;
+    constexpr int RPW = 64 / G;  // row pairs per wave and unroll step
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int rg = lane / G;
+    const int wv = threadIdx.x >> 6;
+    double wr[CPL][VEC];
+    bool second[CPL];  // chunk c of this lane lies in the pair's second row
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int ch = g + c * G;
+        second[c] = ch >= HALF;
+        const int q0 = (second[c] ? ch - HALF : ch) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) wr[c][e] = w[q0 + e];
+    }
+
+    BatchTile nx{};
+    if ((int)blockIdx.x < ntiles) nx = tiles[blockIdx.x];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile tl = nx;
+        const T *f = reinterpret_cast<const T *>(f_arena + tl.f_off);
+        double *phi = phi_arena + tl.phi_off;
+        const int rend = tl.nrows;
+        const int p0 = wv * (RPW * U);
+        V val[U][CPL];
+        double s2a[U], s2b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ra = 2 * (p0 + u * RPW + rg);
+            const bool va = ra < rend, vb = ra + 1 < rend;
+            const V *p = reinterpret_cast<const V *>(f + (int64_t)ra * Q) + g;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) val[u][c] = (second[c] ? vb : va) ? ld_stream(p + c * G) : (V)(T)0;
+            s2a[u] = va ? ld_global(tl.s2 + ra) : 0.0;
+            s2b[u] = vb ? ld_global(tl.s2 + ra + 1) : 0.0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + (int)gridDim.x < ntiles) nx = tiles[t + gridDim.x];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                double d[VEC];
+                to_d(val[u][c], d);
+                double a = second[c] ? acc1 : acc0;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) a = fma(wr[c][e], d[e], a);
+                if (second[c]) acc1 = a;
+                else acc0 = a;
+            }
+            acc0 = group_sum<G>(acc0);
+            acc1 = group_sum<G>(acc1);
+            const int ra = 2 * (p0 + u * RPW + rg);
+            if (g == 0) {
+                if (ra < rend) st_stream(phi + ra, s2a[u] * acc0);
+                if (ra + 1 < rend) st_stream(phi + ra + 1, s2b[u] * acc1);
+            }
+        }
+    }
+}
+
 // One 16-byte chunk per lane for short rows (G/2 < Q/VEC <= G, lanes past
 // Q/VEC idle): the 64/G rows of a load instruction are adjacent, so it reads
 // whole cache lines where the exact-fit shape would read halves of them.
@@ -175,6 +253,17 @@ static hipError_t bfit(const QuadCfg &c, const void *f, const double *w, const B
     return hipGetLastError();
 }
 
+template <typename T, int VEC, int G, int CPL, int U>
+static hipError_t bpair(const QuadCfg &c, const void *f, const double *w, const BatchTile *tiles, int ntiles,
+                        double *phi, hipStream_t s) {
+    if (g_bocc)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_bocc, (const void *)k_bquad_pair<T, VEC, G, CPL, U>,
+                                                            c.block, 0);
+    hipLaunchKernelGGL((k_bquad_pair<T, VEC, G, CPL, U>), dim3(c.grid), dim3(c.block), 0, s,
+                       (const unsigned char *)f, w, tiles, ntiles, phi);
+    return hipGetLastError();
+}
+
 template <typename T, int VEC, int G, int U>
 static hipError_t bone(const QuadCfg &c, const void *f, const double *w, int Q, const BatchTile *tiles,
                        int ntiles, double *phi, hipStream_t s) {
@@ -196,33 +285,47 @@ static hipError_t bgen(const QuadCfg &c, const void *f, const double *w, int Q, 
     return hipGetLastError();
 }
 
-#define LC_BFIT_CASES(TT, VV, GG)                                                                 \
+#define LC_BFIT_CASES_K(K, TT, VV, GG)                                                             \
     if (c.G == GG && c.vec == VV) {                                                               \
         switch (c.cpl * 16 + c.unroll) {                                                          \
-            case 1 * 16 + 1: return bfit<TT, VV, GG, 1, 1>(c, f, w, tiles, ntiles, phi, s); \
-            case 1 * 16 + 2: return bfit<TT, VV, GG, 1, 2>(c, f, w, tiles, ntiles, phi, s); \
-            case 1 * 16 + 4: return bfit<TT, VV, GG, 1, 4>(c, f, w, tiles, ntiles, phi, s); \
-            case 2 * 16 + 1: return bfit<TT, VV, GG, 2, 1>(c, f, w, tiles, ntiles, phi, s); \
-            case 2 * 16 + 2: return bfit<TT, VV, GG, 2, 2>(c, f, w, tiles, ntiles, phi, s); \
-            case 2 * 16 + 4: return bfit<TT, VV, GG, 2, 4>(c, f, w, tiles, ntiles, phi, s); \
-            case 3 * 16 + 1: return bfit<TT, VV, GG, 3, 1>(c, f, w, tiles, ntiles, phi, s); \
-            case 3 * 16 + 2: return bfit<TT, VV, GG, 3, 2>(c, f, w, tiles, ntiles, phi, s); \
-            case 4 * 16 + 1: return bfit<TT, VV, GG, 4, 1>(c, f, w, tiles, ntiles, phi, s); \
-            case 4 * 16 + 2: return bfit<TT, VV, GG, 4, 2>(c, f, w, tiles, ntiles, phi, s); \
-            case 6 * 16 + 1: return bfit<TT, VV, GG, 6, 1>(c, f, w, tiles, ntiles, phi, s); \
-            case 8 * 16 + 1: return bfit<TT, VV, GG, 8, 1>(c, f, w, tiles, ntiles, phi, s); \
-            case 5 * 16 + 1: return bfit<TT, VV, GG, 5, 1>(c, f, w, tiles, ntiles, phi, s); \
-            case 7 * 16 + 1: return bfit<TT, VV, GG, 7, 1>(c, f, w, tiles, ntiles, phi, s); \
-            case 9 * 16 + 1: return bfit<TT, VV, GG, 9, 1>(c, f, w, tiles, ntiles, phi, s); \
-            case 10 * 16 + 1: return bfit<TT, VV, GG, 10, 1>(c, f, w, tiles, ntiles, phi, s);\
-            case 11 * 16 + 1: return bfit<TT, VV, GG, 11, 1>(c, f, w, tiles, ntiles, phi, s);\
+            case 1 * 16 + 1: return K<TT, VV, GG, 1, 1>(c, f, w, tiles, ntiles, phi, s);   \
+            case 1 * 16 + 2: return K<TT, VV, GG, 1, 2>(c, f, w, tiles, ntiles, phi, s);   \
+            case 1 * 16 + 4: return K<TT, VV, GG, 1, 4>(c, f, w, tiles, ntiles, phi, s);   \
+            case 2 * 16 + 1: return K<TT, VV, GG, 2, 1>(c, f, w, tiles, ntiles, phi, s);   \
+            case 2 * 16 + 2: return K<TT, VV, GG, 2, 2>(c, f, w, tiles, ntiles, phi, s);   \
+            case 2 * 16 + 4: return K<TT, VV, GG, 2, 4>(c, f, w, tiles, ntiles, phi, s);   \
+            case 3 * 16 + 1: return K<TT, VV, GG, 3, 1>(c, f, w, tiles, ntiles, phi, s);   \
+            case 3 * 16 + 2: return K<TT, VV, GG, 3, 2>(c, f, w, tiles, ntiles, phi, s);   \
+            case 4 * 16 + 1: return K<TT, VV, GG, 4, 1>(c, f, w, tiles, ntiles, phi, s);   \
+            case 4 * 16 + 2: return K<TT, VV, GG, 4, 2>(c, f, w, tiles, ntiles, phi, s);   \
+            case 6 * 16 + 1: return K<TT, VV, GG, 6, 1>(c, f, w, tiles, ntiles, phi, s);   \
+            case 8 * 16 + 1: return K<TT, VV, GG, 8, 1>(c, f, w, tiles, ntiles, phi, s);   \
+            case 5 * 16 + 1: return K<TT, VV, GG, 5, 1>(c, f, w, tiles, ntiles, phi, s);   \
+            case 7 * 16 + 1: return K<TT, VV, GG, 7, 1>(c, f, w, tiles, ntiles, phi, s);   \
+            case 9 * 16 + 1: return K<TT, VV, GG, 9, 1>(c, f, w, tiles, ntiles, phi, s);   \
+            case 10 * 16 + 1: return K<TT, VV, GG, 10, 1>(c, f, w, tiles, ntiles, phi, s); \
+            case 11 * 16 + 1: return K<TT, VV, GG, 11, 1>(c, f, w, tiles, ntiles, phi, s); \
             default: break;                                                                       \
         }                                                                                         \
     }
+#define LC_BFIT_CASES(TT, VV, GG) LC_BFIT_CASES_K(bfit, TT, VV, GG)
 
 template <typename T>
 static hipError_t bdispatch(const QuadCfg &c, const void *f, const double *w, int Q, const BatchTile *tiles,
                             int ntiles, double *phi, hipStream_t s) {
+    if (c.rpg == 2) {
+        if constexpr (sizeof(T) == 8) {
+            LC_BFIT_CASES_K(bpair, T, 2, 4)
+            LC_BFIT_CASES_K(bpair, T, 2, 8)
+            LC_BFIT_CASES_K(bpair, T, 2, 16)
+        } else {
+            LC_BFIT_CASES_K(bpair, T, 4, 4)
+            LC_BFIT_CASES_K(bpair, T, 4, 8)
+            LC_BFIT_CASES_K(bpair, T, 4, 16)
+        }
+        return hipErrorInvalidValue;
+    }
+    if (c.rpg != 1) return hipErrorInvalidValue;
     if (c.cpl > 0) {
         if constexpr (sizeof(T) == 8) {
             LC_BFIT_CASES(T, 2, 4)
@@ -272,6 +375,7 @@ static hipError_t bdispatch(const QuadCfg &c, const void *f, const double *w, in
     return hipErrorInvalidValue;
 }
 #undef LC_BFIT_CASES
+#undef LC_BFIT_CASES_K
 
 int bquad_blocks_per_cu(const QuadCfg &cfg, int prec) {
     int n = 0;

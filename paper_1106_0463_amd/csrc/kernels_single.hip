@@ -332,12 +332,24 @@ int quad_blocks_per_cu(const QuadCfg &cfg, int prec) {
     return (e == hipSuccess && n > 0) ? n : 0;
 }
 
-int quad_rows_per_block(const QuadCfg &c) { return (c.block / 64) * (64 / c.G) * (c.cpl != 0 ? c.unroll : 1); }
+int quad_rows_per_block(const QuadCfg &c) {
+    return (c.block / 64) * (64 / c.G) * (c.cpl != 0 ? c.unroll : 1) * (c.rpg == 2 ? 2 : 1);
+}
 
 bool quad_cfg_supported(const QuadCfg &c, int prec, int Q) {
     const int esz = prec == LC_FP64 ? 8 : 4;
     if (c.block != 256 || c.grid < 1) return false;
     if (Q % c.vec) return false;
+    if (c.rpg != 1 && c.rpg != 2) return false;
+    if (c.rpg == 2) {  // batch plans only: two rows of Q per lane group
+        if (c.vec != 16 / esz || !(c.G == 4 || c.G == 8 || c.G == 16)) return false;
+        if (c.G * c.cpl * c.vec != 2 * Q) return false;
+        const int key = c.cpl * 16 + c.unroll;
+        const int ok[] = {17, 18, 20, 33, 34, 36, 49, 50, 65, 66, 81, 97, 113, 129, 145, 161, 177};
+        for (int k : ok)
+            if (k == key) return true;
+        return false;
+    }
     if (c.cpl > 0) {
         const int vec_ok = esz == 8 ? 2 : 4;
         if (c.vec != vec_ok) return false;
@@ -363,7 +375,7 @@ bool quad_cfg_supported(const QuadCfg &c, int prec, int Q) {
 
 hipError_t launch_quad(const QuadCfg &cfg, int prec, const void *f, const double *w, const double *s2,
                        int64_t rows, int Q, double *phi, hipStream_t s) {
-    if (!quad_cfg_supported(cfg, prec, Q)) return hipErrorInvalidValue;
+    if (cfg.rpg != 1 || !quad_cfg_supported(cfg, prec, Q)) return hipErrorInvalidValue;
     if (prec == LC_FP64) return dispatch_quad<double>(cfg, f, w, s2, rows, Q, phi, s);
     return dispatch_quad<float>(cfg, f, w, s2, rows, Q, phi, s);
 }

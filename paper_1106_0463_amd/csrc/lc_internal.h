@@ -35,6 +35,8 @@ struct QuadCfg {
     int block;      // threads per block
     int grid;       // blocks
     int Qv;         // Q (used by the batched generic kernel)
+    int rpg = 1;    // rows per lane group: 1, or 2 (batch exact fit over row pairs,
+                    // G * cpl * vec = 2 Q)
 };
 
 struct DstCfg {
@@ -266,6 +268,9 @@ double2 dd_split(long double v);
 void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack,
               std::vector<double2> &fft);
 QuadCfg default_quad_cfg(int prec, int Q, int64_t rows, int num_cu);
+// the batch's exact fit over row pairs for (prec, Q) into out (grid kept);
+// false when 2Q does not split into whole 16-byte chunks of a built shape
+bool pair_quad_cfg(int prec, int Q, QuadCfg &out);
 // resident blocks per CU of the quadrature variant cfg selects (single
 // plans / batch plans; cfg.Qv must hold Q); 0 if unknown
 int quad_blocks_per_cu(const QuadCfg &cfg, int prec);

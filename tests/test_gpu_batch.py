@@ -96,6 +96,42 @@ def test_batch_matches_single_plans(lc):
     bp.destroy()
 
 
+def test_row_pairs_small_ragged_batch(lc, monkeypatch):
+    # the quadrature shape with two rows per lane group (LC_BATCH_ROW_PAIRS=1,
+    # used where 2Q splits into whole 16-byte chunks: Q = 16, 32, 48, 64 here,
+    # both precisions) against the method oracle and against the one-row
+    # shapes (LC_BATCH_ROW_PAIRS=0: another summation order)
+    import torch
+    banner(f"[gpu] ragged batch of {len(SMALL)}, row pairs")
+    funcs = [s[0] for s in SMALL]
+    N = [s[1] for s in SMALL]
+    M = [s[2] for s in SMALL]
+    Q = [s[3] for s in SMALL]
+    prec = [s[4] for s in SMALL]
+    monkeypatch.setenv("LC_BATCH_ROW_PAIRS", "0")
+    bp, arena, c_off = _build(lc, funcs, N, M, Q, prec)
+    c1 = bp.execute(arena).cpu().numpy()
+    bp.destroy()
+    monkeypatch.setenv("LC_BATCH_ROW_PAIRS", "1")
+    bp, arena, c_off = _build(lc, funcs, N, M, Q, prec)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        c2 = bp.execute(arena, stream=s)   # captured graph
+        s.synchronize()
+    c2 = c2.cpu().numpy()
+    for b, (f, n, m, q, pr) in enumerate(SMALL):
+        got = c2[c_off[b]:c_off[b + 1]]
+        ref = np.array(oracle.method_coeffs(f, n, expected_grid(m), q), dtype=float)
+        if pr == "fp64":
+            assert rel_err(got, ref) <= TOL, b
+            assert rel_err(got, c1[c_off[b]:c_off[b + 1]]) <= 5e-14, b
+        else:
+            k = 2 * np.arange(n) + 1
+            assert rel_err(got / k, ref / k) <= 1e-7, b
+            assert rel_err(got, c1[c_off[b]:c_off[b + 1]]) <= 5e-14, b
+    bp.destroy()
+
+
 def test_graph_replay_and_eager_identical(lc):
     import torch
     banner("[gpu] graph replay / eager / re-capture")
@@ -159,10 +195,13 @@ def test_uneven_series_resolving_q_exact(lc):
         assert rel_err(got, coeffs[k]) <= TOL, (k, int(N[k]))
 
 
-def test_uneven_series_full_batch_stated_q(lc):
+@pytest.mark.parametrize("prec,pairs", [("fp64", "0"), ("fp64", "1"), ("fp32", None)])
+def test_uneven_series_full_batch_stated_q(lc, monkeypatch, prec, pairs):
     # The full 4096-function batch at the stated Q = 48 (under-resolving), in
     # the launch the benchmark times: executed on a side stream, so the
-    # captured graph runs (first call captures, the second replays).
+    # captured graph runs (first call captures, the second replays); FP64
+    # samples with one row per lane group and with row pairs
+    # (LC_BATCH_ROW_PAIRS), FP32 samples with the default (row pairs).
     # Arithmetic parity on 64 seeded members, the longest (N_b = 8191, an FFT
     # of 8192 points in LDS) and the shortest among them, against the method
     # oracle.  Those members are sampled at the oracle's own nodes (rounded
@@ -170,12 +209,17 @@ def test_uneven_series_full_batch_stated_q(lc):
     # arithmetic only.
     import torch
     from workloads.gpu import series_ragged
-    banner("[gpu] uneven series batch B=4096, Q=48: 64 members through the captured graph")
+    banner(f"[gpu] uneven series batch B=4096, Q=48, {prec}, row pairs {pairs}: 64 members through the captured graph")
+    if pairs is None:
+        monkeypatch.delenv("LC_BATCH_ROW_PAIRS", raising=False)
+    else:
+        monkeypatch.setenv("LC_BATCH_ROW_PAIRS", pairs)
+    esz, flag = (4, 1) if prec == "fp32" else (8, 0)
     sb = W.batch_uneven(B=4096)
-    bp = lc.plan_batch(sb.N, sb.M, sb.Q, "fp64")
+    bp = lc.plan_batch(sb.N, sb.M, sb.Q, prec)
     f_off, x_off, c_off = bp.offsets()
     arena = torch.zeros(int(f_off[-1]) + 256, dtype=torch.uint8, device="cuda")
-    series_ragged(sb.coeffs, bp.nodes, x_off, arena, f_off, np.zeros(4096, dtype=np.int32))
+    series_ragged(sb.coeffs, bp.nodes, x_off, arena, f_off, np.full(4096, flag, dtype=np.int32))
     rng = np.random.default_rng(35)
     pick = set(rng.choice(4096, 62, replace=False).tolist())
     pick |= {int(np.argmax(sb.N)), int(np.argmin(sb.N))}
@@ -189,12 +233,13 @@ def test_uneven_series_full_batch_stated_q(lc):
     for k, b in enumerate(pick):
         X = oracle.abel_node_set(expected_grid(int(sb.M[b])), 48).astype(np.float64).reshape(-1)
         xs[int(xo[k]):int(xo[k + 1])] = torch.from_numpy(X).cuda()
-    fo = xo * 8
+    fo = xo * esz
     tmp = torch.zeros(int(fo[-1]), dtype=torch.uint8, device="cuda")
-    series_ragged([sb.coeffs[b] for b in pick], xs, xo, tmp, fo, np.zeros(pick.size, dtype=np.int32))
+    series_ragged([sb.coeffs[b] for b in pick], xs, xo, tmp, fo, np.full(pick.size, flag, dtype=np.int32))
     for k, b in enumerate(pick):
         arena[int(f_off[b]):int(f_off[b]) + int(fo[k + 1] - fo[k])] = tmp[int(fo[k]):int(fo[k + 1])]
-    samples = tmp.view(torch.float64).cpu().numpy()
+    # the oracle takes the very samples the kernels read (FP32 ones exactly)
+    samples = tmp.view(torch.float32 if prec == "fp32" else torch.float64).cpu().numpy().astype(np.float64)
     del tmp, xs
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
