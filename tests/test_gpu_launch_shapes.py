@@ -4,8 +4,9 @@ The autotuner times all supported shapes of the single and batched
 quadrature reductions but only the chosen one reaches a caller.  Here each
 shape is forced through the autotuner's cache file (its last entry for a
 plan wins) and executed: exact-fit variants (weights in registers, rows
-unrolled), one-chunk-per-lane variants (rows shorter than a lane group, the
-spare lanes idle) and generic variants (any Q), each with a one-block grid (one
+unrolled), for batches also over row pairs (two rows per lane group),
+one-chunk-per-lane variants (rows shorter than a lane group, the spare lanes
+idle) and generic variants (any Q), each with a one-block grid (one
 block strides over every row), a few blocks and more blocks than rows.
 Every result must equal the default shape's up to summation order, and the
 single FP64 plan also matches the method oracle.  The DST workgroup sizes of
@@ -32,23 +33,25 @@ def lc():
     return lc
 
 
-def shapes(prec: str, q: int):
-    """(vec, G, cpl, unroll) of every reduction the library accepts for q."""
+def shapes(prec: str, q: int, batch: bool = False):
+    """(vec, G, cpl, unroll, rows per lane group) of every reduction the
+    library accepts for q (row pairs in batch plans only)."""
     out = []
     vfit = 2 if prec == "fp64" else 4
-    for G in (4, 8, 16):
-        for cpl in (1, 2, 3, 4, 6, 8):
-            for u in (1, 2, 4):
-                if G * cpl * vfit == q and cpl * 16 + u in FIT_KEYS:
-                    out.append((vfit, G, cpl, u))
+    for rpg in ((1, 2) if batch else (1,)):
+        for G in (4, 8, 16):
+            for cpl in (1, 2, 3, 4, 6, 8):
+                for u in (1, 2, 4):
+                    if G * cpl * vfit == rpg * q and cpl * 16 + u in FIT_KEYS:
+                        out.append((vfit, G, cpl, u, rpg))
     nch = q // vfit  # one 16-byte chunk per lane, lanes past nch idle
     for G in (8, 16, 32, 64):
         if q % vfit == 0 and G < 2 * nch <= 2 * G:
-            out.extend((vfit, G, -1, u) for u in (1, 2, 4, 8))
+            out.extend((vfit, G, -1, u, 1) for u in (1, 2, 4, 8))
     for vec in (1, 2):
         for G in (4, 8, 16, 32, 64):
             if q % vec == 0 and (vec == 1 or G >= 16):
-                out.append((vec, G, 0, 1))
+                out.append((vec, G, 0, 1, 1))
     return out
 
 
@@ -86,7 +89,7 @@ def test_single_shapes(lc, tmp_path, monkeypatch, prec, Q):
     ref = p.execute(fx).cpu().numpy()
     p.autotune()
     key, tok = _last_entry(cache, "single")
-    assert tok[0] == "quad" and tok[7] == "dst" and tok[-2] == "fused"
+    assert tok[0] == "quad" and tok[8] == "dst" and tok[-2] == "fused"
     tok[-1] = "0"  # the reduction kernel, not the fused small path
     if prec == "fp64":
         Me = expected_grid(M)
@@ -95,8 +98,8 @@ def test_single_shapes(lc, tmp_path, monkeypatch, prec, Q):
     worst = 0.0
     cases = [(s, g) for s in shapes(prec, Q) for g in GRIDS]
     banner(f"[gpu] single {prec} Q={Q}: {len(cases)} reduction shapes x grids")
-    for (vec, G, cpl, u), grid in cases:
-        forced = ["quad", vec, G, cpl, u, 256, grid] + tok[7:]
+    for (vec, G, cpl, u, rpg), grid in cases:
+        forced = ["quad", vec, G, cpl, u, 256, grid, rpg] + tok[8:]
         _force(cache, key, forced)
         p.autotune()
         _assert_taken(cache, "single", forced)
@@ -126,21 +129,21 @@ def test_batch_shapes(lc, tmp_path, monkeypatch, prec, Q):
     fill_closed_form_arena(bp.nodes, arena, x_off, f_off, H, [Q] * len(Ns), funcs, [prec == "fp32"] * len(Ns))
     ref = bp.execute(arena).cpu().numpy()
     bp.autotune()
-    key, tok = _last_entry(cache, "batch")
-    assert tok[0] == "1"  # one (Q, precision) class: its six shape numbers follow
+    key, tok = _last_entry(cache, "batch2")
+    assert tok[0] == "1"  # one (Q, precision) class: its seven shape numbers follow
     worst = 0.0
-    cases = [(s, g) for s in shapes(prec, Q) for g in GRIDS]
+    cases = [(s, g) for s in shapes(prec, Q, batch=True) for g in GRIDS]
     banner(f"[gpu] batch {prec} Q={Q}: {len(cases)} reduction shapes x grids")
-    for (vec, G, cpl, u), grid in cases:
-        forced = ["1", vec, G, cpl, u, 256, grid] + tok[7:]
+    for (vec, G, cpl, u, rpg), grid in cases:
+        forced = ["1", vec, G, cpl, u, 256, grid, rpg] + tok[8:]
         _force(cache, key, forced)
         bp.autotune()
-        _assert_taken(cache, "batch", forced)
+        _assert_taken(cache, "batch2", forced)
         got = bp.execute(arena).cpu().numpy()
         torch.cuda.synchronize()
         e = rel_err(got, ref)
         worst = max(worst, e)
-        assert e <= 1e-13, (vec, G, cpl, u, grid, e)
+        assert e <= 1e-13, (vec, G, cpl, u, rpg, grid, e)
     banner(f"    worst difference to the default shape {worst:.2e}")
     bp.destroy()
 
@@ -166,12 +169,12 @@ def test_single_dst_threads(lc, tmp_path, monkeypatch, L):
     assert rel_err(ref, want) <= 1e-12
     p.autotune()
     key, tok = _last_entry(cache, "single")
-    assert tok[7] == "dst" and tok[-2] == "fused"
+    assert tok[8] == "dst" and tok[-2] == "fused"
     tok[-1] = "0"  # the DST kernel, not the fused small path
     sizes = [T for T in (64, 128, 256, 512, 1024) if L <= 8 * T]
     banner(f"[gpu] single DST L={L}: workgroup sizes {sizes}")
     for T in sizes:
-        forced = tok[:8] + [str(T)] + tok[9:]
+        forced = tok[:9] + [str(T)] + tok[10:]
         _force(cache, key, forced)
         p.autotune()
         _assert_taken(cache, "single", forced)
