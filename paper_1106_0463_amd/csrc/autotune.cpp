@@ -111,21 +111,21 @@ std::vector<QuadCfg> quad_candidates(int prec, int Q, int64_t rows, int cu, bool
                 c.Qv = Q;
                 add(c);
             }
-    if (batch)  // two rows per lane group (short rows: halves the per-row work per byte)
-        for (int G : {4, 8, 16})
-            for (int cpl : {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11})
-                for (int u : {1, 2, 4}) {
-                    QuadCfg c{};
-                    c.vec = vfit;
-                    c.G = G;
-                    c.cpl = cpl;
-                    c.unroll = u;
-                    c.block = 256;
-                    c.grid = 1;
-                    c.Qv = Q;
-                    c.rpg = 2;
-                    add(c);
-                }
+    // two rows per lane group (short rows: halves the per-row work per byte)
+    for (int G : {4, 8, 16})
+        for (int cpl : {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11})
+            for (int u : {1, 2, 4}) {
+                QuadCfg c{};
+                c.vec = vfit;
+                c.G = G;
+                c.cpl = cpl;
+                c.unroll = u;
+                c.block = 256;
+                c.grid = 1;
+                c.Qv = Q;
+                c.rpg = 2;
+                add(c);
+            }
     for (int G : {8, 16, 32, 64})
         for (int u : {1, 2, 4, 8}) {
             QuadCfg c{};

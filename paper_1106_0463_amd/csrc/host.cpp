@@ -764,9 +764,6 @@ lc_status tune_single(lc_plan_s *p, hipStream_t s) {
         for (int k = 0; ok && k < 7; ++k) ok = (bool)(in >> v[k]);
         if (ok) {
             q.vec = v[0]; q.G = v[1]; q.cpl = v[2]; q.unroll = v[3]; q.block = v[4]; q.grid = v[5]; q.rpg = v[6];
-            ok = q.rpg == 1;  // single plans use one row per lane group
-        }
-        if (ok) {
             ok = quad_cfg_supported(q, d.prec, d.Q) && (in >> tag) && tag == "dst" && (in >> threads);
         }
         if (ok && d.L <= kLdsFftMax) ok = sched_from(in, dc.sched, (int)d.L) && d.L <= 8 * threads && dst_threads_ok(threads);

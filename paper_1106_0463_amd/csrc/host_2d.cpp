@@ -118,6 +118,11 @@ lc_status lc_plan_2d(int64_t N, int64_t M, int32_t Q, lc_precision prec, lc_plan
     }
     t->q1 = default_quad_cfg((int)prec, Q, SH, device_cu_count());
     t->q2 = default_quad_cfg(LC_FP64, Q, N * d.H, device_cu_count());
+    if (const char *ev = getenv("LC_2D_ROW_PAIRS"))
+        if (atoi(ev)) {
+            pair_quad_cfg((int)prec, Q, t->q1);
+            pair_quad_cfg(LC_FP64, Q, t->q2);
+        }
     lc_plan_s *p = new (std::nothrow) lc_plan_s();
     if (!p) {
         free_2d(t);

@@ -137,6 +137,73 @@ __global__ __launch_bounds__(256) void k_quad_fit(const T *__restrict__ f, const
     }
 }
 
+// Row-pair variant for short rows: a lane group reads rows 2p and 2p+1 (2Q
+// contiguous samples) in the exact-fit pattern of one row of 2Q, each chunk
+// inside one row (Q a multiple of VEC), and keeps one sum per row in chunk
+// order; the per-row reduction and store are spread over twice the bytes.
+template <typename T, int VEC, int G, int CPL, int U>
+__global__ __launch_bounds__(256) void k_quad_pair(const T *__restrict__ f, const double *__restrict__ w,
+                                                   const double *__restrict__ s2, int64_t rows,
+                                                   double *__restrict__ phi) {
+    using V = typename VecOf<T, VEC>::type;
+    constexpr int HALF = G * CPL / 2;  // chunks per row
+    static_assert((G * CPL) % 2 == 0, "a row pair splits into two rows of whole chunks");
+    constexpr int Q = HALF * VEC;
+    constexpr int RPW = 64 / G;  // row pairs per wave and unroll step
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int rg = lane / G;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t pairs = (rows + 1) / 2;
+    double wr[CPL][VEC];
+    bool second[CPL];  // chunk c of this lane lies in the pair's second row
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int ch = g + c * G;
+        second[c] = ch >= HALF;
+        const int q0 = (second[c] ? ch - HALF : ch) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) wr[c][e] = w[q0 + e];
+    }
+
+    for (int64_t p0 = wave * (RPW * U); p0 < pairs; p0 += nwaves * (RPW * U)) {
+        V val[U][CPL];
+        double s2a[U], s2b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t ra = 2 * (p0 + u * RPW + rg);
+            const bool va = ra < rows, vb = ra + 1 < rows;
+            const V *p = reinterpret_cast<const V *>(f + ra * Q) + g;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) val[u][c] = (second[c] ? vb : va) ? ld_stream(p + c * G) : (V)(T)0;
+            s2a[u] = va ? s2[ra] : 0.0;
+            s2b[u] = vb ? s2[ra + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                double d[VEC];
+                to_d(val[u][c], d);
+                double a = second[c] ? acc1 : acc0;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) a = fma(wr[c][e], d[e], a);
+                if (second[c]) acc1 = a;
+                else acc0 = a;
+            }
+            acc0 = group_sum<G>(acc0);
+            acc1 = group_sum<G>(acc1);
+            const int64_t ra = 2 * (p0 + u * RPW + rg);
+            if (g == 0) {
+                if (ra < rows) st_stream(phi + ra, s2a[u] * acc0);
+                if (ra + 1 < rows) st_stream(phi + ra + 1, s2b[u] * acc1);
+            }
+        }
+    }
+}
+
 // One-chunk variant for short rows of NCH = Q/VEC chunks, G/2 < NCH <= G:
 // lane g < NCH reads chunk g, the other lanes idle.  The 64/G rows of one
 // load instruction are adjacent in memory, so it reads whole cache lines
@@ -223,6 +290,17 @@ static hipError_t go_fit(const QuadCfg &c, const void *f, const double *w, const
     return hipGetLastError();
 }
 
+template <typename T, int VEC, int G, int CPL, int U>
+static hipError_t go_pair(const QuadCfg &c, const void *f, const double *w, const double *s2, int64_t rows,
+                          double *phi, hipStream_t s) {
+    if (g_occ)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(g_occ, (const void *)k_quad_pair<T, VEC, G, CPL, U>,
+                                                            c.block, 0);
+    hipLaunchKernelGGL((k_quad_pair<T, VEC, G, CPL, U>), dim3(c.grid), dim3(c.block), 0, s,
+                       (const T *)f, w, s2, rows, phi);
+    return hipGetLastError();
+}
+
 template <typename T, int VEC, int G, int U>
 static hipError_t go_one(const QuadCfg &c, const void *f, const double *w, const double *s2, int64_t rows,
                          int Q, double *phi, hipStream_t s) {
@@ -244,33 +322,47 @@ static hipError_t go_gen(const QuadCfg &c, const void *f, const double *w, const
 }
 
 // Dispatch tables over the instantiated variants.
-#define LC_FIT_CASES(TT, VV, GG)                                                                  \
+#define LC_FIT_CASES_K(K, TT, VV, GG)                                                                    \
     if (c.G == GG && c.vec == VV) {                                                              \
         switch (c.cpl * 16 + c.unroll) {                                                         \
-            case 1 * 16 + 1: return go_fit<TT, VV, GG, 1, 1>(c, f, w, s2, rows, phi, s);          \
-            case 1 * 16 + 2: return go_fit<TT, VV, GG, 1, 2>(c, f, w, s2, rows, phi, s);          \
-            case 1 * 16 + 4: return go_fit<TT, VV, GG, 1, 4>(c, f, w, s2, rows, phi, s);          \
-            case 2 * 16 + 1: return go_fit<TT, VV, GG, 2, 1>(c, f, w, s2, rows, phi, s);          \
-            case 2 * 16 + 2: return go_fit<TT, VV, GG, 2, 2>(c, f, w, s2, rows, phi, s);          \
-            case 2 * 16 + 4: return go_fit<TT, VV, GG, 2, 4>(c, f, w, s2, rows, phi, s);          \
-            case 3 * 16 + 1: return go_fit<TT, VV, GG, 3, 1>(c, f, w, s2, rows, phi, s);          \
-            case 3 * 16 + 2: return go_fit<TT, VV, GG, 3, 2>(c, f, w, s2, rows, phi, s);          \
-            case 4 * 16 + 1: return go_fit<TT, VV, GG, 4, 1>(c, f, w, s2, rows, phi, s);          \
-            case 4 * 16 + 2: return go_fit<TT, VV, GG, 4, 2>(c, f, w, s2, rows, phi, s);          \
-            case 6 * 16 + 1: return go_fit<TT, VV, GG, 6, 1>(c, f, w, s2, rows, phi, s);          \
-            case 8 * 16 + 1: return go_fit<TT, VV, GG, 8, 1>(c, f, w, s2, rows, phi, s);          \
-            case 5 * 16 + 1: return go_fit<TT, VV, GG, 5, 1>(c, f, w, s2, rows, phi, s);         \
-            case 7 * 16 + 1: return go_fit<TT, VV, GG, 7, 1>(c, f, w, s2, rows, phi, s);         \
-            case 9 * 16 + 1: return go_fit<TT, VV, GG, 9, 1>(c, f, w, s2, rows, phi, s);         \
-            case 10 * 16 + 1: return go_fit<TT, VV, GG, 10, 1>(c, f, w, s2, rows, phi, s);        \
-            case 11 * 16 + 1: return go_fit<TT, VV, GG, 11, 1>(c, f, w, s2, rows, phi, s);        \
+            case 1 * 16 + 1: return K<TT, VV, GG, 1, 1>(c, f, w, s2, rows, phi, s);          \
+            case 1 * 16 + 2: return K<TT, VV, GG, 1, 2>(c, f, w, s2, rows, phi, s);          \
+            case 1 * 16 + 4: return K<TT, VV, GG, 1, 4>(c, f, w, s2, rows, phi, s);          \
+            case 2 * 16 + 1: return K<TT, VV, GG, 2, 1>(c, f, w, s2, rows, phi, s);          \
+            case 2 * 16 + 2: return K<TT, VV, GG, 2, 2>(c, f, w, s2, rows, phi, s);          \
+            case 2 * 16 + 4: return K<TT, VV, GG, 2, 4>(c, f, w, s2, rows, phi, s);          \
+            case 3 * 16 + 1: return K<TT, VV, GG, 3, 1>(c, f, w, s2, rows, phi, s);          \
+            case 3 * 16 + 2: return K<TT, VV, GG, 3, 2>(c, f, w, s2, rows, phi, s);          \
+            case 4 * 16 + 1: return K<TT, VV, GG, 4, 1>(c, f, w, s2, rows, phi, s);          \
+            case 4 * 16 + 2: return K<TT, VV, GG, 4, 2>(c, f, w, s2, rows, phi, s);          \
+            case 6 * 16 + 1: return K<TT, VV, GG, 6, 1>(c, f, w, s2, rows, phi, s);          \
+            case 8 * 16 + 1: return K<TT, VV, GG, 8, 1>(c, f, w, s2, rows, phi, s);          \
+            case 5 * 16 + 1: return K<TT, VV, GG, 5, 1>(c, f, w, s2, rows, phi, s);         \
+            case 7 * 16 + 1: return K<TT, VV, GG, 7, 1>(c, f, w, s2, rows, phi, s);         \
+            case 9 * 16 + 1: return K<TT, VV, GG, 9, 1>(c, f, w, s2, rows, phi, s);         \
+            case 10 * 16 + 1: return K<TT, VV, GG, 10, 1>(c, f, w, s2, rows, phi, s);        \
+            case 11 * 16 + 1: return K<TT, VV, GG, 11, 1>(c, f, w, s2, rows, phi, s);        \
             default: break;                                                                      \
         }                                                                                        \
     }
+#define LC_FIT_CASES(TT, VV, GG) LC_FIT_CASES_K(go_fit, TT, VV, GG)
 
 template <typename T>
 static hipError_t dispatch_quad(const QuadCfg &c, const void *f, const double *w, const double *s2,
                                 int64_t rows, int Q, double *phi, hipStream_t s) {
+    if (c.rpg == 2) {
+        if constexpr (sizeof(T) == 8) {
+            LC_FIT_CASES_K(go_pair, T, 2, 4)
+            LC_FIT_CASES_K(go_pair, T, 2, 8)
+            LC_FIT_CASES_K(go_pair, T, 2, 16)
+        } else {
+            LC_FIT_CASES_K(go_pair, T, 4, 4)
+            LC_FIT_CASES_K(go_pair, T, 4, 8)
+            LC_FIT_CASES_K(go_pair, T, 4, 16)
+        }
+        return hipErrorInvalidValue;
+    }
+    if (c.rpg != 1) return hipErrorInvalidValue;
     if (c.cpl > 0) {
         if constexpr (sizeof(T) == 8) {
             LC_FIT_CASES(T, 2, 4)
@@ -320,6 +412,7 @@ static hipError_t dispatch_quad(const QuadCfg &c, const void *f, const double *w
     return hipErrorInvalidValue;
 }
 #undef LC_FIT_CASES
+#undef LC_FIT_CASES_K
 
 int quad_blocks_per_cu(const QuadCfg &cfg, int prec) {
     int n = 0;
@@ -341,7 +434,7 @@ bool quad_cfg_supported(const QuadCfg &c, int prec, int Q) {
     if (c.block != 256 || c.grid < 1) return false;
     if (Q % c.vec) return false;
     if (c.rpg != 1 && c.rpg != 2) return false;
-    if (c.rpg == 2) {  // batch plans only: two rows of Q per lane group
+    if (c.rpg == 2) {  // two rows of Q per lane group
         if (c.vec != 16 / esz || !(c.G == 4 || c.G == 8 || c.G == 16)) return false;
         if (c.G * c.cpl * c.vec != 2 * Q) return false;
         const int key = c.cpl * 16 + c.unroll;
@@ -375,7 +468,7 @@ bool quad_cfg_supported(const QuadCfg &c, int prec, int Q) {
 
 hipError_t launch_quad(const QuadCfg &cfg, int prec, const void *f, const double *w, const double *s2,
                        int64_t rows, int Q, double *phi, hipStream_t s) {
-    if (cfg.rpg != 1 || !quad_cfg_supported(cfg, prec, Q)) return hipErrorInvalidValue;
+    if (!quad_cfg_supported(cfg, prec, Q)) return hipErrorInvalidValue;
     if (prec == LC_FP64) return dispatch_quad<double>(cfg, f, w, s2, rows, Q, phi, s);
     return dispatch_quad<float>(cfg, f, w, s2, rows, Q, phi, s);
 }

@@ -35,7 +35,7 @@ struct QuadCfg {
     int block;      // threads per block
     int grid;       // blocks
     int Qv;         // Q (used by the batched generic kernel)
-    int rpg = 1;    // rows per lane group: 1, or 2 (batch exact fit over row pairs,
+    int rpg = 1;    // rows per lane group: 1, or 2 (exact fit over row pairs,
                     // G * cpl * vec = 2 Q)
 };
 

@@ -71,6 +71,26 @@ def test_2d_separable_closed_forms(lc):
     assert err <= 1e-13
 
 
+@pytest.mark.parametrize("N,M,Q,prec", [(16, 64, 8, "fp64"), (128, 512, 24, "fp64"), (64, 256, 16, "fp32"),
+                                        (256, 1024, 32, "fp64")])
+def test_2d_row_pairs(lc, monkeypatch, N, M, Q, prec):
+    # both passes' reductions over row pairs (LC_2D_ROW_PAIRS=1) against the
+    # one-row shapes (another summation order) and, for FP64 samples, the
+    # 2-D method oracle
+    from helpers import expected_grid
+    banner(f"[gpu] 2-D row pairs N={N} M={M} Q={Q} {prec}")
+    monkeypatch.setenv("LC_2D_ROW_PAIRS", "0")
+    c1, _ = _run(lc, N, M, Q, _f2_torch, precision=prec)
+    monkeypatch.setenv("LC_2D_ROW_PAIRS", "1")
+    c2, _ = _run(lc, N, M, Q, _f2_torch, precision=prec)
+    d = np.max(np.abs(c2 - c1)) / np.max(np.abs(c1))
+    banner(f"    difference to one row per lane group {d:.2e}")
+    assert d <= 1e-13
+    if prec == "fp64" and N <= 16:
+        ref = np.asarray(oracle.method_coeffs_2d(_f2_np, N, expected_grid(M), Q), dtype=float)
+        assert np.max(np.abs(c2 - ref)) / np.max(np.abs(ref)) <= 1e-13
+
+
 def test_2d_fp32_samples(lc):
     banner("[gpu] 2-D FP32 samples vs FP64")
     N, M, Q = 64, 256, 16

@@ -4,7 +4,7 @@ The autotuner times all supported shapes of the single and batched
 quadrature reductions but only the chosen one reaches a caller.  Here each
 shape is forced through the autotuner's cache file (its last entry for a
 plan wins) and executed: exact-fit variants (weights in registers, rows
-unrolled), for batches also over row pairs (two rows per lane group),
+unrolled), also over row pairs (two rows per lane group),
 one-chunk-per-lane variants (rows shorter than a lane group, the spare lanes
 idle) and generic variants (any Q), each with a one-block grid (one
 block strides over every row), a few blocks and more blocks than rows.
@@ -33,12 +33,12 @@ def lc():
     return lc
 
 
-def shapes(prec: str, q: int, batch: bool = False):
+def shapes(prec: str, q: int):
     """(vec, G, cpl, unroll, rows per lane group) of every reduction the
-    library accepts for q (row pairs in batch plans only)."""
+    library accepts for q."""
     out = []
     vfit = 2 if prec == "fp64" else 4
-    for rpg in ((1, 2) if batch else (1,)):
+    for rpg in (1, 2):
         for G in (4, 8, 16):
             for cpl in (1, 2, 3, 4, 6, 8):
                 for u in (1, 2, 4):
@@ -132,7 +132,7 @@ def test_batch_shapes(lc, tmp_path, monkeypatch, prec, Q):
     key, tok = _last_entry(cache, "batch2")
     assert tok[0] == "1"  # one (Q, precision) class: its seven shape numbers follow
     worst = 0.0
-    cases = [(s, g) for s in shapes(prec, Q, batch=True) for g in GRIDS]
+    cases = [(s, g) for s in shapes(prec, Q) for g in GRIDS]
     banner(f"[gpu] batch {prec} Q={Q}: {len(cases)} reduction shapes x grids")
     for (vec, G, cpl, u, rpg), grid in cases:
         forced = ["1", vec, G, cpl, u, 256, grid, rpg] + tok[8:]
