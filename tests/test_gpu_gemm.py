@@ -98,6 +98,42 @@ def test_gemm_split_modes(lc, mode, bound):
     assert E_a <= bound
 
 
+# the largest grids a GEMM plan takes.  Rounding grows with P: the Abel
+# form's FP32 totals and FP32 phi round once per fold and per value, and
+# bf16x6 leaves the mixed class at P = 16384 (E_a 1.16e-7) where fp16x3
+# stays in it (6.4e-8); the FP64 DGEMM form's K = 16384 sums, times up to
+# 2N - 1 in the rescale, reach E_c 1.05e-12 there, the FP64 class's edge.
+# Bounds: E_a for the split modes, E_c for FP64.
+LARGE_P = [("fp16x3", "abel", 8192, 1e-7), ("fp16x3", "abel", 16384, 1e-7), ("fp16x3", "direct", 16384, 1e-7),
+           ("bf16x6", "abel", 8192, 1e-7), ("bf16x6", "abel", 16384, 2e-7), ("fp64", "abel", 8192, 1e-12),
+           ("fp64", "abel", 16384, 2e-12)]
+
+
+def _class_bound(mode):
+    return 1e-12 if mode == "fp64" else 1e-7
+
+
+@pytest.mark.parametrize("mode,form,P,bound", [
+    pytest.param(*c, id=f"{c[0]}-{c[1]}-P{c[2]}" + ("-out_of_class" if c[3] > _class_bound(c[0]) else ""))
+    for c in LARGE_P])
+def test_gemm_largest_p(lc, mode, form, P, bound):
+    # P up to 16384, the largest grid a plan takes (K of 1024 MFMA steps, 64
+    # FP16 exponent chunks per function: the product's largest chunk-factor
+    # run in LDS), with B = 300 functions (one 256-function block and a
+    # ragged second) against the series' own coefficients
+    banner(f"[gpu] gemm {mode} {form}: P = {P}, B = 300")
+    run = _run if form == "abel" else _run_direct
+    C, coef = run(lc, mode, P, 4096, 2048, 300, 1500, seed=21)
+    E_c, E_a = _errors(C, coef, 2048)
+    banner(f"    E_c {E_c:.2e} E_a {E_a:.2e}")
+    if mode == "fp64":
+        assert E_c <= bound
+    else:
+        assert E_a <= bound
+        if form == "direct":
+            assert E_c <= 1e-6
+
+
 def test_gemm_split_matches_fp64_path(lc):
     # ragged sizes (P not a multiple of 32, B not a multiple of the tile)
     banner("[gpu] gemm ragged sizes")
