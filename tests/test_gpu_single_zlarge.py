@@ -8,7 +8,9 @@ configuration the benchmark times, on a seeded subset of 512 indices n.
   49152-point long-double Gauss-Legendre rule), FP64 class 1e-12 max|c|;
 * the composite Abel rule with node counts for band 16384 and six graded
   panels toward x = 1 (about half the samples of the uniform rule): the
-  same definition parity.
+  same definition parity;
+* the largest grid a single plan takes (M = 2^24, the four-step FFT at its
+  largest 2048 x 2048 split) against a closed form.
 """
 import functools
 import numpy as np
@@ -108,3 +110,28 @@ def test_large_band_rule_definition_parity():
     banner(f"    rel err {err:.3e}; {samples / H:.0f} samples per row (uniform rule: 8384)")
     assert err <= TOL
     assert samples < 0.55 * H * 8384
+
+
+def test_largest_grid_closed_form():
+    # the largest grid a single plan takes with the four-step FFT at its
+    # largest split: M = 2^24, H = 2^23, FFT length L = 2^22 = 2048 x 2048
+    # (2 GiB of nodes and 2 GiB of samples at Q = 32), f the generating
+    # function at t = 0.5, whose c_n = 0.5^n (eq. (2.2)) a 32-node Abel rule
+    # resolves; all N = 65536 coefficients against the closed form
+    import torch
+    import paper_1106_0463_amd as lc
+    torch.cuda.set_device(0)
+    N, M, Q = 65536, 1 << 24, 32
+    banner(f"[gpu] largest single grid M = {M}, Q = {Q}: c_n = 0.5^n")
+    p = lc.plan(N, M, Q)
+    assert p.info["M_eff"] == M
+    fx = W.GeneratingFunction(0.5).torch(p.nodes).contiguous()
+    c = p.execute(fx)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy()
+    p.destroy()
+    del fx, c
+    torch.cuda.empty_cache()
+    err = np.max(np.abs(got - 0.5 ** np.arange(N)))
+    banner(f"    max |c_n - 0.5^n| {err:.2e}")
+    assert err <= TOL
