@@ -44,6 +44,7 @@ struct GemmState {
     int h16 = kBF16, npc = 1, kmode = 1, scaled = 0;
     int ks = 0, ns = 0, kch = 0;  // MFMA product shape (0: per-mode defaults)
     int wr = 2;                   // rows of waves per product block (2: 128 functions, 4: 256)
+    bool t64 = false;             // Abel form: FP64 second-level totals (grids above 4096)
     int64_t N = 0, M = 0, M_eff = 0, H = 0, L = 0;
     double *xc = nullptr, *lam = nullptr, *A = nullptr;
     double *Ap = nullptr;  // Abel form: A with the DST pack applied to its rows ([H][P])
@@ -195,6 +196,16 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
     // at the default stage shape, 2-3% faster there than 128 (one ring stage
     // feeds twice the products); 128 (4 waves) for the others
     g->wr = rows == 256 && g->kmode == 3 && g->ks <= 0 && !g->kch ? 4 : 2;
+    // FP64 second-level totals for the Abel form's three- and six-product
+    // modes where K exceeds 4096: the FP32 totals round once per fold, and
+    // at P = 16384 that took bf16x6 to E_a 1.16e-7 and fp16x3 to 6.4e-8
+    // (8.4e-9 and 9.2e-9 with FP64 totals); at P = 4096 they cost 0-3% and
+    // E_a is 0.9-1.8e-8 either way.  LC_MGEMM_T64=0/1 overrides the choice.
+    {
+        bool t64 = g->Kp > 4096;
+        if (const char *t = getenv("LC_MGEMM_T64")) t64 = atoi(t) != 0;
+        g->t64 = t64 && !direct && (g->kmode == 3 || g->kmode == 6) && g->ks <= 0 && !g->kch;
+    }
     if (g->kmode && g->npc && !mgemm_shape_supported(g->kmode, g->ks, g->ns, g->kch, direct != 0)) {
         free_gemm(g);
         return fail_status(LC_ERR_INVALID, who + "LC_MGEMM_STAGES / LC_MGEMM_KCH name no built product kernel");
@@ -295,10 +306,11 @@ lc_status plan_gemm_common(int32_t P, int64_t M, int64_t N, lc_gemm_mode mode, i
     hipGetDevice(&p->device);
     p->ext = g;
     log_line("%sP=%d M_eff=%lld H=%lld N=%lld mode=%d (%d pieces, %d products) rows=%lld padded=%lld "
-             "stages=%s chunk=%s", who.c_str(), P, (long long)g->M_eff, (long long)g->H, (long long)N, g->mode, g->npc,
-             g->kmode, (long long)g->R, (long long)g->Hpad,
+             "stages=%s chunk=%s block=%d totals=%s", who.c_str(), P, (long long)g->M_eff, (long long)g->H,
+             (long long)N, g->mode, g->npc, g->kmode, (long long)g->R, (long long)g->Hpad,
              g->ks ? (std::to_string(g->ks) + "," + std::to_string(g->ns)).c_str() : "default",
-             g->kch ? std::to_string(g->kch).c_str() : "default");
+             g->kch ? std::to_string(g->kch).c_str() : "default", 64 * g->wr,
+             g->direct || g->t64 ? "fp64" : "fp32");
     *out = p;
     return LC_OK;
 }
@@ -373,7 +385,8 @@ lc_status lc_execute_gemm(lc_plan_t p, const double *F_dev, int32_t B, double *C
                          g->ns, g->kch, stream, g->wr);
     else
         e = launch_mgemm(g->h16, g->kmode, g->X, xps, g->Y, g->Hpad * g->Kp, B, (int)g->H, g->Kp, g->Out32,
-                         (int)g->H, nullptr, nullptr, nullptr, g->cscale, g->ks, g->ns, g->kch, stream, g->wr);
+                         (int)g->H, nullptr, nullptr, nullptr, g->cscale, g->ks, g->ns, g->kch, stream, g->wr,
+                         g->t64);
     if (e != hipSuccess) return fail_status(LC_ERR_HIP, std::string("lc_execute_gemm: mfma: ") + hipGetErrorString(e));
     if ((e = timing_end(p, stream, slot)) != hipSuccess) return fail_status(LC_ERR_HIP, "lc_execute_gemm: timing");
     if (g->direct) return LC_OK;

@@ -523,7 +523,7 @@ __device__ __forceinline__ void lds_barrier() {
 // Epilogue: D64 = false writes the FP32 sums to Out[b][j]; D64 = true writes
 // FP64 C[b][j] = sum * 2^(rowexp[j] + colexp[b]) (exponent arrays may be
 // null), the finished coefficients of the direct Legendre-matrix form.
-template <typename H16, int MODE, int KS, int NS, bool D64, int KCH, int WR = 2>
+template <typename H16, int MODE, int KS, int NS, bool D64, int KCH, int WR = 2, bool T64 = false>
 __global__ __launch_bounds__(128 * WR) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mgemm(
     const H16 *__restrict__ X, int64_t xps, const H16 *__restrict__ Y, int64_t yps, int Bn, int Hn, int K16,
     float *__restrict__ Out, int ldo, double *__restrict__ C64, const int *__restrict__ rowexp,
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(128 * WR) __attribute__((amdgpu_waves_per_eu(2, 2))
     // the Abel product (whose output is FP32; the DST that follows averages
     // the errors of phi) and FP64 with shorter chunks for the direct form,
     // where nothing averages the accumulation error of a coefficient.
-    using TotT = typename std::conditional<D64, double, float>::type;
+    using TotT = typename std::conditional<D64 || T64, double, float>::type;
     f32x16 acc[2][2];
     TotT tot[2][2][16];
 #pragma unroll
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(128 * WR) __attribute__((amdgpu_waves_per_eu(2, 2))
                         const int ex = (rowexp ? rowexp[col] : 0) + (colexp ? max(colexp[row], -1000) : 0);
                         C64[(int64_t)row * ldo + col] = ldexp(tot[a][b][v], ex);
                     } else {
-                        Out[(int64_t)row * ldo + col] = tot[a][b][v];
+                        Out[(int64_t)row * ldo + col] = (float)tot[a][b][v];
                     }
                 }
             }
@@ -712,7 +712,7 @@ bool mgemm_shape_supported(int mode, int ks, int ns, int kch, bool direct) {
 
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
                         int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
-                        const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s, int wr) {
+                        const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s, int wr, bool t64) {
     if (Kp % 32) return hipErrorInvalidValue;
     const bool d64 = C64 != nullptr;
     if (h16 == kF16 && !d64 && !cscale) return hipErrorInvalidValue;
@@ -725,18 +725,19 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
     const int npx = mode == 1 ? 1 : (mode == 3 ? 2 : 3);
     const size_t lds = (size_t)NS * npx * (2 * wr + 4) * (KS / 16) * 1024 +
                        (h16 == kF16 && !d64 ? (size_t)(wr / 2) * nchp * 128 : 0);
-#define LC_MG2(T, MV, KSV, NSV, DV, KV, WV)                                                                     \
-    if (mode == MV && KS == KSV && NS == NSV && d64 == DV && kch == KV && wr == WV) {                           \
+#define LC_MG3(T, MV, KSV, NSV, DV, KV, WV, TV)                                                                 \
+    if (mode == MV && KS == KSV && NS == NSV && d64 == DV && kch == KV && wr == WV && t64 == TV) {              \
         if (lds > 65536) {                                                                                      \
-            hipError_t e = hipFuncSetAttribute((const void *)k_mgemm<T, MV, KSV, NSV, DV, KV, WV>,              \
+            hipError_t e = hipFuncSetAttribute((const void *)k_mgemm<T, MV, KSV, NSV, DV, KV, WV, TV>,          \
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
             if (e != hipSuccess) return e;                                                                      \
         }                                                                                                       \
-        hipLaunchKernelGGL((k_mgemm<T, MV, KSV, NSV, DV, KV, WV>), dim3(grid), dim3(128 * WV), lds, s,          \
+        hipLaunchKernelGGL((k_mgemm<T, MV, KSV, NSV, DV, KV, WV, TV>), dim3(grid), dim3(128 * WV), lds, s,      \
                            (const T *)X, xps, (const T *)Y, yps, Bn, Hn, K16, Out, ldo, C64, rowexp, colexp,    \
                            cscale, nchp);                                                                       \
         return hipGetLastError();                                                                               \
     }
+#define LC_MG2(T, MV, KSV, NSV, DV, KV, WV) LC_MG3(T, MV, KSV, NSV, DV, KV, WV, false)
 #define LC_MG1(T, MV, KSV, NSV, DV, KV) LC_MG2(T, MV, KSV, NSV, DV, KV, 2)
 #define LC_MG(T, MV, KSV, NSV)                                                                                  \
     LC_MG1(T, MV, KSV, NSV, false, 8) LC_MG1(T, MV, KSV, NSV, false, 16)                                        \
@@ -749,10 +750,14 @@ hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const voi
     if (h16 == kBF16) {
         LC_MG_ALL(__bf16)
         LC_MG2(__bf16, 3, 16, 4, false, 16, 4) LC_MG2(__bf16, 3, 16, 4, true, 8, 4)
+        LC_MG3(__bf16, 6, 16, 3, false, 8, 2, true) LC_MG3(__bf16, 3, 16, 4, false, 16, 4, true)
+        LC_MG3(__bf16, 3, 16, 4, false, 16, 2, true)
     } else {
         LC_MG_ALL(_Float16)
         LC_MG2(_Float16, 3, 16, 4, false, 16, 4) LC_MG2(_Float16, 3, 16, 4, true, 4, 4)
+        LC_MG3(_Float16, 3, 16, 4, false, 16, 4, true) LC_MG3(_Float16, 3, 16, 4, false, 16, 2, true)
     }
+#undef LC_MG3
 #undef LC_MG2
 #undef LC_MG_ALL
 #undef LC_MG

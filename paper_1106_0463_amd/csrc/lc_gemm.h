@@ -52,7 +52,8 @@ hipError_t launch_split_cols(int h16, const double *F, int P, int B, int Kp, int
 // column split (required there; unused with C64)
 hipError_t launch_mgemm(int h16, int mode, const void *X, int64_t xps, const void *Y, int64_t yps, int Bn, int Hn,
                         int Kp, float *Out, int ldo, double *C64, const int *rowexp, const int *colexp,
-                        const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s, int wr = 2);
+                        const unsigned char *cscale, int ks, int ns, int kch, hipStream_t s, int wr = 2,
+                        bool t64 = false);
 hipError_t launch_gdst(int phi_is_fp32, const void *Out, int ldo, const int *rowexp, const int *colexp, int B,
                        int64_t H, int64_t L, int64_t N, const double2 *tw_pre, const double2 *tw_pack,
                        const double2 *tw_fft, const FftSched &sch, double *C, hipStream_t s);

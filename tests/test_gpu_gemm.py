@@ -98,14 +98,14 @@ def test_gemm_split_modes(lc, mode, bound):
     assert E_a <= bound
 
 
-# the largest grids a GEMM plan takes.  Rounding grows with P: the Abel
-# form's FP32 totals and FP32 phi round once per fold and per value, and
-# bf16x6 leaves the mixed class at P = 16384 (E_a 1.16e-7) where fp16x3
-# stays in it (6.4e-8); the FP64 DGEMM form's K = 16384 sums, times up to
-# 2N - 1 in the rescale, reach E_c 1.05e-12 there, the FP64 class's edge.
-# Bounds: E_a for the split modes, E_c for FP64.
+# the largest grids a GEMM plan takes.  Rounding grows with P: above P =
+# 4096 the Abel form keeps FP64 second-level totals (with FP32 ones, whose
+# every fold rounds, bf16x6 read E_a 1.16e-7 at P = 16384 and fp16x3
+# 6.4e-8; with FP64 ones 8.4e-9 and 9.2e-9); the FP64 DGEMM form's K = 16384
+# sums, times up to 2N - 1 in the rescale, reach E_c 1.05e-12 there, the
+# FP64 class's edge.  Bounds: E_a for the split modes, E_c for FP64.
 LARGE_P = [("fp16x3", "abel", 8192, 1e-7), ("fp16x3", "abel", 16384, 1e-7), ("fp16x3", "direct", 16384, 1e-7),
-           ("bf16x6", "abel", 8192, 1e-7), ("bf16x6", "abel", 16384, 2e-7), ("fp64", "abel", 8192, 1e-12),
+           ("bf16x6", "abel", 8192, 1e-7), ("bf16x6", "abel", 16384, 1e-7), ("fp64", "abel", 8192, 1e-12),
            ("fp64", "abel", 16384, 2e-12)]
 
 
@@ -132,6 +132,26 @@ def test_gemm_largest_p(lc, mode, form, P, bound):
         assert E_a <= bound
         if form == "direct":
             assert E_c <= 1e-6
+
+
+@pytest.mark.parametrize("mode", ["fp16x3", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("rows", ["128", "256"])
+def test_abel_fp64_totals(lc, monkeypatch, mode, rows):
+    # the Abel product's FP64 second-level totals (the default above P =
+    # 4096) forced at a ragged small size (P not a multiple of 32, B past a
+    # block), both block heights, against the FP32 totals and the series
+    monkeypatch.setenv("LC_MGEMM_BLOCK_ROWS", rows)
+    banner(f"[gpu] gemm {mode} Abel form, FP64 totals, block rows {rows}")
+    monkeypatch.setenv("LC_MGEMM_T64", "0")
+    C32, coef = _run(lc, mode, 1000, 1600, 777, 300, 500, seed=9)
+    monkeypatch.setenv("LC_MGEMM_T64", "1")
+    C64, _ = _run(lc, mode, 1000, 1600, 777, 300, 500, seed=9)
+    E_c, E_a = _errors(C64, coef, 777)
+    n = np.arange(777)
+    d = rel_err(C64 / (2 * n + 1), C32 / (2 * n + 1))
+    banner(f"    E_c {E_c:.2e} E_a {E_a:.2e}, difference to FP32 totals {d:.2e}")
+    assert E_a <= BOUND[mode]
+    assert d <= BOUND[mode]
 
 
 def test_gemm_split_matches_fp64_path(lc):
