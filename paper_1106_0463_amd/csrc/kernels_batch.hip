@@ -503,13 +503,32 @@ __global__ __launch_bounds__(64) void k_bdst_multi(const double *__restrict__ ph
     }
     __syncthreads();
     fft_passes<T, 8, false>(lds, L, fpb, f0.sched, f0.tw_fft, 1);  // fpb >= 2
-    const int tot2 = fpb * (int)H;  // N <= H per slot
-    const float rH = 1.0f / (float)H;
+    // unpack in quads: n = 4j .. 4j+3 of a slot read only z[j] and
+    // z[H/2 - 1 - j] (H even), dst_post's values bit for bit, two 16-byte
+    // non-temporal stores where the quad is whole and aligned (N <= H per slot)
+    const int hq = (int)((H + 3) >> 2);
+    const int tot4 = fpb * hq;
+    const float rq = 1.0f / (float)hq;
+    const double r = 1.0 / (double)(2 * H);
 #pragma unroll 1
-    for (int e = threadIdx.x; e < tot2; e += T) {
-        int n;
-        const int sl = fdivmod(e, (int)H, rH, n);
-        if (n < sn[sl]) c_arena[scoff[sl] + n] = dst_post(n, lds + sl * L, H);
+    for (int e = threadIdx.x; e < tot4; e += T) {
+        int j;
+        const int sl = fdivmod(e, hq, rq, j);
+        const int nn = sn[sl], n0 = 4 * j;
+        if (n0 >= nn) continue;
+        const double2 *z = lds + sl * L;
+        const double2 a = z[j], b = z[(H >> 1) - 1 - j];
+        const double f = (double)(8 * j + 1);
+        const double v[4] = {f * a.x * r, -(f + 2.0) * b.y * r, (f + 4.0) * a.y * r, -(f + 6.0) * b.x * r};
+        double *c = c_arena + scoff[sl] + n0;
+        if (n0 + 3 < nn && ((uintptr_t)c & 15) == 0) {
+            __builtin_nontemporal_store(lc_f64x2{v[0], v[1]}, reinterpret_cast<lc_f64x2 *>(c));
+            __builtin_nontemporal_store(lc_f64x2{v[2], v[3]}, reinterpret_cast<lc_f64x2 *>(c) + 1);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (n0 + i < nn) __builtin_nontemporal_store(v[i], c + i);
+        }
     }
 }
 
