@@ -336,28 +336,60 @@ __device__ __forceinline__ double2 dst_pack(int64_t k, PhiAt phi, int64_t H, int
     return make_double2(sum.x - r.y, sum.y + r.x);
 }
 
-// Z_k of every k < L into lds[k], up to EPT values per thread (L <= EPT T),
-// four at a time: indices past L are clamped to L - 1 so that the four
-// values' loads are all issued before the first is used; only k < L is
-// stored.
+// Z_k from its four values of phi (k > 0): the arithmetic of dst_pack.
+__device__ __forceinline__ double2 dst_pack_from(double phi_Hk, double phi_k, double phi_Lk, double phi_Lpk,
+                                                 double2 t0, double2 t1, double2 tp) {
+    const double2 vk = cmul(t0, make_double2(phi_Hk, -phi_k));
+    const double2 vkl = cmul(t1, make_double2(phi_Lk, -phi_Lpk));
+    const double2 sum = cadd(vk, vkl);
+    const double2 r = cmul(tp, csub(vk, vkl));
+    return make_double2(sum.x - r.y, sum.y + r.x);
+}
+
+// Z_k of every k < L into lds[k] (L <= EPT T), dst_pack's values bit for
+// bit.  Z_g and Z_{L-g} read the same four values of phi (phi_g, phi_{H-g},
+// phi_{L-g}, phi_{L+g}), so one thread forms both from one set of loads:
+// pairs g = 1 .. ceil(L/2) - 1, two at a time with indices clamped so that
+// every load is issued before the first use (only valid pairs are stored);
+// thread T-1 adds Z_0 and, for even L, Z_{L/2}.
 template <int T, int EPT, typename PhiAt>
 __device__ __forceinline__ void dst_pack_lds(double2 *__restrict__ lds, PhiAt phi, int64_t H, int L,
                                              const double2 *__restrict__ tw_pre,
                                              const double2 *__restrict__ tw_pack) {
-    constexpr int U = EPT < 4 ? EPT : 4;
+    const int G = (L + 1) >> 1;  // pairs g in [1, G)
+    constexpr int NP = (EPT + 1) / 2;
+    constexpr int U = NP < 2 ? NP : 2;
+    if ((int)threadIdx.x == T - 1) {
+        lds[0] = dst_pack(0, phi, H, L, tw_pre, tw_pack);
+        if (!(L & 1) && L >= 2) lds[L >> 1] = dst_pack(L >> 1, phi, H, L, tw_pre, tw_pack);
+    }
 #pragma unroll
-    for (int i0 = 0; i0 < EPT; i0 += U) {
-        if (i0 * T >= L) break;
-        double2 z[U];
+    for (int i0 = 0; i0 < NP; i0 += U) {
+        if (1 + i0 * T >= G) break;
+        double a[U], b[U], c[U], d[U];
+        double2 t0[U], t1[U], tp[U], s0[U], s1[U], sp[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int k = (int)threadIdx.x + (i0 + u) * T;
-            z[u] = dst_pack(k < L ? k : L - 1, phi, H, L, tw_pre, tw_pack);
+            const int g0 = 1 + (int)threadIdx.x + (i0 + u) * T;
+            const int g = g0 < G ? g0 : G - 1;
+            a[u] = phi(g);
+            b[u] = phi(H - g);
+            c[u] = phi(L - g);
+            d[u] = phi(L + g);
+            t0[u] = tw_pre[g];
+            t1[u] = tw_pre[g + L];
+            tp[u] = tw_pack[g];
+            s0[u] = tw_pre[L - g];
+            s1[u] = tw_pre[2 * L - g];
+            sp[u] = tw_pack[L - g];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int k = (int)threadIdx.x + (i0 + u) * T;
-            if (k < L) lds[k] = z[u];
+            const int g = 1 + (int)threadIdx.x + (i0 + u) * T;
+            if (g < G) {
+                lds[g] = dst_pack_from(b[u], a[u], c[u], d[u], t0[u], t1[u], tp[u]);
+                lds[L - g] = dst_pack_from(d[u], c[u], a[u], b[u], s0[u], s1[u], sp[u]);
+            }
         }
     }
 }
