@@ -348,7 +348,10 @@ __device__ __forceinline__ double2 dst_pack_from(double phi_Hk, double phi_k, do
 
 // Z_k of every k < L into lds[k] (L <= EPT T), dst_pack's values bit for
 // bit.  Z_g and Z_{L-g} read the same four values of phi (phi_g, phi_{H-g},
-// phi_{L-g}, phi_{L+g}), so one thread forms both from one set of loads:
+// phi_{L-g}, phi_{L+g}), so one thread forms both from one set of loads,
+// and three of their six twiddles from the other three (the tables hold
+// tw_pre[2L-g] = swap(tw_pre[g]), tw_pre[L+g] = swap(tw_pre[L-g]) and
+// tw_pack[L-g] = (-tw_pack[g].x, tw_pack[g].y) exactly, by construction):
 // pairs g = 1 .. ceil(L/2) - 1, two at a time with indices clamped so that
 // every load is issued before the first use (only valid pairs are stored);
 // thread T-1 adds Z_0 and, for even L, Z_{L/2}.
@@ -377,11 +380,14 @@ __device__ __forceinline__ void dst_pack_lds(double2 *__restrict__ lds, PhiAt ph
             c[u] = phi(L - g);
             d[u] = phi(L + g);
             t0[u] = tw_pre[g];
-            t1[u] = tw_pre[g + L];
-            tp[u] = tw_pack[g];
             s0[u] = tw_pre[L - g];
-            s1[u] = tw_pre[2 * L - g];
-            sp[u] = tw_pack[L - g];
+            tp[u] = tw_pack[g];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            t1[u] = make_double2(s0[u].y, s0[u].x);     // tw_pre[L + g]
+            s1[u] = make_double2(t0[u].y, t0[u].x);     // tw_pre[2L - g]
+            sp[u] = make_double2(-tp[u].x, tp[u].y);    // tw_pack[L - g]
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {

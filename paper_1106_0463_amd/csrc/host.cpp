@@ -232,6 +232,13 @@ static void sincos_turns(int64_t num, int64_t den, double *c, double *s) {
     *s = (double)rs;
 }
 
+// The DST pack derives three of a mirror pair's six twiddles from the other
+// three; the quadrant/octant reduction of sincos_turns already makes these
+// entries exact images of their partners, and they are set from them so
+// that this holds by construction (1 <= g < L/2, H = 2L):
+//   pre[2L - g] = (pre[g].y, pre[g].x)          (angle pi/2 - theta)
+//   pre[L + g]  = (pre[L - g].y, pre[L - g].x)  (reflection about pi/4)
+//   pack[L - g] = (-pack[g].x, pack[g].y)        (angle pi - theta)
 void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack, std::vector<double2> &fft) {
     const int64_t L = H / 2;
     pre.resize(H);
@@ -240,6 +247,11 @@ void twiddles(int64_t H, std::vector<double2> &pre, std::vector<double2> &pack, 
     for (int64_t k = 0; k < H; ++k) sincos_turns(k, 4 * H, &pre[k].x, &pre[k].y);
     for (int64_t k = 0; k < L; ++k) sincos_turns(k, H, &pack[k].x, &pack[k].y);
     for (int64_t k = 0; k < L; ++k) sincos_turns(k, L, &fft[k].x, &fft[k].y);
+    for (int64_t g = 1; 2 * g < L; ++g) {
+        pre[2 * L - g] = make_double2(pre[g].y, pre[g].x);
+        pre[L + g] = make_double2(pre[L - g].y, pre[L - g].x);
+        pack[L - g] = make_double2(-pack[g].x, pack[g].y);
+    }
 }
 
 // Row factors of the node formula: A_j = 2 sin^2(pi j / (2H)) as a
