@@ -482,24 +482,52 @@ __global__ __launch_bounds__(64) void k_bdst_multi(const double *__restrict__ ph
         sn[threadIdx.x] = fi < 0 ? 0 : (int)f.N;
     }
     __syncthreads();
-    const int tot = fpb * L;
-    const float rL = 1.0f / (float)L;
     struct Phi {
         const double *p;
         __device__ __forceinline__ double operator()(int64_t m) const { return p[m - 1]; }
     };
+    // Z_0 (and Z_{L/2} for even L) of slot threadIdx.x, then the mirror pairs
+    // (Z_g, Z_{L-g}), g = 1 .. ceil(L/2) - 1, of every slot, each from one set
+    // of four phi loads and three twiddle loads (the other three are exact
+    // images in the tables), dst_pack's values bit for bit
+    if ((int)threadIdx.x < fpb) {
+        const Phi ph{phi_arena + sphi[threadIdx.x]};
+        double2 *z = lds + threadIdx.x * L;
+        z[0] = dst_pack(0, ph, H, L, f0.tw_pre, f0.tw_pack);
+        if (!(L & 1) && L >= 2) z[L >> 1] = dst_pack(L >> 1, ph, H, L, f0.tw_pre, f0.tw_pack);
+    }
+    const int gp = ((L + 1) >> 1) - 1;  // pairs per slot
+    const int tot = fpb * gp;
+    const float rg = 1.0f / (float)(gp > 0 ? gp : 1);
 #pragma unroll 1
-    for (int e0 = 0; e0 < tot; e0 += 4 * T) {  // four values' reads in flight per thread
-        double2 z[4];
+    for (int e0 = 0; e0 < tot; e0 += 2 * T) {  // two pairs' reads in flight per thread
+        double a[2], b[2], c[2], d[2];
+        double2 t0[2], s0[2], tp[2];
+        int slot[2], gg[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int k;
-            const int sl = fdivmod(min(e0 + (int)threadIdx.x + u * T, tot - 1), L, rL, k);
-            z[u] = dst_pack(k, Phi{phi_arena + sphi[sl]}, H, L, f0.tw_pre, f0.tw_pack);
+        for (int u = 0; u < 2; ++u) {
+            int g;
+            slot[u] = fdivmod(min(e0 + (int)threadIdx.x + u * T, tot - 1), gp, rg, g);
+            g += 1;
+            gg[u] = g;
+            const Phi ph{phi_arena + sphi[slot[u]]};
+            a[u] = ph(g);
+            b[u] = ph(H - g);
+            c[u] = ph(L - g);
+            d[u] = ph(L + g);
+            t0[u] = f0.tw_pre[g];
+            s0[u] = f0.tw_pre[L - g];
+            tp[u] = f0.tw_pack[g];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (e0 + (int)threadIdx.x + u * T < tot) lds[e0 + threadIdx.x + u * T] = z[u];
+        for (int u = 0; u < 2; ++u)
+            if (e0 + (int)threadIdx.x + u * T < tot) {
+                double2 *z = lds + slot[u] * L;
+                const double2 t1 = make_double2(s0[u].y, s0[u].x), s1 = make_double2(t0[u].y, t0[u].x);
+                const double2 sp = make_double2(-tp[u].x, tp[u].y);
+                z[gg[u]] = dst_pack_from(b[u], a[u], c[u], d[u], t0[u], t1, tp[u]);
+                z[L - gg[u]] = dst_pack_from(d[u], c[u], a[u], b[u], s0[u], s1, sp);
+            }
     }
     __syncthreads();
     fft_passes<T, 8, false>(lds, L, fpb, f0.sched, f0.tw_fft, 1);  // fpb >= 2
