@@ -51,7 +51,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from the 4 GiB copy calibration),
 # with the kernel they were taken on
 TRAFFIC = {"single_large_band": (4.9517e9, "k_aflat<double>"),
-           "batch_fp64": (7.6855e9, "k_bquad_fit<double, 2, 8, 3, 2>")}
+           "batch_fp64": (7.6855e9, "k_bquad_fit<double, 2, 8, 3, 2>"),
+           "batch_fp32": (3.9560e9, "k_bquad_pair<float, 4, 8, 3, 2>")}
 METRIC = "Legendre coeffs/sec at 1 GPU (FP64 ≤1e-12 vs split-BF16 ≤1e-7 rel.)"
 Q_RESOLVING = 8384
 FP64_CLASS = 1e-12   # E_c = max|dc| / max|c|
@@ -381,8 +382,8 @@ def run_batch(args, prec=None, cpu_budget=20.0):
     if not args.no_cpu_baseline and cpu_budget > 0:
         cpu = cpu_baseline_series(sb, np.random.default_rng(3).choice(4096, 64, replace=False), cpu_budget)
     line, c = _batch_common(args, bp, arena, int(sb.N.sum()), alg, cfg, cpu)
-    if prec == "fp64" and "batch_fp64" in TRAFFIC:
-        line["roofline"]["traffic"], line["roofline"]["traffic_kernel"] = TRAFFIC["batch_fp64"]
+    if f"batch_{prec}" in TRAFFIC:
+        line["roofline"]["traffic"], line["roofline"]["traffic_kernel"] = TRAFFIC[f"batch_{prec}"]
     bp.destroy()
     del arena
     _free()
