@@ -802,7 +802,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
-              "(functions shard trivially across GPUs; see the design notes)", file=sys.stderr)
+              "(functions are independent, so a batch shards across GPUs by giving each GPU's "
+              "process its own plans over its share of the functions)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
